@@ -1,0 +1,218 @@
+/*
+ * qtx_rgf.h - batched recursive Green's function (RGF) selected inversion of
+ * block-tridiagonal complex systems on AMD Instinct MI355X (gfx950).
+ *
+ * The library solves, independently at every energy E, the system of the
+ * NEGF+GW paper (arXiv 2508.19138, Eq. system-solve):
+ *
+ *     Mt(E) X^R(E) = I,        Mt(E) X^s(E) Mt(E)^dagger = B^s(E),  s in {<,>}
+ *
+ * and returns the "selected" blocks of the solution: the diagonal and first
+ * off-diagonal blocks of X^R, X^< and X^> (Sec. 3.2, Selected System Solver).
+ * The system matrices are those of Table "quantities" / Sec. 3.2.2:
+ *
+ *   G-type (electrons):        Mt = E S - H - Sigma^R(E),   B^s = Sigma^s(E)
+ *   W-type (screened Coulomb): Mt = I - V P^R(E),           B^s = V P^s(E) V^dagger
+ *
+ * For W the products are formed in block-tridiagonal (BT) form and cut back
+ * to the BT pattern (blocks with |i-j| > 1 dropped).  The solve is the RGF
+ * forward/backward recursion of Sec. 3.2.3 (Eqs. forward-pass, backward-pass).
+ *
+ * Data layout (all operands): complex128 blocks, interleaved (re, im), each
+ * block row-major b x b and contiguous.  A block-tridiagonal operand is three
+ * arrays: diag [n][b][b], upper [n-1][b][b] (block (i,i+1)) and
+ * lower [n-1][b][b] (block (i+1,i)).  Energy-dependent operands carry a
+ * leading energy axis: diag [N_E][n][b][b], upper/lower [N_E][n-1][b][b].
+ * Energy-independent operands (H, S, V) have no energy axis.
+ *
+ * Pointers: every array pointer is a HIP device pointer to memory the caller
+ * owns (for example a PyTorch complex128 tensor's data_ptr()).  The library
+ * never frees, reallocates or retains caller memory beyond the call.  The
+ * energies array is a host pointer.
+ *
+ * Symmetry contract: the paper's lesser/greater quantities are
+ * anti-Hermitian, B^s_ij = -conj(B^s_ji).  The library relies on it: for
+ * Sigma^s and P^s it reads the diagonal and upper blocks only (the lower
+ * block is taken as -upper^dagger; a lower pointer given there is ignored),
+ * and it writes the lower blocks of X^s as -upper^dagger.
+ *
+ * Errors: every entry point returns a qtx_status.  Call-level errors
+ * (bad arguments, HIP failures, out of memory) are returned directly and no
+ * problem is solved.  Numerical failures are per problem: the call returns
+ * QTX_ERR_PROBLEM and each problem's `status` field says what happened
+ * (QTX_ERR_SINGULAR: an exactly zero pivot; QTX_ERR_NOT_FINITE: a NaN or
+ * Inf pivot), with the first failing energy and block index; the other
+ * problems of the batch are unaffected.  Outputs of a failing energy are
+ * unspecified.  No C++ exception crosses this interface.
+ *
+ * Threading: a context may be used by one host thread at a time.
+ */
+#ifndef QTX_RGF_H
+#define QTX_RGF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qtx_rgf_ctx qtx_rgf_ctx;
+
+typedef enum {
+  QTX_OK = 0,
+  QTX_ERR_INVALID_ARG = 1, /* null/negative/inconsistent argument          */
+  QTX_ERR_SINGULAR = 2,    /* exactly zero pivot in a diagonal-block inverse */
+  QTX_ERR_NOT_FINITE = 3,  /* NaN or Inf met as a pivot                      */
+  QTX_ERR_NOMEM = 4,       /* one energy of one problem exceeds the budget   */
+  QTX_ERR_HIP = 5,         /* a HIP runtime call failed                      */
+  QTX_ERR_BUSY = 6,        /* context in use                                 */
+  QTX_ERR_PROBLEM = 7      /* call done; at least one problem status != OK  */
+} qtx_status;
+
+typedef enum { QTX_KIND_G = 0, QTX_KIND_W = 1 } qtx_kind;
+
+/* QTX_FP64: every product and inverse in complex128.
+ * QTX_MIXED: the Schur-update products and all lesser/greater triple
+ * products in complex64 on the FP32 matrix cores (FP32 accumulate); the
+ * diagonal-block inverses and the left-connected x^R_i stay complex128. */
+typedef enum { QTX_FP64 = 0, QTX_MIXED = 1 } qtx_precision;
+
+/* One block-tridiagonal input operand (device pointers, see layout above). */
+typedef struct {
+  const void* diag;
+  const void* upper;
+  const void* lower;
+} qtx_bt_in;
+
+/* One block-tridiagonal output: [N_E][n][b][b] and [N_E][n-1][b][b]. */
+typedef struct {
+  void* diag;
+  void* upper;
+  void* lower;
+} qtx_bt_out;
+
+typedef struct {
+  int32_t kind;        /* qtx_kind                                           */
+  int32_t precision;   /* qtx_precision                                      */
+  int32_t n_blocks;    /* n >= 1                                             */
+  int32_t block_size;  /* b >= 1                                             */
+  int32_t n_energies;  /* N_E >= 1                                           */
+  int32_t flags;       /* reserved, must be 0                                */
+  const double* energies; /* host, [N_E] real energies (G-type; W ignores)   */
+
+  /* G-type inputs.  H: energy independent, Hermitian; H.lower NULL means
+   * lower = upper^dagger.  S: energy independent overlap; S.diag NULL means
+   * S = I (then S.upper/S.lower must be NULL); S.upper/lower NULL = zero.
+   * sigma_r: retarded self-energy (scattering + OBC), per energy; upper and
+   * lower NULL = zero blocks.  sigma_l / sigma_g: Sigma^< / Sigma^>, per
+   * energy, anti-Hermitian; upper NULL = block-diagonal. */
+  qtx_bt_in H, S, sigma_r, sigma_l, sigma_g;
+
+  /* W-type inputs.  V: energy independent, Hermitian (lower NULL =
+   * upper^dagger).  P_r: retarded polarization per energy (upper/lower NULL
+   * = zero).  P_l / P_g: P^< / P^> per energy, anti-Hermitian (upper NULL =
+   * block-diagonal). */
+  qtx_bt_in V, P_r, P_l, P_g;
+
+  /* Outputs (device).  XR is required.  XL / XG: diag NULL skips that
+   * right-hand side altogether; upper/lower may be NULL to skip those
+   * blocks.  For W-type the X^s are W^< and W^>. */
+  qtx_bt_out XR, XL, XG;
+  /* W-type only, optional: diagonal blocks of W^R = X^R V, [N_E][n][b][b]. */
+  void* WR_diag;
+
+  /* Written by the library. */
+  int32_t status;       /* qtx_status of this problem                        */
+  int32_t fail_energy;  /* first failing energy index, or -1                 */
+  int32_t fail_block;   /* block index of that failure, or -1                */
+  int32_t reserved;
+} qtx_rgf_problem;
+
+/* Create a context on HIP device `device`.  Workspace is allocated lazily
+ * and kept below `hbm_budget_bytes` (0 = 90% of the free device memory at
+ * creation); a batch larger than the budget is processed in energy chunks.
+ * `hip_stream` is a hipStream_t to launch on (NULL = a stream owned by the
+ * context).  `flags` bit 0 (QTX_FLAG_PROFILE) records per-kernel-class
+ * launch timings (see qtx_rgf_kernel_stats). */
+#define QTX_FLAG_PROFILE 1u
+qtx_status qtx_rgf_create(qtx_rgf_ctx** out, int device,
+                          uint64_t hbm_budget_bytes, void* hip_stream,
+                          uint32_t flags);
+
+/* Solve `n_problems` independent problems (each with its own n, b, N_E,
+ * kind and precision).  Synchronous: returns when every output is written
+ * (the context's stream is synchronised).  Inputs must not alias outputs. */
+qtx_status qtx_rgf_solve_batch(qtx_rgf_ctx* ctx, qtx_rgf_problem* problems,
+                               int32_t n_problems);
+
+/* Release the context's workspace, streams and events.  Caller memory is
+ * untouched.  Waits for work in flight on the context's stream. */
+qtx_status qtx_rgf_destroy(qtx_rgf_ctx* ctx);
+
+/* Static string for a status code. */
+const char* qtx_rgf_status_string(qtx_status s);
+
+/* Human-readable detail of the last call-level error on this context
+ * (empty string if none).  Valid until the next call on the context. */
+const char* qtx_rgf_last_error(const qtx_rgf_ctx* ctx);
+
+/* Algorithmic flops of one problem at one energy (8 b^3 per complex block
+ * product; an inverse priced as one product), as used for TFLOP/s.
+ * `bt_rhs` != 0 when Sigma^s / P^s have off-diagonal blocks. */
+double qtx_rgf_flops_per_energy(int32_t kind, int32_t n_blocks,
+                                int32_t block_size, int32_t n_rhs,
+                                int32_t bt_rhs, int32_t want_wr);
+
+/* Per-kernel-class launch statistics recorded under QTX_FLAG_PROFILE since
+ * the last reset: number of launches, summed device time (ms, HIP events on
+ * the launch stream), summed algorithmic flops and algorithmic HBM bytes.
+ * Classes: 0 = complex GEMM (FP64), 1 = complex GEMM (FP32), 2 = inverse
+ * panel, 3 = elementwise/assembly.  Returns QTX_ERR_INVALID_ARG for an
+ * unknown class. */
+qtx_status qtx_rgf_kernel_stats(qtx_rgf_ctx* ctx, int32_t kernel_class,
+                                int64_t* launches, double* total_ms,
+                                double* flops, double* bytes);
+qtx_status qtx_rgf_reset_stats(qtx_rgf_ctx* ctx);
+
+/* ---- building blocks, exposed for testing the kernels one at a time ---- */
+
+/* Strided-batched complex128 product on the FP64 matrix cores:
+ *   D[e] = alpha * op(A[e]) * op(B[e]) + beta * C[e],  e = 0..batch-1
+ * op(X) = X (op = 'N') or X^dagger (op = 'C').  All matrices row-major with
+ * leading dimensions lda..ldd (in complex elements); element strides between
+ * consecutive batch entries sA..sD (0 = shared operand).  op(A) is m x k,
+ * op(B) is k x n, C and D are m x n.  C may equal D (in place); C may be
+ * NULL when beta == 0.  Device pointers; runs on the context's stream and
+ * returns after it completes. */
+qtx_status qtx_rgf_zgemm(qtx_rgf_ctx* ctx, char opa, char opb, int32_t m,
+                         int32_t n, int32_t k, double alpha_re,
+                         double alpha_im, const void* A, int64_t lda,
+                         int64_t sA, const void* B, int64_t ldb, int64_t sB,
+                         double beta_re, double beta_im, const void* C,
+                         int64_t ldc, int64_t sC, void* D, int64_t ldd,
+                         int64_t sD, int32_t batch);
+
+/* Same product with complex64 operands on the FP32 matrix cores
+ * (FP32 accumulate), used by QTX_MIXED. */
+qtx_status qtx_rgf_cgemm(qtx_rgf_ctx* ctx, char opa, char opb, int32_t m,
+                         int32_t n, int32_t k, float alpha_re, float alpha_im,
+                         const void* A, int64_t lda, int64_t sA,
+                         const void* B, int64_t ldb, int64_t sB,
+                         float beta_re, float beta_im, const void* C,
+                         int64_t ldc, int64_t sC, void* D, int64_t ldd,
+                         int64_t sD, int32_t batch);
+
+/* Batched inverse of b x b complex128 matrices by Gauss-Jordan elimination
+ * with partial pivoting (largest |z| in the pivot column; ties to the lowest
+ * row).  A [batch][b][b] is overwritten (used as workspace); the inverses
+ * are written to X [batch][b][b].  info[batch] (device int32, may be NULL)
+ * receives 0, or 1 + the column of the first exactly zero pivot, or
+ * -(1 + column) for a non-finite pivot. */
+qtx_status qtx_rgf_zinv(qtx_rgf_ctx* ctx, int32_t b, void* A, void* X,
+                        int32_t* info, int32_t batch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QTX_RGF_H */

@@ -1,0 +1,269 @@
+"""Thin ctypes binding of the C ABI in include/qtx_rgf.h.
+
+Argument marshalling only: every step of the solve runs in the HIP library
+libqtx_rgf.so.  Device memory is handled by the caller (PyTorch complex128
+tensors on the GPU); this module passes their data pointers.  Loading fails
+loudly if the library has not been built.
+"""
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqtx_rgf.so")
+
+QTX_OK = 0
+QTX_ERR_INVALID_ARG = 1
+QTX_ERR_SINGULAR = 2
+QTX_ERR_NOT_FINITE = 3
+QTX_ERR_NOMEM = 4
+QTX_ERR_HIP = 5
+QTX_ERR_BUSY = 6
+QTX_ERR_PROBLEM = 7
+
+QTX_KIND_G = 0
+QTX_KIND_W = 1
+QTX_FP64 = 0
+QTX_MIXED = 1
+QTX_FLAG_PROFILE = 1
+
+KERNEL_CLASSES = {"zgemm": 0, "cgemm": 1, "inverse": 2, "elementwise": 3}
+
+
+class BtIn(ctypes.Structure):
+    _fields_ = [("diag", ctypes.c_void_p), ("upper", ctypes.c_void_p),
+                ("lower", ctypes.c_void_p)]
+
+
+class BtOut(ctypes.Structure):
+    _fields_ = [("diag", ctypes.c_void_p), ("upper", ctypes.c_void_p),
+                ("lower", ctypes.c_void_p)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("n_blocks", ctypes.c_int32), ("block_size", ctypes.c_int32),
+        ("n_energies", ctypes.c_int32), ("flags", ctypes.c_int32),
+        ("energies", ctypes.POINTER(ctypes.c_double)),
+        ("H", BtIn), ("S", BtIn), ("sigma_r", BtIn), ("sigma_l", BtIn),
+        ("sigma_g", BtIn),
+        ("V", BtIn), ("P_r", BtIn), ("P_l", BtIn), ("P_g", BtIn),
+        ("XR", BtOut), ("XL", BtOut), ("XG", BtOut),
+        ("WR_diag", ctypes.c_void_p),
+        ("status", ctypes.c_int32), ("fail_energy", ctypes.c_int32),
+        ("fail_block", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+class QtxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+def lib():
+    """Load libqtx_rgf.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libqtx_rgf.so is not built (%s); run "
+                          "python -m paper_2508_19138_amd.build" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    c_ctx = ctypes.c_void_p
+    L.qtx_rgf_create.argtypes = [ctypes.POINTER(c_ctx), ctypes.c_int,
+                                 ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint32]
+    L.qtx_rgf_create.restype = ctypes.c_int
+    L.qtx_rgf_solve_batch.argtypes = [c_ctx, ctypes.POINTER(Problem), ctypes.c_int32]
+    L.qtx_rgf_solve_batch.restype = ctypes.c_int
+    L.qtx_rgf_destroy.argtypes = [c_ctx]
+    L.qtx_rgf_destroy.restype = ctypes.c_int
+    L.qtx_rgf_status_string.argtypes = [ctypes.c_int]
+    L.qtx_rgf_status_string.restype = ctypes.c_char_p
+    L.qtx_rgf_last_error.argtypes = [c_ctx]
+    L.qtx_rgf_last_error.restype = ctypes.c_char_p
+    L.qtx_rgf_flops_per_energy.argtypes = [ctypes.c_int32] * 6
+    L.qtx_rgf_flops_per_energy.restype = ctypes.c_double
+    L.qtx_rgf_kernel_stats.argtypes = [c_ctx, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]
+    L.qtx_rgf_kernel_stats.restype = ctypes.c_int
+    L.qtx_rgf_reset_stats.argtypes = [c_ctx]
+    L.qtx_rgf_reset_stats.restype = ctypes.c_int
+    gemm_args = [c_ctx, ctypes.c_char, ctypes.c_char, ctypes.c_int32,
+                 ctypes.c_int32, ctypes.c_int32]
+    ptr_ld_s = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]
+    L.qtx_rgf_zgemm.argtypes = (gemm_args + [ctypes.c_double, ctypes.c_double]
+                                + ptr_ld_s + ptr_ld_s
+                                + [ctypes.c_double, ctypes.c_double]
+                                + ptr_ld_s + ptr_ld_s + [ctypes.c_int32])
+    L.qtx_rgf_zgemm.restype = ctypes.c_int
+    L.qtx_rgf_cgemm.argtypes = (gemm_args + [ctypes.c_float, ctypes.c_float]
+                                + ptr_ld_s + ptr_ld_s
+                                + [ctypes.c_float, ctypes.c_float]
+                                + ptr_ld_s + ptr_ld_s + [ctypes.c_int32])
+    L.qtx_rgf_cgemm.restype = ctypes.c_int
+    L.qtx_rgf_zinv.argtypes = [c_ctx, ctypes.c_int32, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+    L.qtx_rgf_zinv.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    return ["qtx_rgf_create", "qtx_rgf_solve_batch", "qtx_rgf_destroy",
+            "qtx_rgf_status_string", "qtx_rgf_last_error",
+            "qtx_rgf_flops_per_energy", "qtx_rgf_kernel_stats",
+            "qtx_rgf_reset_stats", "qtx_rgf_zgemm", "qtx_rgf_cgemm",
+            "qtx_rgf_zinv"]
+
+
+def status_string(st):
+    return lib().qtx_rgf_status_string(st).decode()
+
+
+def flops_per_energy(kind, n, b, n_rhs=2, bt_rhs=False, want_wr=False):
+    return lib().qtx_rgf_flops_per_energy(kind, n, b, n_rhs, int(bt_rhs), int(want_wr))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _bt_in(d=None, u=None, l=None):
+    return BtIn(_ptr(d), _ptr(u), _ptr(l))
+
+
+def _bt_out(d=None, u=None, l=None):
+    return BtOut(_ptr(d), _ptr(u), _ptr(l))
+
+
+class Context:
+    """qtx_rgf_create / qtx_rgf_destroy around one device."""
+
+    def __init__(self, device=0, budget_bytes=0, stream=None, profile=False):
+        L = lib()
+        self._h = ctypes.c_void_p()
+        flags = QTX_FLAG_PROFILE if profile else 0
+        st = L.qtx_rgf_create(ctypes.byref(self._h), device, budget_bytes,
+                              stream, flags)
+        if st != QTX_OK:
+            raise QtxError(st, "qtx_rgf_create: " + status_string(st))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().qtx_rgf_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def last_error(self):
+        return lib().qtx_rgf_last_error(self._h).decode()
+
+    def _check(self, st, what):
+        if st not in (QTX_OK, QTX_ERR_PROBLEM):
+            raise QtxError(st, "%s: %s (%s)" % (what, status_string(st), self.last_error()))
+        return st
+
+    def solve_batch(self, problems):
+        """problems: list of Problem structures (see make_g_problem etc.).
+        Returns the call status; per-problem status is in each structure."""
+        arr = (Problem * len(problems))(*problems)
+        st = lib().qtx_rgf_solve_batch(self._h, arr, len(problems))
+        for i, p in enumerate(problems):
+            p.status = arr[i].status
+            p.fail_energy = arr[i].fail_energy
+            p.fail_block = arr[i].fail_block
+        return self._check(st, "qtx_rgf_solve_batch")
+
+    def kernel_stats(self, cls):
+        n = ctypes.c_int64()
+        ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        st = lib().qtx_rgf_kernel_stats(self._h, KERNEL_CLASSES.get(cls, cls),
+                                        ctypes.byref(n), ctypes.byref(ms),
+                                        ctypes.byref(fl), ctypes.byref(by))
+        self._check(st, "qtx_rgf_kernel_stats")
+        return {"launches": n.value, "ms": ms.value, "flops": fl.value,
+                "bytes": by.value}
+
+    def reset_stats(self):
+        lib().qtx_rgf_reset_stats(self._h)
+
+    def zgemm(self, opa, opb, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta,
+              C, ldc, sC, D, ldd, sD, batch):
+        st = lib().qtx_rgf_zgemm(self._h, opa.encode(), opb.encode(), m, n, k,
+                                 alpha.real, alpha.imag, _ptr(A), lda, sA,
+                                 _ptr(B), ldb, sB, beta.real, beta.imag,
+                                 _ptr(C), ldc, sC, _ptr(D), ldd, sD, batch)
+        return self._check(st, "qtx_rgf_zgemm")
+
+    def zinv(self, b, A, X, info, batch):
+        st = lib().qtx_rgf_zinv(self._h, b, _ptr(A), _ptr(X), _ptr(info), batch)
+        return self._check(st, "qtx_rgf_zinv")
+
+
+def make_g_problem(energies_host, H, sigma_r, sigma_l, sigma_g, XR, XL=None,
+                   XG=None, S=None, precision=QTX_FP64):
+    """Problem structure for a G-type solve.
+
+    energies_host: ctypes-compatible float64 numpy array (kept alive by the
+    caller).  H, S: (diag, upper, lower) device tensors (upper/lower may be
+    None).  sigma_*: (diag, upper, lower) per-energy device tensors.  XR, XL,
+    XG: (diag, upper, lower) output tensors (XL/XG may be None).
+    """
+    n_e, n, b = sigma_r[0].shape[0], sigma_r[0].shape[1], sigma_r[0].shape[2]
+    p = Problem()
+    p.kind = QTX_KIND_G
+    p.precision = precision
+    p.n_blocks, p.block_size, p.n_energies = n, b, n_e
+    p.energies = energies_host.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.H = _bt_in(*H)
+    if S is not None:
+        p.S = _bt_in(*S)
+    p.sigma_r = _bt_in(*sigma_r)
+    p.sigma_l = _bt_in(*(sigma_l or (None, None, None)))
+    p.sigma_g = _bt_in(*(sigma_g or (None, None, None)))
+    p.XR = _bt_out(*XR)
+    p.XL = _bt_out(*(XL or (None, None, None)))
+    p.XG = _bt_out(*(XG or (None, None, None)))
+    p.status = -1
+    return p
+
+
+def make_w_problem(V, P_r, P_l, P_g, XR, XL=None, XG=None, WR_diag=None,
+                   precision=QTX_FP64):
+    n_e, n, b = P_r[0].shape[0], P_r[0].shape[1], P_r[0].shape[2]
+    p = Problem()
+    p.kind = QTX_KIND_W
+    p.precision = precision
+    p.n_blocks, p.block_size, p.n_energies = n, b, n_e
+    p.V = _bt_in(*V)
+    p.P_r = _bt_in(*P_r)
+    p.P_l = _bt_in(*(P_l or (None, None, None)))
+    p.P_g = _bt_in(*(P_g or (None, None, None)))
+    p.XR = _bt_out(*XR)
+    p.XL = _bt_out(*(XL or (None, None, None)))
+    p.XG = _bt_out(*(XG or (None, None, None)))
+    p.WR_diag = _ptr(WR_diag)
+    p.status = -1
+    return p

@@ -1,0 +1,81 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+the header declares, the ctypes structure matches the C layout, and the
+library's flop model agrees with the oracle's.  No GPU compute is called."""
+
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2508_19138_amd import qtx_rgf as Q
+from oracle.flops import rgf_flops, w_assembly_flops
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qtx_rgf.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qtx_rgf_\w+)\s*\(", src)))
+
+
+def test_header_declares_core_entry_points():
+    names = _declared()
+    for n in ("qtx_rgf_create", "qtx_rgf_solve_batch", "qtx_rgf_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = Q.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert sorted(Q.exported_symbols()) == _declared()
+
+
+def test_problem_struct_layout_matches_c(tmp_path):
+    """Compile a tiny C program against the header (gcc, host only) and
+    compare sizeof/offsetof with the ctypes mirror."""
+    fields = [f[0] for f in Q.Problem._fields_]
+    prog = ["#include <stdio.h>", "#include <stddef.h>", '#include "qtx_rgf.h"',
+            "int main(void){", 'printf("%zu\\n", sizeof(qtx_rgf_problem));']
+    for f in fields:
+        prog.append('printf("%%zu\\n", offsetof(qtx_rgf_problem, %s));' % f)
+    prog.append("return 0;}")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(prog))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert int(out[0]) == ctypes.sizeof(Q.Problem)
+    for f, off in zip(fields, out[1:]):
+        assert int(off) == getattr(Q.Problem, f).offset, f
+
+
+@pytest.mark.parametrize("n,b", [(1, 8), (2, 32), (8, 32), (32, 512), (17, 100)])
+def test_flop_model_matches_oracle(n, b):
+    for bt in (False, True):
+        assert Q.flops_per_energy(Q.QTX_KIND_G, n, b, 2, bt) == rgf_flops(n, b, 2, bt)
+        assert Q.flops_per_energy(Q.QTX_KIND_G, n, b, 1, bt) == rgf_flops(n, b, 1, bt)
+    w = Q.flops_per_energy(Q.QTX_KIND_W, n, b, 2, True, True)
+    assert w == rgf_flops(n, b, 2, True) + w_assembly_flops(n, b, 2, True)
+
+
+def test_status_strings():
+    for st in range(8):
+        assert Q.status_string(st)
+
+
+def test_create_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    h = ctypes.c_void_p()
+    st = Q.lib().qtx_rgf_create(ctypes.byref(h), 0, 0, None, 0)
+    assert st != Q.QTX_OK and not h.value
+    st = Q.lib().qtx_rgf_create(ctypes.byref(h), -1, 0, None, 0)
+    assert st == Q.QTX_ERR_INVALID_ARG

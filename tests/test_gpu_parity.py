@@ -1,0 +1,319 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: FP64 outputs match the oracle to a relative Frobenius error of 1e-10
+per block (blocks far below the output's largest block norm are measured
+against that norm instead).  Kernel building blocks are checked against
+NumPy's matmul / inverse on the same inputs.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import rgf_selected, assemble_g, assemble_w, w_retarded_diag  # noqa: E402
+from paper_2508_19138_amd import synth  # noqa: E402
+from paper_2508_19138_amd import qtx_rgf as Q  # noqa: E402
+from blockcmp import triple_err, max_rel_err, block_rel_err  # noqa: E402
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    c = Q.Context(0)
+    yield c
+    c.close()
+
+
+def _gh():
+    import gpu_helpers
+    return gpu_helpers
+
+
+def _oracle_g(p, e, bt=None):
+    E = p["energies"][e]
+    sr = tuple(None if t is None else t[e] for t in p["sigma_r"])
+    A = assemble_g(E, p["H"], sr)
+    adj = lambda T: np.conj(np.swapaxes(T, -1, -2))
+    Bs = []
+    for key in ("sigma_l", "sigma_g"):
+        d, u, _ = (t[e] for t in p[key])
+        Bs.append((d, u, -adj(u)))       # anti-Hermitian lower
+    return rgf_selected(A, Bs)
+
+
+def _sel(T, e):
+    return tuple(t[e] for t in T)
+
+
+# ------------------------------------------------------------- building blocks
+
+@pytest.mark.parametrize("opa,opb", [("N", "N"), ("N", "C"), ("C", "N"), ("C", "C")])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (17, 33, 5), (64, 64, 64), (100, 70, 130), (130, 257, 96)])
+def test_zgemm_matches_numpy(ctx, opa, opb, m, n, k):
+    gh = _gh()
+    rng = np.random.default_rng(m * 7 + n * 3 + k)
+    batch = 3
+    ra, ca = (m, k) if opa == "N" else (k, m)
+    rb, cb = (k, n) if opb == "N" else (n, k)
+    A = synth.cn(rng, (batch, ra, ca), 1.0)
+    B = synth.cn(rng, (batch, rb, cb), 1.0)
+    C = synth.cn(rng, (batch, m, n), 1.0)
+    alpha, beta = 0.7 - 0.2j, -1.1 + 0.4j
+    dA, dB, dC = gh.dev(A), gh.dev(B), gh.dev(C)
+    dD = gh.empty((batch, m, n))
+    ctx.zgemm(opa, opb, m, n, k, alpha, dA, ca, ra * ca, dB, cb, rb * cb, beta,
+              dC, n, m * n, dD, n, m * n, batch)
+    D = dD.cpu().numpy()
+    opA = A if opa == "N" else np.conj(np.swapaxes(A, 1, 2))
+    opB = B if opb == "N" else np.conj(np.swapaxes(B, 1, 2))
+    ref = alpha * (opA @ opB) + beta * C
+    err = np.abs(D - ref).max() / np.abs(ref).max()
+    assert err < 1e-14, err
+
+
+def test_zgemm_in_place_and_shared_operand(ctx):
+    gh = _gh()
+    rng = np.random.default_rng(5)
+    A = synth.cn(rng, (48, 48), 1.0)                 # shared (stride 0)
+    B = synth.cn(rng, (4, 48, 48), 1.0)
+    C = synth.cn(rng, (4, 48, 48), 1.0)
+    dA, dB, dC = gh.dev(A), gh.dev(B), gh.dev(C)
+    ctx.zgemm("N", "N", 48, 48, 48, -1.0 + 0j, dA, 48, 0, dB, 48, 48 * 48,
+              1.0 + 0j, dC, 48, 48 * 48, dC, 48, 48 * 48, 4)
+    assert np.abs(dC.cpu().numpy() - (C - A[None] @ B)).max() < 1e-13
+
+
+def _adversarial(b, kind, rng):
+    if kind == "random":
+        return synth.cn(rng, (b, b), 1.0 / b) + np.eye(b) * 0.5
+    if kind == "zero_lead":
+        M = synth.cn(rng, (b, b), 1.0 / b)
+        M[:, 0] = 0.0
+        M[b // 2, 0] = 1.0                            # only pivot far down
+        return M
+    if kind == "perm_identity":
+        P = np.eye(b, dtype=np.complex128)[rng.permutation(b)]
+        return P * (1.0 + 0.5j)
+    if kind == "graded":
+        M = synth.cn(rng, (b, b), 1.0) + 2 * np.eye(b)
+        return M * (10.0 ** (-np.arange(b) * 6.0 / max(b - 1, 1)))[:, None]
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("b", [1, 5, 16, 17, 32, 64, 100, 257, 512, 768])
+@pytest.mark.parametrize("kind", ["random", "zero_lead", "perm_identity", "graded"])
+def test_zinv_matches_numpy(ctx, b, kind):
+    gh = _gh()
+    if kind == "zero_lead" and b < 3:
+        pytest.skip("needs b >= 3")
+    rng = np.random.default_rng(b * 13 + len(kind))
+    batch = 3
+    A = np.stack([_adversarial(b, kind, rng) for _ in range(batch)])
+    dA = gh.dev(A)
+    dX = gh.empty((batch, b, b))
+    info = torch.zeros(batch, dtype=torch.int32, device=gh.DEV)
+    ctx.zinv(b, dA, dX, info, batch)
+    X = dX.cpu().numpy()
+    assert np.all(info.cpu().numpy() == 0)
+    ref = np.linalg.inv(A)
+    for e in range(batch):
+        cond = np.linalg.cond(A[e])
+        err = np.linalg.norm(X[e] - ref[e]) / np.linalg.norm(ref[e])
+        assert err < 1e-15 * cond * b + 1e-13, (e, err, cond)
+
+
+def test_zinv_reports_singular_column(ctx):
+    gh = _gh()
+    rng = np.random.default_rng(1)
+    A = np.stack([synth.cn(rng, (40, 40), 1.0) + 2 * np.eye(40) for _ in range(3)])
+    A[1][:, 23] = 0.0                                 # exactly singular
+    dA = gh.dev(A)
+    dX = gh.empty((3, 40, 40))
+    info = torch.zeros(3, dtype=torch.int32, device=gh.DEV)
+    ctx.zinv(40, dA, dX, info, 3)
+    inf = info.cpu().numpy()
+    assert inf[0] == 0 and inf[2] == 0
+    assert inf[1] > 0
+    X = dX.cpu().numpy()
+    for e in (0, 2):
+        assert np.linalg.norm(X[e] - np.linalg.inv(A[e])) < 1e-12 * np.linalg.norm(X[e])
+
+
+# ----------------------------------------------------------- end-to-end RGF
+
+def test_config1_plain_fp64(ctx):
+    """8 blocks of 32, 16 energies on [-2, 2]: every output block vs oracle."""
+    gh = _gh()
+    p = synth.g_problem(1234, 8, 32, n_e=16)
+    prob, XR, XL, XG = gh.solve_g(ctx, p)
+    assert prob.status == 0
+    worst = 0.0
+    for e in range(16):
+        OR, (OL, OG) = _oracle_g(p, e)
+        worst = max(worst, triple_err(_sel(XR, e), OR), triple_err(_sel(XL, e), OL),
+                    triple_err(_sel(XG, e), OG))
+    assert worst < TOL, worst
+
+
+@pytest.mark.parametrize("n,b", [(1, 24), (2, 17), (5, 40), (3, 100), (4, 130)])
+def test_ragged_shapes_bt_sigma(ctx, n, b):
+    """Block sizes off the tile grid and self-energies with off-diagonal
+    blocks (the y_i / Y_i terms)."""
+    gh = _gh()
+    p = synth.g_problem(77 + n + b, n, b, n_e=3, bt_sigma=True)
+    prob, XR, XL, XG = gh.solve_g(ctx, p, h_lower=False)
+    assert prob.status == 0
+    for e in range(3):
+        OR, (OL, OG) = _oracle_g(p, e)
+        assert triple_err(_sel(XR, e), OR) < TOL
+        assert triple_err(_sel(XL, e), OL) < TOL
+        assert triple_err(_sel(XG, e), OG) < TOL
+
+
+def test_overlap_matrix_and_single_rhs(ctx):
+    """Non-identity S with off-diagonal blocks, only X^< requested."""
+    gh = _gh()
+    n, b = 4, 20
+    p = synth.g_problem(9, n, b, n_e=2)
+    rng = np.random.default_rng(10)
+    Sd, Su, Sl = synth.hermitian_bt(rng, n, b, 0.01, 0.01)
+    Sd = Sd + np.eye(b)[None]
+    prob, XR, XL, XG = gh.solve_g(ctx, p, want=("L",), S=(Sd, Su, Sl))
+    assert prob.status == 0 and XG is None
+    for e in range(2):
+        E = p["energies"][e]
+        A = assemble_g(E, p["H"], (p["sigma_r"][0][e], None, None), S=(Sd, Su, Sl))
+        d, u, _ = (t[e] for t in p["sigma_l"])
+        OR, (OL,) = rgf_selected(A, [(d, u, -np.conj(np.swapaxes(u, -1, -2)))])
+        assert triple_err(_sel(XR, e), OR) < TOL
+        assert triple_err(_sel(XL, e), OL) < TOL
+
+
+def test_w_type_with_retarded_w(ctx):
+    """Screened-Coulomb system I - V P^R with B^s = V P^s V^dag (BT
+    truncation) and the diagonal of W^R = X^R V."""
+    gh = _gh()
+    n, b = 6, 48
+    E = np.array([-1.5, 0.2, 1.9])
+    p = synth.w_problem(21, n, b, E)
+    prob, XR, XL, XG, WR = gh.solve_w(ctx, p, v_lower=False)
+    assert prob.status == 0
+    for e in range(3):
+        Pr = tuple(t[e] for t in p["P_r"])
+        Pl = tuple(t[e] for t in p["P_l"])
+        Pg = tuple(t[e] for t in p["P_g"])
+        A, Bs = assemble_w(p["V"], Pr, [Pl, Pg])
+        OR, (OL, OG) = rgf_selected(A, Bs)
+        assert triple_err(_sel(XR, e), OR) < TOL
+        assert triple_err(_sel(XL, e), OL) < TOL
+        assert triple_err(_sel(XG, e), OG) < TOL
+        assert max_rel_err(WR[e], w_retarded_diag(OR, p["V"])) < TOL
+
+
+def test_w_type_bt_polarization(ctx):
+    """P^s with off-diagonal blocks exercises every V P^s V^dag term."""
+    gh = _gh()
+    n, b = 5, 33
+    E = np.array([0.4, -0.9])
+    p = synth.w_problem(3, n, b, E)
+    rng = np.random.default_rng(4)
+    for key in ("P_l", "P_g"):
+        d, u, l = synth.random_antihermitian_bt(rng, n, b, 0.1)
+        p[key] = (np.stack([d, d * 0.5]), np.stack([u, u * 0.5]), np.stack([l, l * 0.5]))
+    prob, XR, XL, XG, WR = gh.solve_w(ctx, p)
+    assert prob.status == 0
+    for e in range(2):
+        A, Bs = assemble_w(p["V"], tuple(t[e] for t in p["P_r"]),
+                           [tuple(t[e] for t in p["P_l"]), tuple(t[e] for t in p["P_g"])])
+        OR, (OL, OG) = rgf_selected(A, Bs)
+        assert triple_err(_sel(XR, e), OR) < TOL
+        assert triple_err(_sel(XL, e), OL) < TOL
+        assert triple_err(_sel(XG, e), OG) < TOL
+
+
+def test_energy_chunking_is_exact(ctx):
+    """A small workspace budget forces several energy chunks; results are
+    bitwise those of a single chunk."""
+    gh = _gh()
+    p = synth.g_problem(5, 6, 64, n_e=7)
+    _, XR1, XL1, XG1 = gh.solve_g(ctx, p)
+    small = Q.Context(0, budget_bytes=3 * 1024 * 1024)
+    _, XR2, XL2, XG2 = gh.solve_g(small, p)
+    small.close()
+    for a, b_ in zip(XR1 + XL1 + XG1, XR2 + XL2 + XG2):
+        assert np.array_equal(a, b_)
+
+
+def test_singular_problem_isolated(ctx):
+    """An exactly singular diagonal block is reported with its energy and
+    block; the other problem of the batch is solved normally."""
+    gh = _gh()
+    n, b = 4, 16
+    good = synth.g_problem(31, n, b, n_e=2)
+    bad = synth.g_problem(32, n, b, n_e=2)
+    # make Mt_22 exactly singular at energy 1: H_22 = E*I - Sigma^R_22 - K, K rank-deficient
+    E1 = bad["energies"][1]
+    K = np.zeros((b, b), np.complex128)
+    K[:, 1:] = synth.cn(np.random.default_rng(2), (b, b - 1), 1.0)
+    bad["H"] = (bad["H"][0].copy(), bad["H"][1], bad["H"][2])
+    bad["H"][0][2] = E1 * np.eye(b) - bad["sigma_r"][0][1][2] - K
+    bad["H"] = (bad["H"][0], np.zeros_like(bad["H"][1]), np.zeros_like(bad["H"][2]))
+    import gpu_helpers as G
+    probs, outs = [], []
+    for p in (good, bad):
+        Ee = np.ascontiguousarray(p["energies"])
+        H = (G.dev(p["H"][0]), G.dev(p["H"][1]), G.dev(p["H"][2]))
+        sr = tuple(G.dev(t) for t in p["sigma_r"])
+        sl = (G.dev(p["sigma_l"][0]), None, None)
+        sg = (G.dev(p["sigma_g"][0]), None, None)
+        XR, XL, XG = G.outputs(2, n, b), G.outputs(2, n, b), G.outputs(2, n, b)
+        probs.append(Q.make_g_problem(Ee, H, sr, sl, sg, XR, XL, XG))
+        outs.append((Ee, H, sr, sl, sg, XR, XL, XG))
+    st = ctx.solve_batch(probs)
+    assert st == Q.QTX_ERR_PROBLEM
+    assert probs[0].status == Q.QTX_OK
+    assert probs[1].status == Q.QTX_ERR_SINGULAR
+    assert probs[1].fail_energy == 1 and probs[1].fail_block == 2
+    XR = G.host(outs[0][5])
+    OR, _ = _oracle_g(good, 1)
+    assert triple_err(_sel(XR, 1), OR) < TOL
+
+
+def test_invalid_arguments_rejected(ctx):
+    gh = _gh()
+    p = synth.g_problem(1, 3, 8, n_e=1)
+    E = np.ascontiguousarray(p["energies"])
+    H = (gh.dev(p["H"][0]), gh.dev(p["H"][1]), gh.dev(p["H"][2]))
+    sr = tuple(gh.dev(t) for t in p["sigma_r"])
+    XR = gh.outputs(1, 3, 8)
+    prob = Q.make_g_problem(E, H, sr, None, None, XR)
+    prob.n_blocks = 0
+    with pytest.raises(Q.QtxError) as ei:
+        ctx.solve_batch([prob])
+    assert ei.value.status == Q.QTX_ERR_INVALID_ARG
+
+
+# --------------------------------------------- device-size shape (config 2)
+
+def test_device_size_sampled_energies(ctx):
+    """32 blocks of 512, in the launch shapes the benchmark uses: two
+    energies (both grid ends of the 128-point grid) checked block by block
+    against the oracle, plus the spectral identity on the GPU outputs."""
+    gh = _gh()
+    E = synth.energy_grid(128)[[0, 127]]
+    p = synth.g_problem(2024, 32, 512, energies=E)
+    prob, XR, XL, XG = gh.solve_g(ctx, p)
+    assert prob.status == 0
+    adj = lambda T: np.conj(np.swapaxes(T, -1, -2))
+    for e in range(2):
+        OR, (OL, OG) = _oracle_g(p, e)
+        assert triple_err(_sel(XR, e), OR) < TOL
+        assert triple_err(_sel(XL, e), OL) < TOL
+        assert triple_err(_sel(XG, e), OG) < TOL
+        # G^> - G^< = G^R - G^A on the GPU outputs
+        assert max_rel_err(XG[0][e] - XL[0][e], XR[0][e] - adj(XR[0][e])) < 1e-9
