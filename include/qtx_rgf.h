@@ -192,13 +192,15 @@ qtx_status qtx_rgf_zgemm(qtx_rgf_ctx* ctx, char opa, char opb, int32_t m,
                          int64_t ldc, int64_t sC, void* D, int64_t ldd,
                          int64_t sD, int32_t batch);
 
-/* Same product with complex64 operands on the FP32 matrix cores
- * (FP32 accumulate), used by QTX_MIXED. */
+/* The same product computed on the FP32 matrix cores, as QTX_MIXED uses it:
+ * the complex128 operands are rounded to complex64 when staged, products
+ * accumulate in FP32, and the epilogue (alpha, beta, C, D) is complex128.
+ * Arguments as for qtx_rgf_zgemm. */
 qtx_status qtx_rgf_cgemm(qtx_rgf_ctx* ctx, char opa, char opb, int32_t m,
-                         int32_t n, int32_t k, float alpha_re, float alpha_im,
-                         const void* A, int64_t lda, int64_t sA,
-                         const void* B, int64_t ldb, int64_t sB,
-                         float beta_re, float beta_im, const void* C,
+                         int32_t n, int32_t k, double alpha_re,
+                         double alpha_im, const void* A, int64_t lda,
+                         int64_t sA, const void* B, int64_t ldb, int64_t sB,
+                         double beta_re, double beta_im, const void* C,
                          int64_t ldc, int64_t sC, void* D, int64_t ldd,
                          int64_t sD, int32_t batch);
 

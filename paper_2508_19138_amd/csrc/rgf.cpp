@@ -145,6 +145,9 @@ class Solver {
   Solver(qtx_rgf_ctx* c, int b, int ec) : c_(c), b_(b), ec_(ec) {
     blk_ = (long long)b * b;
   }
+  // QTX_MIXED: the recursion's products run on the FP32 matrix cores with
+  // FP64 epilogues; inverses, assembly and storage stay FP64.
+  void set_fp32_products(bool on) { fp32_ = on; }
 
   // Grouped product launch: all terms share op and shape (b x b x b),
   // the batch is the chunk's energies, and `nb2` consecutive blocks
@@ -174,7 +177,10 @@ class Solver {
     }
     const double mult = (double)ec_ * nb2;
     const double flops = 8.0 * g.M * g.N * (double)g.K * g.ngroups * mult;
-    timed(c_, kClassZgemm, flops, bytes * mult, [&] { return launch_zgemm(opa, opb, g, c_->stream); });
+    if (fp32_)
+      timed(c_, kClassCgemm, flops, bytes * mult, [&] { return launch_cgemm(opa, opb, g, c_->stream); });
+    else
+      timed(c_, kClassZgemm, flops, bytes * mult, [&] { return launch_zgemm(opa, opb, g, c_->stream); });
   }
 
   void inverse(const View& S, long long is, const View& X, long long ix,
@@ -221,6 +227,7 @@ class Solver {
   qtx_rgf_ctx* c_;
   int b_, ec_;
   long long blk_;
+  bool fp32_ = false;
 };
 
 // Operands of the recursion for one chunk.
@@ -453,7 +460,6 @@ View in_view(const void* p, long long es, long long bs) {
 std::string validate(const qtx_rgf_problem& p) {
   if (p.kind != QTX_KIND_G && p.kind != QTX_KIND_W) return "unknown kind";
   if (p.precision != QTX_FP64 && p.precision != QTX_MIXED) return "unknown precision";
-  if (p.precision == QTX_MIXED) return "precision QTX_MIXED is not available in this build";
   if (p.n_blocks < 1 || p.block_size < 1 || p.n_energies < 1) return "n_blocks, block_size and n_energies must be >= 1";
   if (p.block_size > 1024) return "block_size above 1024 is not supported";
   if (p.flags != 0) return "flags must be 0";
@@ -713,6 +719,7 @@ qtx_status solve_problem(qtx_rgf_ctx* c, qtx_rgf_problem& p) {
       } else {
         k.U = Hu; k.L = HL; k.su = -1.0; k.sl = -1.0;
       }
+      sc.set_fp32_products(p.precision == QTX_MIXED);
       run_core(sc, k, [&](int i) {
         LinComb a{};
         a.E = d_E;
@@ -740,7 +747,9 @@ qtx_status solve_problem(qtx_rgf_ctx* c, qtx_rgf_problem& p) {
       }
       w_assemble(sc, w, n, nr);
       k.U = w.Au; k.L = w.Al; k.su = 1.0; k.sl = 1.0;
+      sc.set_fp32_products(p.precision == QTX_MIXED);
       run_core(sc, k, [&](int i) { sc.copy(k.tS, 0, w.Ad, i); });
+      sc.set_fp32_products(false);
       if (p.WR_diag) {
         // W^R_ii = X_ii V_ii + X_{i,i-1} V_{i-1,i} + X_{i,i+1} V_{i+1,i}
         const View WR = outv(p.WR_diag, n);
@@ -917,18 +926,20 @@ qtx_status qtx_rgf_reset_stats(qtx_rgf_ctx* c) {
   return QTX_OK;
 }
 
-qtx_status qtx_rgf_zgemm(qtx_rgf_ctx* c, char opa, char opb, int32_t m, int32_t n,
-                         int32_t k, double ar, double ai, const void* A, int64_t lda,
-                         int64_t sA, const void* B, int64_t ldb, int64_t sB,
-                         double br, double bi, const void* C, int64_t ldc, int64_t sC,
-                         void* D, int64_t ldd, int64_t sD, int32_t batch) {
+}  // extern "C"
+
+namespace {
+qtx_status gemm_abi(bool fp32, qtx_rgf_ctx* c, char opa, char opb, int32_t m, int32_t n,
+                    int32_t k, double ar, double ai, const void* A, int64_t lda,
+                    int64_t sA, const void* B, int64_t ldb, int64_t sB,
+                    double br, double bi, const void* C, int64_t ldc, int64_t sC,
+                    void* D, int64_t ldd, int64_t sD, int32_t batch) {
   if (!c) return QTX_ERR_INVALID_ARG;
   if ((opa != 'N' && opa != 'C') || (opb != 'N' && opb != 'C') || m < 0 || n < 0 ||
       k < 0 || batch < 0 || batch > 65535 || !A || !B || !D || (!C && (br != 0.0 || bi != 0.0)))
     return QTX_ERR_INVALID_ARG;
-  const int64_t rowsA = opa == 'N' ? m : k, colsA = opa == 'N' ? k : m;
-  const int64_t rowsB = opb == 'N' ? k : n, colsB = opb == 'N' ? n : k;
-  (void)rowsA; (void)rowsB;
+  const int64_t colsA = opa == 'N' ? k : m;
+  const int64_t colsB = opb == 'N' ? n : k;
   if (lda < std::max<int64_t>(1, colsA) || ldb < std::max<int64_t>(1, colsB) ||
       ldd < std::max<int64_t>(1, n) || (C && ldc < std::max<int64_t>(1, n)))
     return QTX_ERR_INVALID_ARG;
@@ -947,7 +958,9 @@ qtx_status qtx_rgf_zgemm(qtx_rgf_ctx* c, char opa, char opb, int32_t m, int32_t 
     g.g[0].beta = C ? zc{br, bi} : kZero;
     const double fl = 8.0 * m * n * (double)k * batch;
     const double by = 16.0 * ((double)m * k + (double)k * n + (C ? 2.0 : 1.0) * m * n) * batch;
-    timed(c, kClassZgemm, fl, by, [&] { return launch_zgemm(opa, opb, g, c->stream); });
+    timed(c, fp32 ? kClassCgemm : kClassZgemm, fl, by, [&] {
+      return fp32 ? launch_cgemm(opa, opb, g, c->stream) : launch_zgemm(opa, opb, g, c->stream);
+    });
     HIPCHK(c, hipStreamSynchronize(c->stream));
     flush_stats(c);
   } catch (const Fail& f) {
@@ -955,13 +968,26 @@ qtx_status qtx_rgf_zgemm(qtx_rgf_ctx* c, char opa, char opb, int32_t m, int32_t 
   }
   return QTX_OK;
 }
+}  // namespace
 
-qtx_status qtx_rgf_cgemm(qtx_rgf_ctx* c, char, char, int32_t, int32_t, int32_t,
-                         float, float, const void*, int64_t, int64_t, const void*,
-                         int64_t, int64_t, float, float, const void*, int64_t,
-                         int64_t, void*, int64_t, int64_t, int32_t) {
-  if (c) c->err = "complex64 products are not available in this build";
-  return QTX_ERR_INVALID_ARG;
+extern "C" {
+
+qtx_status qtx_rgf_zgemm(qtx_rgf_ctx* c, char opa, char opb, int32_t m, int32_t n,
+                         int32_t k, double ar, double ai, const void* A, int64_t lda,
+                         int64_t sA, const void* B, int64_t ldb, int64_t sB,
+                         double br, double bi, const void* C, int64_t ldc, int64_t sC,
+                         void* D, int64_t ldd, int64_t sD, int32_t batch) {
+  return gemm_abi(false, c, opa, opb, m, n, k, ar, ai, A, lda, sA, B, ldb, sB, br, bi,
+                  C, ldc, sC, D, ldd, sD, batch);
+}
+
+qtx_status qtx_rgf_cgemm(qtx_rgf_ctx* c, char opa, char opb, int32_t m, int32_t n,
+                         int32_t k, double ar, double ai, const void* A, int64_t lda,
+                         int64_t sA, const void* B, int64_t ldb, int64_t sB,
+                         double br, double bi, const void* C, int64_t ldc, int64_t sC,
+                         void* D, int64_t ldd, int64_t sD, int32_t batch) {
+  return gemm_abi(true, c, opa, opb, m, n, k, ar, ai, A, lda, sA, B, ldb, sB, br, bi,
+                  C, ldc, sC, D, ldd, sD, batch);
 }
 
 qtx_status qtx_rgf_zinv(qtx_rgf_ctx* c, int32_t b, void* A, void* X, int32_t* info,

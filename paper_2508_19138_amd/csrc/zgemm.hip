@@ -13,8 +13,41 @@
 // and conjugated on the way into LDS.
 #include "qtx_internal.h"
 
+// Row held by accumulator register r of lane group lk (= lane / 16) for
+// v_mfma_f32_16x16x4_f32.
+#ifndef QTX_F32_ROW
+#define QTX_F32_ROW(r, lk) (4 * (lk) + (r))
+#endif
+
 namespace qtx {
 namespace {
+
+// Arithmetic of the matrix-core product.  Operands always live in HBM as
+// complex128; the FP32 variant rounds them to complex64 on the way into LDS
+// and accumulates in FP32, while the epilogue (alpha, beta, C) stays FP64.
+struct MathF64 {
+  typedef double2 lds_t;
+  typedef d4v acc_t;
+  typedef double real_t;
+  static __device__ __forceinline__ lds_t cvt(double2 v) { return v; }
+  static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator register r of lane group lk holds row 4r + lk
+  static __device__ __forceinline__ int row(int r, int lk) { return 4 * r + lk; }
+};
+struct MathF32 {
+  typedef float2 lds_t;
+  typedef f4v acc_t;
+  typedef float real_t;
+  static __device__ __forceinline__ lds_t cvt(double2 v) {
+    return make_float2((float)v.x, (float)v.y);
+  }
+  static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int lk) { return QTX_F32_ROW(r, lk); }
+};
 
 template <int OPA, int OPB, int BM, int BN, int BK, int WGM, int WGN>
 struct ZTile {
@@ -32,12 +65,15 @@ struct ZTile {
   static_assert(kWM % 16 == 0 && kWN % 16 == 0 && BK % 4 == 0, "tile");
 };
 
-template <int OPA, int OPB, int BM, int BN, int BK, int WGM, int WGN>
+template <class P, int OPA, int OPB, int BM, int BN, int BK, int WGM, int WGN>
 __global__ __launch_bounds__(64 * WGM * WGN)
 void zgemm_kernel(GemmArgs args) {
   using T = ZTile<OPA, OPB, BM, BN, BK, WGM, WGN>;
-  __shared__ double2 As[2][BK][T::kLdA];
-  __shared__ double2 Bs[2][BK][T::kLdB];
+  typedef typename P::lds_t L;
+  typedef typename P::acc_t Acc;
+  typedef typename P::real_t R;
+  __shared__ L As[2][BK][T::kLdA];
+  __shared__ L Bs[2][BK][T::kLdB];
 
   const GemmGroup& g = args.g[blockIdx.z];
   const int M = args.M, N = args.N, K = args.K;
@@ -88,7 +124,7 @@ void zgemm_kernel(GemmArgs args) {
       int q = tid + r * T::kThreads;
       int m, k;
       if (OPA == 0) { m = q / BK; k = q % BK; } else { k = q / BM; m = q % BM; }
-      double2 v = ra[r];
+      L v = P::cvt(ra[r]);
       if (OPA == 1) v.y = -v.y;
       As[buf][k][m] = v;
     }
@@ -97,19 +133,19 @@ void zgemm_kernel(GemmArgs args) {
       int q = tid + r * T::kThreads;
       int n, k;
       if (OPB == 0) { k = q / BN; n = q % BN; } else { n = q / BK; k = q % BK; }
-      double2 v = rb[r];
+      L v = P::cvt(rb[r]);
       if (OPB == 1) v.y = -v.y;
       Bs[buf][k][n] = v;
     }
   };
 
-  d4v accR[T::kTM][T::kTN], accI[T::kTM][T::kTN];
+  Acc accR[T::kTM][T::kTN], accI[T::kTM][T::kTN];
 #pragma unroll
   for (int i = 0; i < T::kTM; ++i)
 #pragma unroll
     for (int j = 0; j < T::kTN; ++j) {
-      accR[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
-      accI[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
+      accR[i][j] = Acc{0, 0, 0, 0};
+      accI[i][j] = Acc{0, 0, 0, 0};
     }
 
   const int nk = (K + BK - 1) / BK;
@@ -123,20 +159,20 @@ void zgemm_kernel(GemmArgs args) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kidx = kk * 4 + lk;
-      double2 a[T::kTM], b[T::kTN];
+      L a[T::kTM], b[T::kTN];
 #pragma unroll
       for (int i = 0; i < T::kTM; ++i) a[i] = As[buf][kidx][wm * T::kWM + i * 16 + lrow];
 #pragma unroll
       for (int j = 0; j < T::kTN; ++j) b[j] = Bs[buf][kidx][wn * T::kWN + j * 16 + lrow];
 #pragma unroll
       for (int i = 0; i < T::kTM; ++i) {
-        const double nai = -a[i].y;
+        const R nai = -a[i].y;
 #pragma unroll
         for (int j = 0; j < T::kTN; ++j) {
-          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, accR[i][j], 0, 0, 0);
-          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].y, accI[i][j], 0, 0, 0);
-          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, b[j].y, accR[i][j], 0, 0, 0);
-          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].x, accI[i][j], 0, 0, 0);
+          accR[i][j] = P::mfma(a[i].x, b[j].x, accR[i][j]);
+          accI[i][j] = P::mfma(a[i].x, b[j].y, accI[i][j]);
+          accR[i][j] = P::mfma(nai, b[j].y, accR[i][j]);
+          accI[i][j] = P::mfma(a[i].y, b[j].x, accI[i][j]);
         }
       }
     }
@@ -155,35 +191,44 @@ void zgemm_kernel(GemmArgs args) {
     for (int j = 0; j < T::kTN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm * T::kWM + i * 16 + 4 * r + lk;
+        const int gm = m0 + wm * T::kWM + i * 16 + P::row(r, lk);
         const int gn = n0 + wn * T::kWN + j * 16 + lrow;
         if (gm < M && gn < N) {
-          double2 v = cscale(g.alpha, make_double2(accR[i][j][r], accI[i][j][r]));
+          double2 v = cscale(g.alpha, make_double2((double)accR[i][j][r], (double)accI[i][j][r]));
           if (useC) v = cadd(v, cscale(g.beta, C[(long long)gm * ldc + gn]));
           D[(long long)gm * ldd + gn] = v;
         }
       }
 }
 
-template <int OPA, int OPB>
+template <class P, int OPA, int OPB>
 hipError_t launch_t(const GemmArgs& a, hipStream_t s) {
   constexpr int BM = 64, BN = 64, BK = 16, WGM = 2, WGN = 2;
   const int nb2 = a.batch2 > 0 ? a.batch2 : 1;
   dim3 grid(((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN), a.batch * nb2, a.ngroups);
-  hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, BM, BN, BK, WGM, WGN>), grid,
+  hipLaunchKernelGGL((zgemm_kernel<P, OPA, OPB, BM, BN, BK, WGM, WGN>), grid,
                      dim3(64 * WGM * WGN), 0, s, a);
   return hipGetLastError();
+}
+
+template <class P>
+hipError_t dispatch(char opa, char opb, const GemmArgs& a, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0 || a.batch <= 0 || a.ngroups <= 0) return hipSuccess;
+  const int oa = (opa == 'C'), ob = (opb == 'C');
+  if (oa == 0 && ob == 0) return launch_t<P, 0, 0>(a, s);
+  if (oa == 0 && ob == 1) return launch_t<P, 0, 1>(a, s);
+  if (oa == 1 && ob == 0) return launch_t<P, 1, 0>(a, s);
+  return launch_t<P, 1, 1>(a, s);
 }
 
 }  // namespace
 
 hipError_t launch_zgemm(char opa, char opb, const GemmArgs& a, hipStream_t s) {
-  if (a.M <= 0 || a.N <= 0 || a.batch <= 0 || a.ngroups <= 0) return hipSuccess;
-  const int oa = (opa == 'C'), ob = (opb == 'C');
-  if (oa == 0 && ob == 0) return launch_t<0, 0>(a, s);
-  if (oa == 0 && ob == 1) return launch_t<0, 1>(a, s);
-  if (oa == 1 && ob == 0) return launch_t<1, 0>(a, s);
-  return launch_t<1, 1>(a, s);
+  return dispatch<MathF64>(opa, opb, a, s);
+}
+
+hipError_t launch_cgemm(char opa, char opb, const GemmArgs& a, hipStream_t s) {
+  return dispatch<MathF32>(opa, opb, a, s);
 }
 
 }  // namespace qtx

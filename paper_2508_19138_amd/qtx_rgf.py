@@ -104,10 +104,7 @@ def lib():
                                 + [ctypes.c_double, ctypes.c_double]
                                 + ptr_ld_s + ptr_ld_s + [ctypes.c_int32])
     L.qtx_rgf_zgemm.restype = ctypes.c_int
-    L.qtx_rgf_cgemm.argtypes = (gemm_args + [ctypes.c_float, ctypes.c_float]
-                                + ptr_ld_s + ptr_ld_s
-                                + [ctypes.c_float, ctypes.c_float]
-                                + ptr_ld_s + ptr_ld_s + [ctypes.c_int32])
+    L.qtx_rgf_cgemm.argtypes = L.qtx_rgf_zgemm.argtypes
     L.qtx_rgf_cgemm.restype = ctypes.c_int
     L.qtx_rgf_zinv.argtypes = [c_ctx, ctypes.c_int32, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
@@ -210,12 +207,13 @@ class Context:
         lib().qtx_rgf_reset_stats(self._h)
 
     def zgemm(self, opa, opb, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta,
-              C, ldc, sC, D, ldd, sD, batch):
-        st = lib().qtx_rgf_zgemm(self._h, opa.encode(), opb.encode(), m, n, k,
-                                 alpha.real, alpha.imag, _ptr(A), lda, sA,
-                                 _ptr(B), ldb, sB, beta.real, beta.imag,
-                                 _ptr(C), ldc, sC, _ptr(D), ldd, sD, batch)
-        return self._check(st, "qtx_rgf_zgemm")
+              C, ldc, sC, D, ldd, sD, batch, fp32=False):
+        fn = lib().qtx_rgf_cgemm if fp32 else lib().qtx_rgf_zgemm
+        st = fn(self._h, opa.encode(), opb.encode(), m, n, k,
+                alpha.real, alpha.imag, _ptr(A), lda, sA,
+                _ptr(B), ldb, sB, beta.real, beta.imag,
+                _ptr(C), ldc, sC, _ptr(D), ldd, sD, batch)
+        return self._check(st, "qtx_rgf_cgemm" if fp32 else "qtx_rgf_zgemm")
 
     def zinv(self, b, A, X, info, batch):
         st = lib().qtx_rgf_zinv(self._h, b, _ptr(A), _ptr(X), _ptr(info), batch)

@@ -317,3 +317,45 @@ def test_device_size_sampled_energies(ctx):
         assert triple_err(_sel(XG, e), OG) < TOL
         # G^> - G^< = G^R - G^A on the GPU outputs
         assert max_rel_err(XG[0][e] - XL[0][e], XR[0][e] - adj(XR[0][e])) < 1e-9
+
+
+# ------------------------------------------------------ mixed precision (S2)
+
+@pytest.mark.parametrize("opa,opb", [("N", "N"), ("N", "C"), ("C", "N")])
+@pytest.mark.parametrize("m,n,k", [(17, 33, 5), (64, 64, 64), (130, 100, 257)])
+def test_cgemm_fp32_matrix_cores(ctx, opa, opb, m, n, k):
+    """complex128 operands rounded to complex64, FP32 accumulation, FP64
+    epilogue: error within FP32 rounding of the product."""
+    gh = _gh()
+    rng = np.random.default_rng(m + n + k)
+    ra, ca = (m, k) if opa == "N" else (k, m)
+    rb, cb = (k, n) if opb == "N" else (n, k)
+    A = synth.cn(rng, (2, ra, ca), 1.0)
+    B = synth.cn(rng, (2, rb, cb), 1.0)
+    C = synth.cn(rng, (2, m, n), 1.0)
+    dD = gh.empty((2, m, n))
+    ctx.zgemm(opa, opb, m, n, k, 1.0 + 0j, gh.dev(A), ca, ra * ca, gh.dev(B), cb,
+              rb * cb, -1.0 + 0j, gh.dev(C), n, m * n, dD, n, m * n, 2, fp32=True)
+    opA = A if opa == "N" else np.conj(np.swapaxes(A, 1, 2))
+    opB = B if opb == "N" else np.conj(np.swapaxes(B, 1, 2))
+    ref = opA @ opB - C
+    err = np.abs(dD.cpu().numpy() - ref).max() / (np.sqrt(k) * 1.0)
+    assert err < 5e-6, err
+
+
+def test_mixed_precision_error_vs_fp64_oracle(ctx):
+    """QTX_MIXED on a 16-block, b=64 system: per-output error against the
+    FP64 oracle is reported and bounded (FP32 products, FP64 inverses)."""
+    gh = _gh()
+    p = synth.g_problem(88, 16, 64, n_e=4)
+    prob, XR, XL, XG = gh.solve_g(ctx, p, precision=Q.QTX_MIXED)
+    assert prob.status == 0
+    worst = {}
+    for e in range(4):
+        OR, (OL, OG) = _oracle_g(p, e)
+        for name, got, ref in (("XR", XR, OR), ("XL", XL, OL), ("XG", XG, OG)):
+            for part, g_, r_ in zip("dul", _sel(got, e), ref):
+                worst[name + part] = max(worst.get(name + part, 0.0), max_rel_err(g_, r_))
+    print("mixed-precision max block rel err:", worst)
+    assert max(worst.values()) < 1e-3
+    assert max(worst.values()) > 1e-9          # the FP32 path really ran
