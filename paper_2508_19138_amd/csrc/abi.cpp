@@ -1,0 +1,561 @@
+// C ABI of the RGF library: argument validation, lanes, admission of lanes
+// into the workspace by footprint, and the merged execution of a batch.
+//
+// A batch of problems becomes a set of lanes (one problem, a contiguous
+// chunk of its energies, its own workspace region).  Lanes are admitted into
+// the workspace first-fit as memory frees up, and every admitted lane
+// advances in the same merged launches (see exec.cpp), so solves of
+// different block size, block count and kind share the GPU.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/qtx_rgf.h"
+#include "emit.h"
+#include "exec.h"
+
+using namespace qtx;
+
+struct qtx_rgf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  uint64_t budget = 0;
+  uint32_t flags = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  char* aux = nullptr;
+  size_t aux_bytes = 0;
+  std::string err;
+  std::vector<KStat> stats = std::vector<KStat>(kNumClasses);
+  std::unique_ptr<Executor> exe;
+  Tuner tuner;
+  bool graphs = true;
+  bool busy = false;
+};
+
+namespace {
+
+#define HIPCHK(ctx, expr)                                                    \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);        \
+      throw Fail{QTX_ERR_HIP};                                               \
+    }                                                                        \
+  } while (0)
+
+constexpr size_t kArenaLimit = 32u << 20;    // descriptor bytes per segment
+
+// First-fit allocator over [0, cap) with 256-byte granularity.
+class Regions {
+ public:
+  explicit Regions(size_t cap) { free_[0] = cap; }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = (bytes + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        const size_t o = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[o] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
+size_t budget_now(qtx_rgf_ctx* c) {
+  if (c->budget) return c->budget;
+  size_t fr = 0, tot = 0;
+  HIPCHK(c, hipMemGetInfo(&fr, &tot));
+  return (size_t)(0.9 * (double)(fr + c->ws_bytes));
+}
+
+void ensure(qtx_rgf_ctx* c, char** p, size_t* have, size_t need) {
+  if (*have >= need) return;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (*p) {
+    c->exe->release();              // cached graphs refer to the old memory
+    (void)hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+  }
+  if (hipMalloc((void**)p, need) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    c->err = "device allocation of " + std::to_string(need) + " bytes failed";
+    throw Fail{QTX_ERR_NOMEM};
+  }
+  *have = need;
+}
+
+std::string validate(const qtx_rgf_problem& p) {
+  if (p.kind != QTX_KIND_G && p.kind != QTX_KIND_W) return "unknown kind";
+  if (p.precision != QTX_FP64 && p.precision != QTX_MIXED) return "unknown precision";
+  if (p.n_blocks < 1 || p.block_size < 1 || p.n_energies < 1)
+    return "n_blocks, block_size and n_energies must be >= 1";
+  if (p.block_size > 1024) return "block_size above 1024 is not supported";
+  if (p.flags != 0) return "flags must be 0";
+  if (!p.XR.diag) return "XR.diag is required";
+  if (p.n_blocks > 1 && (!p.XR.upper || !p.XR.lower))
+    return "XR.upper and XR.lower are required when n_blocks > 1";
+  if (p.XL.diag && p.n_blocks > 1 && !p.XL.upper) return "XL.upper is required with XL.diag when n_blocks > 1";
+  if (p.XG.diag && p.n_blocks > 1 && !p.XG.upper) return "XG.upper is required with XG.diag when n_blocks > 1";
+  if (p.kind == QTX_KIND_G) {
+    if (!p.energies) return "energies (host) are required for G-type problems";
+    if (!p.H.diag || (p.n_blocks > 1 && !p.H.upper)) return "H.diag and H.upper are required";
+    if (!p.sigma_r.diag) return "sigma_r.diag is required";
+    if (!p.S.diag && (p.S.upper || p.S.lower)) return "S.upper/S.lower given without S.diag";
+    if (p.XL.diag && !p.sigma_l.diag) return "sigma_l.diag is required for XL";
+    if (p.XG.diag && !p.sigma_g.diag) return "sigma_g.diag is required for XG";
+    if (p.WR_diag) return "WR_diag applies to W-type problems only";
+  } else {
+    if (!p.V.diag || (p.n_blocks > 1 && !p.V.upper)) return "V.diag and V.upper are required";
+    if (!p.P_r.diag) return "P_r.diag is required";
+    if (p.XL.diag && !p.P_l.diag) return "P_l.diag is required for XL";
+    if (p.XG.diag && !p.P_g.diag) return "P_g.diag is required for XG";
+  }
+  return "";
+}
+
+struct BusyGuard {
+  qtx_rgf_ctx* c;
+  explicit BusyGuard(qtx_rgf_ctx* c_) : c(c_) { c->busy = true; }
+  ~BusyGuard() { c->busy = false; }
+};
+
+void run_lanes_to_end(qtx_rgf_ctx* c, std::vector<Lane*>& lanes) {
+  const bool prof = (c->flags & QTX_FLAG_PROFILE) != 0;
+  while (true) {
+    c->exe->build(lanes, kArenaLimit);
+    if (c->exe->empty()) break;
+    c->exe->flush(prof, c->graphs, c->stats);
+  }
+}
+
+qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
+  const bool prof = (c->flags & QTX_FLAG_PROFILE) != 0;
+  std::vector<Plan> plans(np);
+  size_t n_e_tot = 0, hl_tot = 0;
+  std::vector<size_t> e_off(np), hl_off(np, (size_t)-1);
+  for (int i = 0; i < np; ++i) {
+    probs[i].status = QTX_OK;
+    probs[i].fail_energy = -1;
+    probs[i].fail_block = -1;
+    plans[i] = make_plan(probs[i]);
+    e_off[i] = n_e_tot;
+    n_e_tot += probs[i].n_energies;
+    if (plans[i].need_hl) {
+      hl_off[i] = hl_tot;
+      hl_tot += ((size_t)(probs[i].n_blocks - 1) * probs[i].block_size * probs[i].block_size * 16 + 255) & ~size_t(255);
+    }
+  }
+  // aux: energies | info | H lower blocks
+  const size_t eb = ((n_e_tot * 8) + 255) & ~size_t(255);
+  const size_t ib = ((n_e_tot * 4) + 255) & ~size_t(255);
+  ensure(c, &c->aux, &c->aux_bytes, eb + ib + hl_tot + 256);
+  double* d_E = (double*)c->aux;
+  int* d_info = (int*)(c->aux + eb);
+  char* d_hl = c->aux + eb + ib;
+  {
+    std::vector<double> hE(n_e_tot, 0.0);
+    for (int i = 0; i < np; ++i)
+      if (probs[i].kind == QTX_KIND_G)
+        std::memcpy(&hE[e_off[i]], probs[i].energies, sizeof(double) * probs[i].n_energies);
+    HIPCHK(c, hipMemcpyAsync(d_E, hE.data(), sizeof(double) * n_e_tot, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+
+  // lanes: the largest energy chunk whose workspace fits the budget
+  const size_t budget = budget_now(c);
+  struct Pend { int prob, e0, ec; size_t bytes; };
+  std::vector<Pend> pending;
+  size_t total = 0, largest = 0;
+  for (int i = 0; i < np; ++i) {
+    const Plan& q = plans[i];
+    if (lane_bytes(q, 1) > budget) {
+      c->err = "problem " + std::to_string(i) + ": one energy needs " +
+               std::to_string(lane_bytes(q, 1)) + " workspace bytes, budget is " + std::to_string(budget);
+      throw Fail{QTX_ERR_NOMEM};
+    }
+    int lo = 1, hi = q.ne;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (lane_bytes(q, mid) <= budget) lo = mid; else hi = mid - 1;
+    }
+    for (int e0 = 0; e0 < q.ne; e0 += lo) {
+      const int ec = std::min(lo, q.ne - e0);
+      const size_t by = lane_bytes(q, ec);
+      pending.push_back(Pend{i, e0, ec, by});
+      total += (by + 255) & ~size_t(255);
+      largest = std::max(largest, by);
+    }
+  }
+  const size_t cap = std::min(budget, total + 4096);
+  ensure(c, &c->ws, &c->ws_bytes, std::max(cap, largest + 4096));
+
+  // H lower blocks where absent: one prologue pass
+  {
+    std::vector<std::unique_ptr<Lane>> pro;
+    std::vector<Lane*> lp;
+    for (int i = 0; i < np; ++i)
+      if (plans[i].need_hl) {
+        pro.emplace_back(new Lane());
+        build_hl_lane(*pro.back(), probs[i], d_hl + hl_off[i]);
+        lp.push_back(pro.back().get());
+      }
+    if (!lp.empty()) run_lanes_to_end(c, lp);
+  }
+
+  // admission and merged execution
+  Regions reg(std::max(cap, largest + 4096));
+  std::vector<std::unique_ptr<Lane>> active;
+  size_t next = 0;
+  while (next < pending.size() || !active.empty()) {
+    // admit in order while the next lane fits
+    while (next < pending.size()) {
+      const Pend& pd = pending[next];
+      size_t off = 0;
+      if (!reg.alloc(pd.bytes, &off)) break;
+      std::unique_ptr<Lane> L(new Lane());
+      L->problem = pd.prob;
+      L->e0 = pd.e0;
+      L->ec = pd.ec;
+      L->ws_off = off;
+      L->ws_bytes = pd.bytes;
+      const qtx_rgf_problem& p = probs[pd.prob];
+      build_lane(*L, p, plans[pd.prob], c->ws + off, pd.e0, pd.ec, d_E + e_off[pd.prob],
+                 d_info + e_off[pd.prob], plans[pd.prob].need_hl ? d_hl + hl_off[pd.prob] : nullptr,
+                 c->tuner, c->stream);
+      active.push_back(std::move(L));
+      ++next;
+    }
+    if (active.empty()) {
+      c->err = "workspace admission stalled";
+      throw Fail{QTX_ERR_NOMEM};
+    }
+    std::vector<Lane*> lp;
+    for (auto& l : active) lp.push_back(l.get());
+    // with lanes waiting, stop the segment once a lane finishes so that its
+    // memory can be handed to the next lane
+    if (next < pending.size()) {
+      while (true) {
+        c->exe->build(lp, kArenaLimit);
+        bool fin = false;
+        for (Lane* l : lp) fin |= l->done();
+        if (c->exe->empty()) break;
+        c->exe->flush(prof, c->graphs, c->stats);
+        if (fin) break;
+      }
+    } else {
+      run_lanes_to_end(c, lp);
+    }
+    for (size_t i = 0; i < active.size();) {
+      if (active[i]->done()) {
+        reg.release(active[i]->ws_off, active[i]->ws_bytes);
+        active.erase(active.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+  }
+  std::vector<int> h_info(n_e_tot);
+  HIPCHK(c, hipMemcpyAsync(h_info.data(), d_info, sizeof(int) * n_e_tot, hipMemcpyDeviceToHost, c->stream));
+  c->exe->sync_and_collect(c->stats);
+  qtx_status worst = QTX_OK;
+  for (int i = 0; i < np; ++i) {
+    for (int e = 0; e < probs[i].n_energies; ++e) {
+      const int v = h_info[e_off[i] + e];
+      if (v != 0) {
+        probs[i].status = v > 0 ? QTX_ERR_SINGULAR : QTX_ERR_NOT_FINITE;
+        probs[i].fail_energy = e;
+        probs[i].fail_block = std::abs(v) - 1;
+        worst = QTX_ERR_PROBLEM;
+        break;
+      }
+    }
+  }
+  return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qtx_rgf_status_string(qtx_status s) {
+  switch (s) {
+    case QTX_OK: return "ok";
+    case QTX_ERR_INVALID_ARG: return "invalid argument";
+    case QTX_ERR_SINGULAR: return "singular diagonal block (zero pivot)";
+    case QTX_ERR_NOT_FINITE: return "non-finite pivot";
+    case QTX_ERR_NOMEM: return "out of device memory / workspace budget";
+    case QTX_ERR_HIP: return "HIP runtime error";
+    case QTX_ERR_BUSY: return "context busy";
+    case QTX_ERR_PROBLEM: return "at least one problem failed (see its status)";
+  }
+  return "unknown status";
+}
+
+const char* qtx_rgf_last_error(const qtx_rgf_ctx* c) { return c ? c->err.c_str() : ""; }
+
+qtx_status qtx_rgf_create(qtx_rgf_ctx** out, int device, uint64_t budget, void* stream,
+                          uint32_t flags) {
+  if (!out) return QTX_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (flags & ~QTX_FLAG_PROFILE) return QTX_ERR_INVALID_ARG;
+  if (device < 0) return QTX_ERR_INVALID_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) {
+    (void)hipGetLastError();
+    return QTX_ERR_HIP;
+  }
+  qtx_rgf_ctx* c = new (std::nothrow) qtx_rgf_ctx();
+  if (!c) return QTX_ERR_NOMEM;
+  c->device = device;
+  c->budget = budget;
+  c->flags = flags;
+  const char* g = std::getenv("QTX_GRAPHS");
+  c->graphs = !(g && g[0] == '0');
+  const char* t = std::getenv("QTX_TUNE");
+  c->tuner.set_enabled(!(t && t[0] == '0'));
+  if (hipSetDevice(device) != hipSuccess) { delete c; return QTX_ERR_HIP; }
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return QTX_ERR_HIP;
+    }
+    c->own_stream = true;
+  }
+  c->exe.reset(new Executor(c->stream));
+  *out = c;
+  return QTX_OK;
+}
+
+qtx_status qtx_rgf_destroy(qtx_rgf_ctx* c) {
+  if (!c) return QTX_ERR_INVALID_ARG;
+  if (c->busy) return QTX_ERR_BUSY;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  c->exe.reset();
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->aux) (void)hipFree(c->aux);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return QTX_OK;
+}
+
+qtx_status qtx_rgf_solve_batch(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int32_t np) {
+  if (!c) return QTX_ERR_INVALID_ARG;
+  if (c->busy) return QTX_ERR_BUSY;
+  c->err.clear();
+  if (np < 0 || (np > 0 && !probs)) { c->err = "bad problem array"; return QTX_ERR_INVALID_ARG; }
+  for (int i = 0; i < np; ++i) {
+    const std::string m = validate(probs[i]);
+    if (!m.empty()) { c->err = "problem " + std::to_string(i) + ": " + m; return QTX_ERR_INVALID_ARG; }
+  }
+  if (np == 0) return QTX_OK;
+  BusyGuard g(c);
+  try {
+    HIPCHK(c, hipSetDevice(c->device));
+    return solve(c, probs, np);
+  } catch (const Fail& f) {
+    (void)hipStreamSynchronize(c->stream);
+    try { c->exe->sync_and_collect(c->stats); } catch (...) {}
+    return (qtx_status)f.st;
+  } catch (...) {
+    c->err = "internal error";
+    return QTX_ERR_HIP;
+  }
+}
+
+double qtx_rgf_flops_per_energy(int32_t kind, int32_t n, int32_t b, int32_t n_rhs,
+                                int32_t bt_rhs, int32_t want_wr) {
+  if (n < 1 || b < 1 || n_rhs < 0) return 0.0;
+  const double g = 8.0 * (double)b * b * b;
+  const int per_fwd = 4 + (bt_rhs ? 1 : 0);
+  const int per_bwd = 4 + (bt_rhs ? 3 : 0);
+  double cnt = 1 + 2.0 * n_rhs + (n - 1.0) * (3 + per_fwd * n_rhs) + (n - 1.0) * (6 + per_bwd * n_rhs);
+  if (kind == QTX_KIND_W) {
+    // products of trunc(V P^R) and of the diagonal and upper blocks of
+    // trunc(V P^s V^dag), both with block-tridiagonal P
+    auto nprod = [&](int i, int j) {
+      int c = 0;
+      for (int k = std::max(0, i - 1); k <= std::min(n - 1, i + 1); ++k)
+        if (std::abs(k - j) <= 1) ++c;
+      return c;
+    };
+    double lhs = 0, rhs = 0;
+    for (int i = 0; i < n; ++i) {
+      for (int j = i - 1; j <= i + 1; ++j)
+        if (j >= 0 && j < n) lhs += nprod(i, j);
+      for (int k = i - 1; k <= i + 2; ++k)
+        if (k >= 0 && k < n) rhs += nprod(i, k);
+      for (int j = i; j <= i + 1; ++j) {
+        if (j >= n) continue;
+        for (int k = i - 1; k <= i + 2; ++k)
+          if (k >= 0 && k < n && std::abs(k - j) <= 1) rhs += 1;
+      }
+    }
+    cnt += lhs + n_rhs * rhs;
+    if (want_wr) cnt += 3.0 * n - 2.0;          // (X^R V)_ii: 3 products, 1 at the ends
+  }
+  return cnt * g;
+}
+
+qtx_status qtx_rgf_kernel_stats(qtx_rgf_ctx* c, int32_t cls, int64_t* launches, double* ms,
+                                double* flops, double* bytes) {
+  if (!c || cls < 0 || cls >= kNumClasses) return QTX_ERR_INVALID_ARG;
+  const KStat& s = c->stats[cls];
+  if (launches) *launches = s.launches;
+  if (ms) *ms = s.ms;
+  if (flops) *flops = s.flops;
+  if (bytes) *bytes = s.bytes;
+  return QTX_OK;
+}
+
+qtx_status qtx_rgf_reset_stats(qtx_rgf_ctx* c) {
+  if (!c) return QTX_ERR_INVALID_ARG;
+  for (auto& s : c->stats) s = KStat();
+  return QTX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+qtx_status gemm_abi(bool fp32, qtx_rgf_ctx* c, char opa, char opb, int32_t m, int32_t n,
+                    int32_t k, double ar, double ai, const void* A, int64_t lda, int64_t sA,
+                    const void* B, int64_t ldb, int64_t sB, double br, double bi,
+                    const void* C, int64_t ldc, int64_t sC, void* D, int64_t ldd, int64_t sD,
+                    int32_t batch) {
+  if (!c) return QTX_ERR_INVALID_ARG;
+  if (c->busy) return QTX_ERR_BUSY;
+  if ((opa != 'N' && opa != 'C') || (opb != 'N' && opb != 'C') || m < 0 || n < 0 || k < 0 ||
+      batch < 0 || !A || !B || !D || (!C && (br != 0.0 || bi != 0.0)))
+    return QTX_ERR_INVALID_ARG;
+  const int64_t colsA = opa == 'N' ? k : m;
+  const int64_t colsB = opb == 'N' ? n : k;
+  if (lda < std::max<int64_t>(1, colsA) || ldb < std::max<int64_t>(1, colsB) ||
+      ldd < std::max<int64_t>(1, n) || (C && ldc < std::max<int64_t>(1, n)))
+    return QTX_ERR_INVALID_ARG;
+  if (m == 0 || n == 0 || batch == 0) return QTX_OK;
+  BusyGuard g(c);
+  try {
+    HIPCHK(c, hipSetDevice(c->device));
+    Lane L;
+    GemmDesc d{};
+    d.A = A; d.sA = sA; d.lda = lda;
+    d.B = B; d.sB = sB; d.ldb = ldb;
+    d.C = C; d.sC = sC; d.ldc = C ? ldc : ldd;
+    d.D = D; d.sD = sD; d.ldd = ldd;
+    d.alpha = zc{ar, ai};
+    d.beta = C ? zc{br, bi} : zc{0.0, 0.0};
+    d.M = m; d.N = n; d.K = k;
+    d.batch = batch; d.batch2 = 1;
+    L.gd.push_back(d);
+    Op o;
+    o.k = OpK::Gemm;
+    o.opa = opa; o.opb = opb; o.fp32 = fp32;
+    o.cfg = c->tuner.cfg(m, n, k, fp32, c->stream);
+    o.first = 0; o.count = 1;
+    o.flops = 8.0 * m * n * (double)k * batch;
+    o.bytes = 16.0 * ((double)m * k + (double)k * n + (C ? 2.0 : 1.0) * m * n) * batch;
+    L.ops.push_back(o);
+    std::vector<Lane*> lp{&L};
+    run_lanes_to_end(c, lp);
+    c->exe->sync_and_collect(c->stats);
+  } catch (const Fail& f) {
+    return (qtx_status)f.st;
+  }
+  return QTX_OK;
+}
+}  // namespace
+
+extern "C" {
+
+qtx_status qtx_rgf_zgemm(qtx_rgf_ctx* c, char opa, char opb, int32_t m, int32_t n, int32_t k,
+                         double ar, double ai, const void* A, int64_t lda, int64_t sA,
+                         const void* B, int64_t ldb, int64_t sB, double br, double bi,
+                         const void* C, int64_t ldc, int64_t sC, void* D, int64_t ldd,
+                         int64_t sD, int32_t batch) {
+  return gemm_abi(false, c, opa, opb, m, n, k, ar, ai, A, lda, sA, B, ldb, sB, br, bi, C,
+                  ldc, sC, D, ldd, sD, batch);
+}
+
+qtx_status qtx_rgf_cgemm(qtx_rgf_ctx* c, char opa, char opb, int32_t m, int32_t n, int32_t k,
+                         double ar, double ai, const void* A, int64_t lda, int64_t sA,
+                         const void* B, int64_t ldb, int64_t sB, double br, double bi,
+                         const void* C, int64_t ldc, int64_t sC, void* D, int64_t ldd,
+                         int64_t sD, int32_t batch) {
+  return gemm_abi(true, c, opa, opb, m, n, k, ar, ai, A, lda, sA, B, ldb, sB, br, bi, C,
+                  ldc, sC, D, ldd, sD, batch);
+}
+
+qtx_status qtx_rgf_zinv(qtx_rgf_ctx* c, int32_t b, void* A, void* X, int32_t* info,
+                        int32_t batch) {
+  if (!c || b < 1 || b > 1024 || !A || !X || batch < 0 || A == X) return QTX_ERR_INVALID_ARG;
+  if (c->busy) return QTX_ERR_BUSY;
+  if (batch == 0) return QTX_OK;
+  BusyGuard g(c);
+  void* work = nullptr;
+  try {
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t pan = (size_t)batch * b * kPanel * 16;
+    const size_t ints = (size_t)batch * b * 4;
+    HIPCHK(c, hipMalloc(&work, 2 * pan + 2 * ints + 1024));
+    Lane L;
+    InvDesc d{};
+    d.S = A; d.sS = (long long)b * b;
+    d.X = X; d.sX = (long long)b * b;
+    d.panel = work;
+    d.brow = (char*)work + pan;
+    d.perm = (int*)((char*)work + 2 * pan);
+    d.used = (int*)((char*)work + 2 * pan + ints);
+    d.info = info; d.code = 0; d.reset_info = 1;
+    d.b = b; d.batch = batch;
+    L.id.push_back(d);
+    Op o;
+    o.k = OpK::Inv;
+    o.first = 0; o.count = 1;
+    o.flops = 8.0 * (double)b * b * b * batch;
+    L.ops.push_back(o);
+    std::vector<Lane*> lp{&L};
+    run_lanes_to_end(c, lp);
+    c->exe->sync_and_collect(c->stats);
+    HIPCHK(c, hipFree(work));
+  } catch (const Fail& f) {
+    if (work) (void)hipFree(work);
+    return (qtx_status)f.st;
+  }
+  return QTX_OK;
+}
+
+}  // extern "C"

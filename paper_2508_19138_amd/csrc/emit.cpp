@@ -1,0 +1,598 @@
+// The RGF recursion of one lane as a list of block operations
+// (arXiv 2508.19138, Sec. 3.2.3, Eqs. forward-pass / backward-pass; system
+// assembly of Sec. 3.2.2 and Table "quantities").
+//
+// Notation: x_i = x^R_i (left-connected), xs_i = x^s_i, X_i = X^R_i,
+// U_i = Mt_{i,i+1}, L_i = Mt_{i+1,i}.  The right-hand sides are
+// anti-Hermitian, so each of  y - y^dag,  Y - Y^dag  and  Z - Z^dag  needs a
+// single product, and the lower blocks of X^s are -upper^dagger.
+#include "emit.h"
+
+#include <algorithm>
+#include <initializer_list>
+
+namespace qtx {
+namespace {
+
+const zc kOne{1.0, 0.0}, kZero{0.0, 0.0}, kMinus{-1.0, 0.0};
+inline zc rs(double v) { return zc{v, 0.0}; }
+
+// A block-indexed operand: block i of energy e (relative to the view's
+// base) starts at p + e * es + i * bs (complex elements).
+struct View {
+  const double2* p = nullptr;
+  long long es = 0, bs = 0;
+  bool ok() const { return p != nullptr; }
+  const double2* at(long long i) const { return p + i * bs; }
+  double2* w(long long i) const { return const_cast<double2*>(p + i * bs); }
+};
+
+struct Opnd {
+  View v;
+  long long i;
+};
+
+struct Term {            // D = alpha * A B + beta * C, batched over energies
+  Opnd A, B;
+  const View* C;         // null = no C
+  long long ic;
+  View D;
+  long long id;
+  zc alpha, beta;
+};
+
+class Emitter {
+ public:
+  Emitter(Lane& L, Tuner& T, hipStream_t s, int b, int ec)
+      : L_(L), T_(T), s_(s), b_(b), ec_(ec), blk_((long long)b * b) {}
+  void set_fp32(bool on) { fp32_ = on; }
+
+  // One operation: the terms are independent products with the same
+  // operand ops; `nb2` consecutive blocks (each view's bs) form a second
+  // batch index.
+  void gemm(char opa, char opb, std::initializer_list<Term> terms, int nb2 = 1) {
+    Op o;
+    o.k = OpK::Gemm;
+    o.opa = opa; o.opb = opb; o.fp32 = fp32_;
+    o.cfg = T_.cfg(b_, b_, b_, fp32_, s_);
+    o.first = (int)L_.gd.size();
+    for (const Term& t : terms) {
+      GemmDesc g{};
+      g.A = t.A.v.at(t.A.i); g.sA = t.A.v.es; g.tA = t.A.v.bs;
+      g.B = t.B.v.at(t.B.i); g.sB = t.B.v.es; g.tB = t.B.v.bs;
+      if (t.C) { g.C = t.C->at(t.ic); g.sC = t.C->es; g.tC = t.C->bs; }
+      g.D = t.D.w(t.id); g.sD = t.D.es; g.tD = t.D.bs;
+      g.lda = g.ldb = g.ldc = g.ldd = b_;
+      g.alpha = t.alpha;
+      g.beta = t.C ? t.beta : kZero;
+      g.M = g.N = g.K = b_;
+      g.batch = ec_;
+      g.batch2 = nb2;
+      L_.gd.push_back(g);
+      o.flops += 8.0 * blk_ * b_ * (double)ec_ * nb2;
+      o.bytes += 16.0 * blk_ * (t.C ? 4.0 : 3.0) * ec_ * nb2;
+    }
+    o.count = (int)L_.gd.size() - o.first;
+    L_.ops.push_back(o);
+  }
+
+  void inverse(const View& S, long long is, const View& X, long long ix, void* panel,
+               void* brow, int* perm, int* used, int* info, int code, bool reset) {
+    Op o;
+    o.k = OpK::Inv;
+    o.first = (int)L_.id.size();
+    InvDesc d{};
+    d.S = S.w(is); d.sS = S.es;
+    d.X = X.w(ix); d.sX = X.es;
+    d.panel = panel; d.brow = brow; d.perm = perm; d.used = used;
+    d.info = info; d.code = code; d.reset_info = reset ? 1 : 0;
+    d.b = b_; d.batch = ec_;
+    L_.id.push_back(d);
+    o.count = 1;
+    o.flops = 8.0 * blk_ * b_ * ec_;
+    L_.ops.push_back(o);
+  }
+
+  void lincomb(LinCombDesc a) {
+    Op o;
+    o.k = OpK::Lin;
+    o.first = (int)L_.ld.size();
+    a.b = b_;
+    a.batch = ec_;
+    L_.ld.push_back(a);
+    o.count = 1;
+    o.bytes = 16.0 * blk_ * ec_ * (1 + (a.src[0] != nullptr) + (a.src[1] != nullptr) + (a.src[2] != nullptr));
+    L_.ops.push_back(o);
+  }
+
+  // D(e) = C(e) + z Z(e) + g Z(e)^dag, for up to two independent targets.
+  void antiherm2(int count, const View* D, const long long* id, const View* const* C,
+                 const long long* ic, const View* Z, const long long* iz, zc z, zc g) {
+    Op o;
+    o.k = OpK::Trans;
+    o.first = (int)L_.td.size();
+    for (int q = 0; q < count; ++q) {
+      TransDesc t{};
+      t.C = C[q] ? C[q]->at(ic[q]) : nullptr; t.sC = C[q] ? C[q]->es : 0;
+      t.Z = Z[q].at(iz[q]); t.sZ = Z[q].es;
+      t.D = D[q].w(id[q]); t.sD = D[q].es;
+      t.a = C[q] ? kOne : kZero; t.z = z; t.g = g;
+      t.b = b_; t.batch = ec_;
+      L_.td.push_back(t);
+      o.bytes += 16.0 * blk_ * ec_ * (2 + (C[q] != nullptr));
+    }
+    o.count = count;
+    L_.ops.push_back(o);
+  }
+  void antiherm(const View& D, long long id, const View* C, long long ic,
+                const View& Z, long long iz, zc z, zc g) {
+    const View* Cs[1] = {C};
+    antiherm2(1, &D, &id, Cs, &ic, &Z, &iz, z, g);
+  }
+
+  void copy(const View& D, long long id, const View& S, long long is) {
+    LinCombDesc a{};
+    a.src[0] = S.at(is); a.sSrc[0] = S.es; a.c[0] = kOne;
+    a.D = D.w(id); a.sD = D.es;
+    lincomb(a);
+  }
+
+  long long blk() const { return blk_; }
+
+ private:
+  Lane& L_;
+  Tuner& T_;
+  hipStream_t s_;
+  int b_, ec_;
+  long long blk_;
+  bool fp32_ = false;
+};
+
+struct Rhs {
+  View Bd, Bu;             // B^s diag, upper (Bu may be empty)
+  View Xd, Xu, Xl;         // outputs (Xl may be empty)
+};
+
+struct Core {
+  int n = 0;
+  View U, L;               // U_i = su * U[i], L_i = sl * L[i]
+  double su = 1.0, sl = 1.0;
+  std::vector<Rhs> rhs;
+  View XRd, XRu, XRl;
+  View xR;                 // workspace [n] per energy
+  View tS, tF, tP, tM, tR; // workspace, one block per energy
+  View tG[2], tW[2], tY[2];
+  void *panel = nullptr, *brow = nullptr;
+  int *perm = nullptr, *used = nullptr, *info = nullptr;
+};
+
+// Forward and backward passes, given a callback that writes Mt_ii into tS.
+template <class PrepDiag>
+void run_core(Emitter& s, const Core& k, PrepDiag prep_diag) {
+  const int n = k.n;
+  const int nr = (int)k.rhs.size();
+  const zc su = rs(k.su), sl = rs(k.sl);
+  auto inv = [&](int i) {
+    s.inverse(k.tS, 0, k.xR, i, k.panel, k.brow, k.perm, k.used, k.info, i + 1, i == 0);
+  };
+
+  // ---- forward pass ----------------------------------------------------
+  prep_diag(0);
+  inv(0);
+  if (nr == 2) {
+    s.gemm('N', 'N', {Term{{k.xR, 0}, {k.rhs[0].Bd, 0}, nullptr, 0, k.tG[0], 0, kOne, kZero},
+                      Term{{k.xR, 0}, {k.rhs[1].Bd, 0}, nullptr, 0, k.tG[1], 0, kOne, kZero}});
+    s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.xR, 0}, nullptr, 0, k.rhs[0].Xd, 0, kOne, kZero},
+                      Term{{k.tG[1], 0}, {k.xR, 0}, nullptr, 0, k.rhs[1].Xd, 0, kOne, kZero}});
+  } else if (nr == 1) {
+    s.gemm('N', 'N', {Term{{k.xR, 0}, {k.rhs[0].Bd, 0}, nullptr, 0, k.tG[0], 0, kOne, kZero}});
+    s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.xR, 0}, nullptr, 0, k.rhs[0].Xd, 0, kOne, kZero}});
+  }
+  for (int i = 1; i < n; ++i) {
+    // F = L_{i-1} x_{i-1};  Mt_ii - F U_{i-1}  -> inverse -> x_i
+    s.gemm('N', 'N', {Term{{k.L, i - 1}, {k.xR, i - 1}, nullptr, 0, k.tF, 0, sl, kZero}});
+    prep_diag(i);
+    s.gemm('N', 'N', {Term{{k.tF, 0}, {k.U, i - 1}, &k.tS, 0, k.tS, 0, rs(-k.su), kOne}});
+    inv(i);
+    if (nr == 0) continue;
+    // W = B_ii + L xs_{i-1} L^dag - y + y^dag;  xs_i = x_i W x_i^dag
+    if (nr == 2) {
+      s.gemm('N', 'N', {Term{{k.L, i - 1}, {k.rhs[0].Xd, i - 1}, nullptr, 0, k.tG[0], 0, sl, kZero},
+                        Term{{k.L, i - 1}, {k.rhs[1].Xd, i - 1}, nullptr, 0, k.tG[1], 0, sl, kZero}});
+      s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.L, i - 1}, &k.rhs[0].Bd, i, k.tW[0], 0, sl, kOne},
+                        Term{{k.tG[1], 0}, {k.L, i - 1}, &k.rhs[1].Bd, i, k.tW[1], 0, sl, kOne}});
+    } else {
+      s.gemm('N', 'N', {Term{{k.L, i - 1}, {k.rhs[0].Xd, i - 1}, nullptr, 0, k.tG[0], 0, sl, kZero}});
+      s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.L, i - 1}, &k.rhs[0].Bd, i, k.tW[0], 0, sl, kOne}});
+    }
+    for (int r = 0; r < nr; ++r) {
+      if (!k.rhs[r].Bu.ok()) continue;
+      s.gemm('N', 'N', {Term{{k.tF, 0}, {k.rhs[r].Bu, i - 1}, nullptr, 0, k.tY[r], 0, kOne, kZero}});
+      s.antiherm(k.tW[r], 0, &k.tW[r], 0, k.tY[r], 0, kMinus, kOne);
+    }
+    if (nr == 2) {
+      s.gemm('N', 'N', {Term{{k.xR, i}, {k.tW[0], 0}, nullptr, 0, k.tG[0], 0, kOne, kZero},
+                        Term{{k.xR, i}, {k.tW[1], 0}, nullptr, 0, k.tG[1], 0, kOne, kZero}});
+      s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.xR, i}, nullptr, 0, k.rhs[0].Xd, i, kOne, kZero},
+                        Term{{k.tG[1], 0}, {k.xR, i}, nullptr, 0, k.rhs[1].Xd, i, kOne, kZero}});
+    } else {
+      s.gemm('N', 'N', {Term{{k.xR, i}, {k.tW[0], 0}, nullptr, 0, k.tG[0], 0, kOne, kZero}});
+      s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.xR, i}, nullptr, 0, k.rhs[0].Xd, i, kOne, kZero}});
+    }
+  }
+
+  // ---- backward pass ---------------------------------------------------
+  s.copy(k.XRd, n - 1, k.xR, n - 1);
+  for (int i = n - 2; i >= 0; --i) {
+    // P = x_i U_i,  M = X_{i+1} L_i
+    s.gemm('N', 'N', {Term{{k.xR, i}, {k.U, i}, nullptr, 0, k.tP, 0, su, kZero},
+                      Term{{k.XRd, i + 1}, {k.L, i}, nullptr, 0, k.tM, 0, sl, kZero}});
+    // X_{i,i+1} = -P X_{i+1} (= -Q),  X_{i+1,i} = -M x_i
+    s.gemm('N', 'N', {Term{{k.tP, 0}, {k.XRd, i + 1}, nullptr, 0, k.XRu, i, kMinus, kZero},
+                      Term{{k.tM, 0}, {k.xR, i}, nullptr, 0, k.XRl, i, kMinus, kZero}});
+    // R = Q L_i = -X_{i,i+1} L_i
+    s.gemm('N', 'N', {Term{{k.XRu, i}, {k.L, i}, nullptr, 0, k.tR, 0, rs(-k.sl), kZero}});
+    // X_i = x_i + R x_i
+    s.gemm('N', 'N', {Term{{k.tR, 0}, {k.xR, i}, &k.xR, i, k.XRd, i, kOne, kOne}});
+    if (nr == 0) continue;
+    if (nr == 2) {
+      // T1 = P X^s_{i+1},  Z = R xs_i
+      s.gemm('N', 'N', {Term{{k.tP, 0}, {k.rhs[0].Xd, i + 1}, nullptr, 0, k.tG[0], 0, kOne, kZero},
+                        Term{{k.tP, 0}, {k.rhs[1].Xd, i + 1}, nullptr, 0, k.tG[1], 0, kOne, kZero},
+                        Term{{k.tR, 0}, {k.rhs[0].Xd, i}, nullptr, 0, k.tW[0], 0, kOne, kZero},
+                        Term{{k.tR, 0}, {k.rhs[1].Xd, i}, nullptr, 0, k.tW[1], 0, kOne, kZero}});
+      // X^s_{i,i+1} = -T1 - xs_i M^dag
+      s.gemm('N', 'C', {Term{{k.rhs[0].Xd, i}, {k.tM, 0}, &k.tG[0], 0, k.rhs[0].Xu, i, kMinus, kMinus},
+                        Term{{k.rhs[1].Xd, i}, {k.tM, 0}, &k.tG[1], 0, k.rhs[1].Xu, i, kMinus, kMinus}});
+      // X^s_ii = xs_i + T1 P^dag (+ Z - Z^dag below)
+      s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.tP, 0}, &k.rhs[0].Xd, i, k.rhs[0].Xd, i, kOne, kOne},
+                        Term{{k.tG[1], 0}, {k.tP, 0}, &k.rhs[1].Xd, i, k.rhs[1].Xd, i, kOne, kOne}});
+      const View D2[2] = {k.rhs[0].Xd, k.rhs[1].Xd};
+      const long long ii[2] = {i, i}, zz[2] = {0, 0};
+      const View* C2[2] = {&k.rhs[0].Xd, &k.rhs[1].Xd};
+      const View Z2[2] = {k.tW[0], k.tW[1]};
+      s.antiherm2(2, D2, ii, C2, ii, Z2, zz, kOne, kMinus);
+    } else {
+      s.gemm('N', 'N', {Term{{k.tP, 0}, {k.rhs[0].Xd, i + 1}, nullptr, 0, k.tG[0], 0, kOne, kZero},
+                        Term{{k.tR, 0}, {k.rhs[0].Xd, i}, nullptr, 0, k.tW[0], 0, kOne, kZero}});
+      s.gemm('N', 'C', {Term{{k.rhs[0].Xd, i}, {k.tM, 0}, &k.tG[0], 0, k.rhs[0].Xu, i, kMinus, kMinus}});
+      s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.tP, 0}, &k.rhs[0].Xd, i, k.rhs[0].Xd, i, kOne, kOne}});
+      s.antiherm(k.rhs[0].Xd, i, &k.rhs[0].Xd, i, k.tW[0], 0, kOne, kMinus);
+    }
+    for (int r = 0; r < nr; ++r) {
+      const Rhs& h = k.rhs[r];
+      if (h.Bu.ok()) {
+        // V = x_i B_{i,i+1};  X^s_{i,i+1} += V X_{i+1}^dag;  X^s_ii -= Y - Y^dag
+        // with Y = V Q^dag = -V X_{i,i+1}^dag
+        s.gemm('N', 'N', {Term{{k.xR, i}, {h.Bu, i}, nullptr, 0, k.tY[r], 0, kOne, kZero}});
+        s.gemm('N', 'C', {Term{{k.tY[r], 0}, {k.XRd, i + 1}, &h.Xu, i, h.Xu, i, kOne, kOne}});
+        s.gemm('N', 'C', {Term{{k.tY[r], 0}, {k.XRu, i}, nullptr, 0, k.tW[r], 0, kOne, kZero}});
+        s.antiherm(h.Xd, i, &h.Xd, i, k.tW[r], 0, kOne, kMinus);
+      }
+    }
+    // X^s lower = -(X^s upper)^dag
+    int cnt = 0;
+    View D2[2], Z2[2];
+    long long ii[2] = {i, i};
+    const View* C2[2] = {nullptr, nullptr};
+    for (int r = 0; r < nr; ++r)
+      if (k.rhs[r].Xl.ok()) { D2[cnt] = k.rhs[r].Xl; Z2[cnt] = k.rhs[r].Xu; ++cnt; }
+    if (cnt) s.antiherm2(cnt, D2, ii, C2, ii, Z2, ii, kZero, kMinus);
+  }
+}
+
+// ---------------------------------------------------------------- W setup --
+
+struct WOps {
+  View Vd, Vu, Vl;        // Vl empty -> use Vu with op C
+  View Prd, Pru, Prl;     // per energy
+  View Psd[2], Psu[2];    // per energy
+  View Ad, Au, Al;        // outputs (workspace)
+  View Bd[2], Bu[2];      // outputs (workspace)
+  View Tm1, T0, Tp1, Tp2; // (V P^s)_{i,i-1}, _{i,i}, _{i,i+1}, _{i,i+2}
+};
+
+// Mt = I - trunc(V P^R) and B^s = trunc(V P^s V^dag); V lower = V upper^dag
+// when absent, P^s lower = -(P^s upper)^dag.
+void w_assemble(Emitter& s, const WOps& w, int n, int nr) {
+  for (int i = 0; i < n; ++i) {
+    LinCombDesc a{};
+    a.idc0 = kOne;
+    a.D = w.Ad.w(i); a.sD = w.Ad.es;
+    s.lincomb(a);
+  }
+  const bool vl = w.Vl.ok();
+  const char opVl = vl ? 'N' : 'C';            // V_{i+1,i} as a stored operand
+  const View& VL = vl ? w.Vl : w.Vu;
+  s.gemm('N', 'N', {Term{{w.Vd, 0}, {w.Prd, 0}, &w.Ad, 0, w.Ad, 0, kMinus, kOne}}, n);
+  if (n > 1) {
+    if (w.Pru.ok())   // Ad[i] -= V_{i,i-1} P_{i-1,i},  i >= 1
+      s.gemm(opVl, 'N', {Term{{VL, 0}, {w.Pru, 0}, &w.Ad, 1, w.Ad, 1, kMinus, kOne}}, n - 1);
+    if (w.Prl.ok())   // Ad[i] -= V_{i,i+1} P_{i+1,i},  i <= n-2
+      s.gemm('N', 'N', {Term{{w.Vu, 0}, {w.Prl, 0}, &w.Ad, 0, w.Ad, 0, kMinus, kOne}}, n - 1);
+    // Au[i] = -(V_ii P_{i,i+1} + V_{i,i+1} P_{i+1,i+1})
+    if (w.Pru.ok()) {
+      s.gemm('N', 'N', {Term{{w.Vd, 0}, {w.Pru, 0}, nullptr, 0, w.Au, 0, kMinus, kZero}}, n - 1);
+      s.gemm('N', 'N', {Term{{w.Vu, 0}, {w.Prd, 1}, &w.Au, 0, w.Au, 0, kMinus, kOne}}, n - 1);
+    } else {
+      s.gemm('N', 'N', {Term{{w.Vu, 0}, {w.Prd, 1}, nullptr, 0, w.Au, 0, kMinus, kZero}}, n - 1);
+    }
+    // Al[i] = -(V_{i+1,i} P_ii + V_{i+1,i+1} P_{i+1,i})
+    s.gemm(opVl, 'N', {Term{{VL, 0}, {w.Prd, 0}, nullptr, 0, w.Al, 0, kMinus, kZero}}, n - 1);
+    if (w.Prl.ok())
+      s.gemm('N', 'N', {Term{{w.Vd, 1}, {w.Prl, 0}, &w.Al, 0, w.Al, 0, kMinus, kOne}}, n - 1);
+  }
+  for (int r = 0; r < nr; ++r) {
+    const View& Pd = w.Psd[r];
+    const View& Pu = w.Psu[r];
+    const bool pu = Pu.ok() && n > 1;
+    // T0[i] = V_ii P_ii (+ V_{i,i-1} P_{i-1,i} + V_{i,i+1} P_{i+1,i})
+    s.gemm('N', 'N', {Term{{w.Vd, 0}, {Pd, 0}, nullptr, 0, w.T0, 0, kOne, kZero}}, n);
+    if (n > 1) {
+      if (pu) {
+        s.gemm(opVl, 'N', {Term{{VL, 0}, {Pu, 0}, &w.T0, 1, w.T0, 1, kOne, kOne}}, n - 1);
+        s.gemm('N', 'C', {Term{{w.Vu, 0}, {Pu, 0}, &w.T0, 0, w.T0, 0, kMinus, kOne}}, n - 1);
+      }
+      // Tm1[i] = V_{i,i-1} P_{i-1,i-1} + V_ii P_{i,i-1},  i >= 1
+      s.gemm(opVl, 'N', {Term{{VL, 0}, {Pd, 0}, nullptr, 0, w.Tm1, 1, kOne, kZero}}, n - 1);
+      if (pu) s.gemm('N', 'C', {Term{{w.Vd, 1}, {Pu, 0}, &w.Tm1, 1, w.Tm1, 1, kMinus, kOne}}, n - 1);
+      // Tp1[i] = V_ii P_{i,i+1} + V_{i,i+1} P_{i+1,i+1},  i <= n-2
+      s.gemm('N', 'N', {Term{{w.Vu, 0}, {Pd, 1}, nullptr, 0, w.Tp1, 0, kOne, kZero}}, n - 1);
+      if (pu) s.gemm('N', 'N', {Term{{w.Vd, 0}, {Pu, 0}, &w.Tp1, 0, w.Tp1, 0, kOne, kOne}}, n - 1);
+      // Tp2[i] = V_{i,i+1} P_{i+1,i+2},  i <= n-3
+      if (pu && n > 2) s.gemm('N', 'N', {Term{{w.Vu, 0}, {Pu, 1}, nullptr, 0, w.Tp2, 0, kOne, kZero}}, n - 2);
+    }
+    // B_ii = T0 V_ii^dag + Tm1 V_{i,i-1}^dag + Tp1 V_{i,i+1}^dag
+    s.gemm('N', 'C', {Term{{w.T0, 0}, {w.Vd, 0}, nullptr, 0, w.Bd[r], 0, kOne, kZero}}, n);
+    if (n > 1) {
+      s.gemm('N', vl ? 'C' : 'N', {Term{{w.Tm1, 1}, {VL, 0}, &w.Bd[r], 1, w.Bd[r], 1, kOne, kOne}}, n - 1);
+      s.gemm('N', 'C', {Term{{w.Tp1, 0}, {w.Vu, 0}, &w.Bd[r], 0, w.Bd[r], 0, kOne, kOne}}, n - 1);
+      // B_{i,i+1} = T0 V_{i+1,i}^dag + Tp1 V_{i+1,i+1}^dag + Tp2 V_{i+1,i+2}^dag
+      s.gemm('N', vl ? 'C' : 'N', {Term{{w.T0, 0}, {VL, 0}, nullptr, 0, w.Bu[r], 0, kOne, kZero}}, n - 1);
+      s.gemm('N', 'C', {Term{{w.Tp1, 0}, {w.Vd, 1}, &w.Bu[r], 0, w.Bu[r], 0, kOne, kOne}}, n - 1);
+      if (pu && n > 2)
+        s.gemm('N', 'C', {Term{{w.Tp2, 0}, {w.Vu, 1}, &w.Bu[r], 0, w.Bu[r], 0, kOne, kOne}}, n - 2);
+    }
+  }
+}
+
+// ------------------------------------------------------------- workspace --
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  char* take(size_t bytes) {
+    const size_t o = (off + 255) & ~size_t(255);
+    off = o + bytes;
+    return base ? base + o : nullptr;
+  }
+};
+
+View in_view(const void* p, long long es, long long bs) {
+  View v;
+  v.p = (const double2*)p;
+  v.es = es;
+  v.bs = bs;
+  return v;
+}
+
+// The lane's workspace layout; with ws == nullptr only the size is computed.
+struct Layout {
+  View xR, tS, tF, tP, tM, tR, tG[2], tW[2], tY[2], Uw, Lw;
+  View Ad, Bd[2], Bu[2], Tm1, T0, Tp1, Tp2;
+  void *panel, *brow;
+  int *perm, *used;
+  size_t bytes;
+};
+
+Layout carve_layout(const Plan& q, int ec, char* ws) {
+  Layout L{};
+  Carve cv{ws};
+  const int n = q.n, b = q.b;
+  const long long blk = (long long)b * b;
+  auto blocks = [&](long long nblk) {
+    View v;
+    v.p = (const double2*)cv.take((size_t)ec * nblk * blk * 16);
+    v.es = nblk * blk;
+    v.bs = blk;
+    return v;
+  };
+  L.xR = blocks(n);
+  L.tS = blocks(1); L.tF = blocks(1); L.tP = blocks(1); L.tM = blocks(1); L.tR = blocks(1);
+  for (int r = 0; r < q.nr; ++r) {
+    L.tG[r] = blocks(1);
+    L.tW[r] = blocks(1);
+    if (q.bt_rhs[r]) L.tY[r] = blocks(1);
+  }
+  if (q.general_ul && n > 1) { L.Uw = blocks(n - 1); L.Lw = blocks(n - 1); }
+  L.panel = cv.take((size_t)ec * b * kPanel * 16);
+  L.brow = cv.take((size_t)ec * b * kPanel * 16);
+  L.perm = (int*)cv.take((size_t)ec * b * 4);
+  L.used = (int*)cv.take((size_t)ec * b * 4);
+  if (q.is_w) {
+    L.Ad = blocks(n);
+    for (int r = 0; r < q.nr; ++r) {
+      L.Bd[r] = blocks(n);
+      if (n > 1) L.Bu[r] = blocks(n - 1);
+    }
+    if (q.nr) { L.Tm1 = blocks(n); L.T0 = blocks(n); L.Tp1 = blocks(n); L.Tp2 = blocks(n); }
+  }
+  L.bytes = cv.off + 256;
+  return L;
+}
+
+}  // namespace
+
+Plan make_plan(const qtx_rgf_problem& p) {
+  Plan q{};
+  q.n = p.n_blocks; q.b = p.block_size; q.ne = p.n_energies;
+  q.is_w = p.kind == QTX_KIND_W;
+  q.fp32 = p.precision == QTX_MIXED;
+  q.nr = (p.XL.diag ? 1 : 0) + (p.XG.diag ? 1 : 0);
+  const int n = q.n;
+  int ri = 0;
+  if (!q.is_w) {
+    q.general_ul = (p.S.diag && (p.S.upper || p.S.lower)) || p.sigma_r.upper || p.sigma_r.lower;
+    q.need_hl = (n > 1) && !p.H.lower;
+    if (p.XL.diag) q.bt_rhs[ri++] = p.sigma_l.upper != nullptr && n > 1;
+    if (p.XG.diag) q.bt_rhs[ri++] = p.sigma_g.upper != nullptr && n > 1;
+  } else {
+    q.general_ul = true;
+    for (int r = 0; r < q.nr; ++r) q.bt_rhs[r] = n > 1;
+  }
+  return q;
+}
+
+size_t lane_bytes(const Plan& q, int ec) { return carve_layout(q, ec, nullptr).bytes; }
+
+void build_hl_lane(Lane& lane, const qtx_rgf_problem& p, void* Hl) {
+  const int n = p.n_blocks, b = p.block_size;
+  const long long blk = (long long)b * b;
+  Op o;
+  o.k = OpK::Trans;
+  o.first = (int)lane.td.size();
+  for (int i = 0; i < n - 1; ++i) {
+    TransDesc t{};
+    t.Z = (const double2*)p.H.upper + i * blk;
+    t.D = (double2*)Hl + i * blk;
+    t.a = kZero; t.z = kZero; t.g = kOne;
+    t.b = b; t.batch = 1;
+    lane.td.push_back(t);
+  }
+  o.count = (int)lane.td.size() - o.first;
+  o.bytes = 32.0 * blk * (n - 1);
+  if (o.count) lane.ops.push_back(o);
+}
+
+void build_lane(Lane& lane, const qtx_rgf_problem& p, const Plan& q, char* ws,
+                int e0, int ec, const double* d_E, int* d_info, const void* Hl,
+                Tuner& tuner, hipStream_t strm) {
+  const int n = q.n, b = q.b;
+  const long long blk = (long long)b * b;
+  Layout lay = carve_layout(q, ec, ws);
+  Emitter s(lane, tuner, strm, b, ec);
+
+  auto outv = [&](void* ptr, long long per_e) {
+    View v;
+    if (!ptr) return v;
+    v.p = (const double2*)ptr + (long long)e0 * per_e * blk;
+    v.es = per_e * blk;
+    v.bs = blk;
+    return v;
+  };
+  auto inv_ = [&](const void* ptr, long long per_e) { return outv(const_cast<void*>(ptr), per_e); };
+
+  Core k;
+  k.n = n;
+  k.xR = lay.xR;
+  k.tS = lay.tS; k.tF = lay.tF; k.tP = lay.tP; k.tM = lay.tM; k.tR = lay.tR;
+  for (int r = 0; r < 2; ++r) { k.tG[r] = lay.tG[r]; k.tW[r] = lay.tW[r]; k.tY[r] = lay.tY[r]; }
+  k.panel = lay.panel; k.brow = lay.brow; k.perm = lay.perm; k.used = lay.used;
+  k.info = d_info + e0;
+  k.XRd = outv(p.XR.diag, n);
+  k.XRu = outv(p.XR.upper, n - 1);
+  k.XRl = outv(p.XR.lower, n - 1);
+
+  const qtx_bt_out* outs[2] = {&p.XL, &p.XG};
+  int r = 0;
+  for (int t = 0; t < 2; ++t) {
+    if (!outs[t]->diag) continue;
+    Rhs h;
+    h.Xd = outv(outs[t]->diag, n);
+    if (n > 1) {
+      h.Xu = outv(outs[t]->upper, n - 1);
+      h.Xl = outv(outs[t]->lower, n - 1);
+    }
+    if (!q.is_w) {
+      const qtx_bt_in& B = t == 0 ? p.sigma_l : p.sigma_g;
+      h.Bd = inv_(B.diag, n);
+      if (n > 1 && B.upper) h.Bu = inv_(B.upper, n - 1);
+    } else {
+      h.Bd = lay.Bd[r];
+      if (n > 1) h.Bu = lay.Bu[r];
+    }
+    k.rhs.push_back(h);
+    ++r;
+  }
+
+  if (!q.is_w) {
+    const double* E = d_E + e0;
+    const View Hd = in_view(p.H.diag, 0, blk);
+    const View Hu = in_view(p.H.upper, 0, blk);
+    const View HL = p.H.lower ? in_view(p.H.lower, 0, blk) : in_view(Hl, 0, blk);
+    const View Sd = in_view(p.S.diag, 0, blk);
+    const View SRd = inv_(p.sigma_r.diag, n);
+    if (q.general_ul && n > 1) {
+      const View Su = in_view(p.S.upper, 0, blk), Sl = in_view(p.S.lower, 0, blk);
+      const View SRu = inv_(p.sigma_r.upper, n - 1), SRl = inv_(p.sigma_r.lower, n - 1);
+      for (int i = 0; i < n - 1; ++i) {
+        LinCombDesc a{};
+        a.E = E;
+        a.src[0] = Hu.at(i); a.sSrc[0] = 0; a.c[0] = kMinus;
+        if (Su.ok()) { a.src[1] = Su.at(i); a.sSrc[1] = 0; a.d[1] = kOne; }
+        if (SRu.ok()) { a.src[2] = SRu.at(i); a.sSrc[2] = SRu.es; a.c[2] = kMinus; }
+        a.D = lay.Uw.w(i); a.sD = lay.Uw.es;
+        s.lincomb(a);
+        LinCombDesc l{};
+        l.E = E;
+        l.src[0] = HL.at(i); l.sSrc[0] = 0; l.c[0] = kMinus;
+        if (Sl.ok()) { l.src[1] = Sl.at(i); l.sSrc[1] = 0; l.d[1] = kOne; }
+        if (SRl.ok()) { l.src[2] = SRl.at(i); l.sSrc[2] = SRl.es; l.c[2] = kMinus; }
+        l.D = lay.Lw.w(i); l.sD = lay.Lw.es;
+        s.lincomb(l);
+      }
+      k.U = lay.Uw; k.L = lay.Lw; k.su = 1.0; k.sl = 1.0;
+    } else {
+      k.U = Hu; k.L = HL; k.su = -1.0; k.sl = -1.0;
+    }
+    s.set_fp32(q.fp32);
+    run_core(s, k, [&](int i) {
+      LinCombDesc a{};
+      a.E = E;
+      if (Sd.ok()) { a.src[0] = Sd.at(i); a.sSrc[0] = 0; a.d[0] = kOne; }
+      else a.idc1 = kOne;
+      a.src[1] = Hd.at(i); a.sSrc[1] = 0; a.c[1] = kMinus;
+      a.src[2] = SRd.at(i); a.sSrc[2] = SRd.es; a.c[2] = kMinus;
+      a.D = k.tS.w(0); a.sD = k.tS.es;
+      s.lincomb(a);
+    });
+    s.set_fp32(false);
+  } else {
+    WOps w{};
+    w.Vd = in_view(p.V.diag, 0, blk);
+    w.Vu = in_view(p.V.upper, 0, blk);
+    w.Vl = in_view(p.V.lower, 0, blk);
+    w.Prd = inv_(p.P_r.diag, n);
+    w.Pru = n > 1 ? inv_(p.P_r.upper, n - 1) : View();
+    w.Prl = n > 1 ? inv_(p.P_r.lower, n - 1) : View();
+    const qtx_bt_in* Ps[2] = {&p.P_l, &p.P_g};
+    int rr = 0;
+    for (int t = 0; t < 2; ++t) {
+      if (!outs[t]->diag) continue;
+      w.Psd[rr] = inv_(Ps[t]->diag, n);
+      w.Psu[rr] = n > 1 ? inv_(Ps[t]->upper, n - 1) : View();
+      ++rr;
+    }
+    w.Ad = lay.Ad;
+    if (n > 1) { w.Au = lay.Uw; w.Al = lay.Lw; }
+    for (int t = 0; t < 2; ++t) { w.Bd[t] = lay.Bd[t]; w.Bu[t] = lay.Bu[t]; }
+    w.Tm1 = lay.Tm1; w.T0 = lay.T0; w.Tp1 = lay.Tp1; w.Tp2 = lay.Tp2;
+    w_assemble(s, w, n, q.nr);
+    k.U = w.Au; k.L = w.Al; k.su = 1.0; k.sl = 1.0;
+    s.set_fp32(q.fp32);
+    run_core(s, k, [&](int i) { s.copy(k.tS, 0, w.Ad, i); });
+    s.set_fp32(false);
+    if (p.WR_diag) {
+      // W^R_ii = X_ii V_ii + X_{i,i-1} V_{i-1,i} + X_{i,i+1} V_{i+1,i}
+      const View WR = outv(p.WR_diag, n);
+      s.gemm('N', 'N', {Term{{k.XRd, 0}, {w.Vd, 0}, nullptr, 0, WR, 0, kOne, kZero}}, n);
+      if (n > 1) {
+        s.gemm('N', 'N', {Term{{k.XRl, 0}, {w.Vu, 0}, &WR, 1, WR, 1, kOne, kOne}}, n - 1);
+        const bool vl = w.Vl.ok();
+        s.gemm('N', vl ? 'N' : 'C', {Term{{k.XRu, 0}, {vl ? w.Vl : w.Vu, 0}, &WR, 0, WR, 0, kOne, kOne}}, n - 1);
+      }
+    }
+  }
+}
+
+}  // namespace qtx

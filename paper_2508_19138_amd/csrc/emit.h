@@ -1,0 +1,34 @@
+// Emission of the RGF recursion as one lane's operation list.
+#pragma once
+#include "../../include/qtx_rgf.h"
+#include "exec.h"
+
+namespace qtx {
+
+// Per-problem sizes and options fixed before lanes are built.
+struct Plan {
+  int n = 0, b = 0, ne = 0, nr = 0;
+  bool is_w = false;
+  bool general_ul = false;   // U/L assembled per energy
+  bool need_hl = false;      // H.lower absent: H.upper^dagger built once
+  bool bt_rhs[2] = {false, false};
+  bool fp32 = false;
+};
+
+Plan make_plan(const qtx_rgf_problem& p);
+
+// Exact workspace bytes of one lane of `ec` energies.
+size_t lane_bytes(const Plan& q, int ec);
+
+// Operations of one lane (energies e0 .. e0+ec-1 of problem p) whose
+// workspace is ws[0 .. lane_bytes(q, ec)).  d_E: the problem's energies on
+// the device (G-type), d_info: the problem's per-energy status words, Hl:
+// the problem's H lower blocks when H.lower is absent.
+void build_lane(Lane& lane, const qtx_rgf_problem& p, const Plan& q, char* ws,
+                int e0, int ec, const double* d_E, int* d_info, const void* Hl,
+                Tuner& tuner, hipStream_t s);
+
+// Operations that write H.upper^dagger into Hl (one lane, no energy axis).
+void build_hl_lane(Lane& lane, const qtx_rgf_problem& p, void* Hl);
+
+}  // namespace qtx

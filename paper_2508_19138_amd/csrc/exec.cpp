@@ -1,0 +1,455 @@
+// Merged-launch scheduler, descriptor arena, graph replay and autotuner.
+//
+// Lanes (independent solves) are advanced in rounds.  In every round the
+// next operation of each unfinished lane is taken; operations with the same
+// signature (kind, operand ops, precision, tile configuration) become one
+// flat launch over all their descriptors, whatever the lanes' block sizes,
+// block counts or positions in their recursions.  The descriptors of a
+// whole segment of rounds are written into a pinned host arena, uploaded in
+// one copy and launched in order on one stream, so lane order is the only
+// dependency the runtime has to respect.
+#include "exec.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+namespace qtx {
+
+#define XCHK(expr)                                  \
+  do {                                              \
+    hipError_t e_ = (expr);                         \
+    if (e_ != hipSuccess) throw Fail{5};            \
+  } while (0)
+
+// ------------------------------------------------------------------ tuner --
+
+std::string Tuner::cache_path() const {
+  const char* p = std::getenv("QTX_TUNE_CACHE");
+  if (p && *p) return p;
+  const char* h = std::getenv("HOME");
+  return std::string(h ? h : "/tmp") + "/.cache/qtx_rgf_tune_gfx950.json";
+}
+
+void Tuner::load() {
+  loaded_ = true;
+  std::ifstream f(cache_path());
+  if (!f) return;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  // flat {"key": value, ...}
+  size_t i = 0;
+  while ((i = s.find('"', i)) != std::string::npos) {
+    const size_t j = s.find('"', i + 1);
+    if (j == std::string::npos) break;
+    const std::string key = s.substr(i + 1, j - i - 1);
+    const size_t c = s.find(':', j);
+    if (c == std::string::npos) break;
+    const int v = std::atoi(s.c_str() + c + 1);
+    if (v >= 0 && v < kGemmConfigs) table_[key] = v;
+    i = c + 1;
+  }
+}
+
+void Tuner::save() const {
+  const std::string p = cache_path();
+  const size_t slash = p.rfind('/');
+  if (slash != std::string::npos) {
+    std::string dir = p.substr(0, slash);
+    std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
+    (void)!std::system(cmd.c_str());
+  }
+  std::ofstream f(p);
+  if (!f) return;
+  f << "{";
+  bool first = true;
+  for (auto& kv : table_) {
+    f << (first ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
+    first = false;
+  }
+  f << "}\n";
+}
+
+static int heuristic_cfg(int b) { return b <= 32 ? 2 : (b >= 384 ? 1 : 0); }
+
+int Tuner::measure(int b, bool fp32, hipStream_t s) {
+  // time each configuration on a batch of b x b x b products large enough
+  // to fill the chip; operands are zero-filled scratch
+  const long long blk = (long long)b * b;
+  int batch = std::max(1, std::min(512, (int)(4096 * 4096LL / blk)));
+  void* buf = nullptr;
+  if (hipMalloc(&buf, (size_t)(3 * batch) * blk * 16 + 4096) != hipSuccess) {
+    (void)hipGetLastError();
+    return heuristic_cfg(b);
+  }
+  XCHK(hipMemsetAsync(buf, 0, (size_t)(3 * batch) * blk * 16, s));
+  GemmDesc d{};
+  d.A = buf;
+  d.B = (char*)buf + (size_t)batch * blk * 16;
+  d.D = (char*)buf + (size_t)2 * batch * blk * 16;
+  d.sA = blk; d.sB = blk; d.sD = blk;
+  d.lda = b; d.ldb = b; d.ldc = b; d.ldd = b;
+  d.alpha = zc{1.0, 0.0};
+  d.beta = zc{0.0, 0.0};
+  d.M = b; d.N = b; d.K = b;
+  d.batch = batch; d.batch2 = 1;
+  void* ddesc = nullptr;
+  XCHK(hipMalloc(&ddesc, sizeof(GemmDesc) + 64));
+  hipEvent_t a, z;
+  XCHK(hipEventCreate(&a));
+  XCHK(hipEventCreate(&z));
+  int best = heuristic_cfg(b);
+  float best_ms = 1e30f;
+  for (int cfg = 0; cfg < kGemmConfigs; ++cfg) {
+    if (cfg == 1 && b < 128) continue;
+    d.tiles = gemm_tiles(cfg, b, b);
+    int pre[2] = {0, d.tiles * batch};
+    XCHK(hipMemcpy(ddesc, &d, sizeof(d), hipMemcpyHostToDevice));
+    int* dpre = (int*)((char*)ddesc + sizeof(GemmDesc));
+    (void)dpre;
+    void* dp = nullptr;
+    XCHK(hipMalloc(&dp, sizeof(pre)));
+    XCHK(hipMemcpy(dp, pre, sizeof(pre), hipMemcpyHostToDevice));
+    FlatLaunch l{ddesc, (const int*)dp, 1, pre[1]};
+    XCHK(launch_gemm(cfg, fp32, 'N', 'N', l, s));   // warm
+    XCHK(hipEventRecord(a, s));
+    for (int r = 0; r < 3; ++r) XCHK(launch_gemm(cfg, fp32, 'N', 'N', l, s));
+    XCHK(hipEventRecord(z, s));
+    XCHK(hipEventSynchronize(z));
+    float ms = 0;
+    XCHK(hipEventElapsedTime(&ms, a, z));
+    XCHK(hipFree(dp));
+    if (ms < best_ms) { best_ms = ms; best = cfg; }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(z);
+  (void)hipFree(ddesc);
+  (void)hipFree(buf);
+  return best;
+}
+
+int Tuner::cfg(int M, int N, int K, bool fp32, hipStream_t s) {
+  const int b = std::max(M, N);
+  if (K < 32) return heuristic_cfg(std::min(b, 64));   // thin updates
+  if (!enabled_) return heuristic_cfg(b);
+  if (!loaded_) load();
+  char key[64];
+  std::snprintf(key, sizeof key, "gfx950/%s/b%d", fp32 ? "c64" : "c128", b);
+  auto it = table_.find(key);
+  if (it != table_.end()) return it->second;
+  const int c = measure(b, fp32, s);
+  table_[key] = c;
+  save();
+  return c;
+}
+
+// ----------------------------------------------------------------- arena --
+
+template <class D>
+size_t Executor::put(const std::vector<D>& v) {
+  size_t off = (host_.size() + 255) & ~size_t(255);
+  host_.resize(off + v.size() * sizeof(D));
+  std::memcpy(host_.data() + off, v.data(), v.size() * sizeof(D));
+  return off;
+}
+
+size_t Executor::put_prefix(const std::vector<int>& p) { return put(p); }
+
+static uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  return h;
+}
+
+// Signature: operations that may share a launch.
+static uint64_t signature(const Op& o) {
+  uint64_t k = (uint64_t)o.k;
+  if (o.k == OpK::Gemm)
+    k |= ((uint64_t)(o.opa == 'C') << 8) | ((uint64_t)(o.opb == 'C') << 9) |
+         ((uint64_t)o.fp32 << 10) | ((uint64_t)o.cfg << 12);
+  return k;
+}
+
+void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
+  const Op& f = *ops[0].second;
+  if (f.k == OpK::Gemm) {
+    std::vector<GemmDesc> d;
+    std::vector<int> pre(1, 0);
+    double fl = 0, by = 0;
+    for (auto& lo : ops) {
+      const Op* o = lo.second;
+      for (int q = 0; q < o->count; ++q) {
+        GemmDesc g = lo.first->gd[o->first + q];
+        g.tiles = gemm_tiles(o->cfg, g.M, g.N);
+        d.push_back(g);
+        pre.push_back(pre.back() + g.tiles * g.batch * std::max(1, g.batch2));
+      }
+      fl += o->flops;
+      by += o->bytes;
+    }
+    LaunchRec r{LaunchRec::Gemm, f.opa, f.opb, f.fp32, f.cfg, 0, put(d), put_prefix(pre),
+                (int)d.size(), pre.back(), f.fp32 ? kClassCgemm : kClassZgemm, fl, by};
+    recs_.push_back(r);
+    return;
+  }
+  if (f.k == OpK::Inv) {
+    // panels k0 = 0, kPanel, ... up to the largest block, each followed by
+    // its rank-kPanel update; one permutation at the end
+    std::vector<InvDesc> all;
+    double fl = 0;
+    for (auto& lo : ops) {
+      for (int q = 0; q < lo.second->count; ++q) all.push_back(lo.first->id[lo.second->first + q]);
+      fl += lo.second->flops;
+    }
+    int maxb = 0;
+    for (auto& v : all) maxb = std::max(maxb, v.b);
+    const int R = (maxb + kInvThreads - 1) / kInvThreads;
+    for (int k0 = 0; k0 < maxb; k0 += kPanel) {
+      std::vector<InvDesc> d;
+      std::vector<int> pre(1, 0);
+      std::vector<GemmDesc> gd;
+      std::vector<int> gpre(1, 0);
+      double by = 0, gby = 0;
+      for (const InvDesc& v : all) {
+        if (v.b <= k0) continue;
+        d.push_back(v);
+        pre.push_back(pre.back() + v.batch);
+        by += 16.0 * 3.0 * v.b * kPanel * v.batch;
+        if (v.b > kPanel) {
+          GemmDesc g{};
+          g.M = v.b; g.N = v.b; g.K = kPanel;
+          g.A = v.panel; g.sA = (long long)v.b * kPanel; g.lda = kPanel;
+          g.B = v.brow; g.sB = (long long)kPanel * v.b; g.ldb = v.b;
+          g.C = v.S; g.sC = v.sS; g.ldc = v.b;
+          g.D = v.S; g.sD = v.sS; g.ldd = v.b;
+          g.alpha = zc{1.0, 0.0};
+          g.beta = zc{1.0, 0.0};
+          g.batch = v.batch; g.batch2 = 1;
+          g.tiles = gemm_tiles(0, v.b, v.b);
+          gd.push_back(g);
+          gpre.push_back(gpre.back() + g.tiles * g.batch);
+          gby += 16.0 * 2.0 * g.M * (double)g.N * g.batch;
+        }
+      }
+      recs_.push_back(LaunchRec{LaunchRec::Panel, 'N', 'N', false, R, k0, put(d), put_prefix(pre),
+                                (int)d.size(), pre.back(), kClassInv, (k0 == 0 ? fl : 0.0), by});
+      if (!gd.empty())
+        recs_.push_back(LaunchRec{LaunchRec::Gemm, 'N', 'N', false, kGemmInvUpdate, k0, put(gd), put_prefix(gpre),
+                                  (int)gd.size(), gpre.back(), kClassInv, 0.0, gby});
+    }
+    std::vector<int> pre(1, 0);
+    double by = 0;
+    for (const InvDesc& v : all) {
+      pre.push_back(pre.back() + v.batch * ((v.b + kPermRows - 1) / kPermRows));
+      by += 32.0 * v.b * (double)v.b * v.batch;
+    }
+    recs_.push_back(LaunchRec{LaunchRec::Permute, 'N', 'N', false, 0, 0, put(all), put_prefix(pre),
+                              (int)all.size(), pre.back(), kClassInv, 0.0, by});
+    return;
+  }
+  if (f.k == OpK::Lin) {
+    std::vector<LinCombDesc> d;
+    std::vector<int> pre(1, 0);
+    double by = 0;
+    for (auto& lo : ops) {
+      for (int q = 0; q < lo.second->count; ++q) {
+        const LinCombDesc& v = lo.first->ld[lo.second->first + q];
+        d.push_back(v);
+        pre.push_back(pre.back() + v.batch * lincomb_chunks(v.b));
+      }
+      by += lo.second->bytes;
+    }
+    recs_.push_back(LaunchRec{LaunchRec::Lin, 'N', 'N', false, 0, 0, put(d), put_prefix(pre),
+                              (int)d.size(), pre.back(), kClassElem, 0.0, by});
+    return;
+  }
+  std::vector<TransDesc> d;
+  std::vector<int> pre(1, 0);
+  double by = 0;
+  for (auto& lo : ops) {
+    for (int q = 0; q < lo.second->count; ++q) {
+      const TransDesc& v = lo.first->td[lo.second->first + q];
+      d.push_back(v);
+      pre.push_back(pre.back() + v.batch * trans_tiles(v.b));
+    }
+    by += lo.second->bytes;
+  }
+  recs_.push_back(LaunchRec{LaunchRec::Trans, 'N', 'N', false, 0, 0, put(d), put_prefix(pre),
+                            (int)d.size(), pre.back(), kClassElem, 0.0, by});
+}
+
+int Executor::build(std::vector<Lane*>& lanes, size_t arena_limit) {
+  int rounds = 0;
+  struct Head { uint64_t sig; Lane* l; Op* o; };
+  std::vector<Head> heads;
+  std::vector<std::pair<Lane*, Op*>> grp;
+  while (host_.size() < arena_limit) {
+    heads.clear();
+    for (Lane* l : lanes)
+      if (!l->done()) heads.push_back(Head{signature(l->ops[l->next]), l, &l->ops[l->next]});
+    if (heads.empty()) break;
+    std::stable_sort(heads.begin(), heads.end(),
+                     [](const Head& a, const Head& b) { return a.sig < b.sig; });
+    size_t i = 0;
+    while (i < heads.size()) {
+      size_t j = i;
+      grp.clear();
+      while (j < heads.size() && heads[j].sig == heads[i].sig) {
+        grp.push_back({heads[j].l, heads[j].o});
+        ++j;
+      }
+      emit_group(grp);
+      i = j;
+    }
+    for (Lane* l : lanes)
+      if (!l->done()) l->next++;
+    ++rounds;
+  }
+  return rounds;
+}
+
+hipEvent_t Executor::get_event() {
+  if (!ev_pool_.empty()) {
+    hipEvent_t e = ev_pool_.back();
+    ev_pool_.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  XCHK(hipEventCreate(&e));
+  return e;
+}
+
+void Executor::issue(char* base, bool profile) {
+  for (const LaunchRec& r : recs_) {
+    FlatLaunch l{base + r.desc_off, (const int*)(base + r.prefix_off), r.nd, r.total};
+    hipEvent_t a = nullptr, b = nullptr;
+    if (profile) {
+      a = get_event();
+      b = get_event();
+      XCHK(hipEventRecord(a, s_));
+    }
+    switch (r.kind) {
+      case LaunchRec::Gemm: XCHK(launch_gemm(r.cfg, r.fp32, r.opa, r.opb, l, s_)); break;
+      case LaunchRec::Panel: XCHK(launch_inv_panel(r.cfg, r.k0, l, s_)); break;
+      case LaunchRec::Permute: XCHK(launch_inv_permute(l, s_)); break;
+      case LaunchRec::Lin: XCHK(launch_lincomb(l, s_)); break;
+      case LaunchRec::Trans: XCHK(launch_transcomb(l, s_)); break;
+    }
+    if (profile) {
+      XCHK(hipEventRecord(b, s_));
+      pending_.push_back(Pending{r.cls, a, b, r.flops, r.bytes});
+    }
+  }
+}
+
+void Executor::flush(bool profile, bool graphs, std::vector<KStat>& stats) {
+  if (recs_.empty()) {
+    host_.clear();
+    return;
+  }
+  const size_t bytes = host_.size();
+  uint64_t key = 0;
+  if (graphs && !profile) {
+    key = fnv1a(host_.data(), bytes);
+    key = fnv1a(recs_.data(), recs_.size() * sizeof(LaunchRec), key);
+    auto it = graphs_.find(key);
+    if (it != graphs_.end()) {
+      it->second.last = ++tick_;
+      XCHK(hipGraphLaunch(it->second.exec, s_));
+      recs_.clear();
+      host_.clear();
+      return;
+    }
+    if (++seen_[key] >= 2 && graphs_.size() < 64) {
+      // second sight of this segment: capture it with its own arena
+      GraphEntry g{};
+      XCHK(hipMalloc((void**)&g.arena, bytes));
+      XCHK(hipMemcpyAsync(g.arena, host_.data(), bytes, hipMemcpyHostToDevice, s_));
+      XCHK(hipStreamSynchronize(s_));
+      hipGraph_t graph;
+      XCHK(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
+      issue(g.arena, false);
+      XCHK(hipStreamEndCapture(s_, &graph));
+      XCHK(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(graph);
+      g.bytes = bytes;
+      g.last = ++tick_;
+      graphs_[key] = g;
+      XCHK(hipGraphLaunch(g.exec, s_));
+      recs_.clear();
+      host_.clear();
+      return;
+    }
+  }
+  // eager: pinned staging + device arena, double-buffered by slot
+  const int sl = slot_;
+  slot_ ^= 1;
+  if (done_[sl]) XCHK(hipEventSynchronize(done_[sl]));
+  if (pin_cap_[sl] < bytes) {
+    if (pin_[sl]) (void)hipHostFree(pin_[sl]);
+    pin_cap_[sl] = std::max(bytes, (size_t)1 << 20);
+    XCHK(hipHostMalloc((void**)&pin_[sl], pin_cap_[sl], 0));
+  }
+  if (dev_cap_[sl] < bytes) {
+    if (dev_[sl]) {
+      XCHK(hipStreamSynchronize(s_));
+      (void)hipFree(dev_[sl]);
+    }
+    dev_cap_[sl] = std::max(bytes, (size_t)1 << 20);
+    XCHK(hipMalloc((void**)&dev_[sl], dev_cap_[sl]));
+  }
+  std::memcpy(pin_[sl], host_.data(), bytes);
+  XCHK(hipMemcpyAsync(dev_[sl], pin_[sl], bytes, hipMemcpyHostToDevice, s_));
+  issue(dev_[sl], profile);
+  if (!done_[sl]) XCHK(hipEventCreateWithFlags(&done_[sl], hipEventDisableTiming));
+  XCHK(hipEventRecord(done_[sl], s_));
+  recs_.clear();
+  host_.clear();
+  if (pending_.size() > 8192) sync_and_collect(stats);
+}
+
+void Executor::sync_and_collect(std::vector<KStat>& stats) {
+  XCHK(hipStreamSynchronize(s_));
+  for (auto& p : pending_) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      KStat& s = stats[p.cls];
+      s.launches += 1;
+      s.ms += ms;
+      s.flops += p.flops;
+      s.bytes += p.bytes;
+    }
+    ev_pool_.push_back(p.a);
+    ev_pool_.push_back(p.b);
+  }
+  pending_.clear();
+}
+
+void Executor::release() {
+  (void)hipStreamSynchronize(s_);
+  for (auto& kv : graphs_) {
+    (void)hipGraphExecDestroy(kv.second.exec);
+    (void)hipFree(kv.second.arena);
+  }
+  graphs_.clear();
+  seen_.clear();
+  for (int i = 0; i < 2; ++i) {
+    if (dev_[i]) (void)hipFree(dev_[i]);
+    if (pin_[i]) (void)hipHostFree(pin_[i]);
+    if (done_[i]) (void)hipEventDestroy(done_[i]);
+    dev_[i] = nullptr; pin_[i] = nullptr; done_[i] = nullptr;
+    dev_cap_[i] = pin_cap_[i] = 0;
+  }
+  for (auto& p : pending_) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  pending_.clear();
+  for (auto e : ev_pool_) (void)hipEventDestroy(e);
+  ev_pool_.clear();
+}
+
+Executor::~Executor() { release(); }
+
+}  // namespace qtx

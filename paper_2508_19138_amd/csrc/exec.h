@@ -1,0 +1,132 @@
+// Host runtime of the RGF library: the operation stream of one solve lane,
+// the merged-launch scheduler, the descriptor arena, graph replay and the
+// tile autotuner.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "qtx_internal.h"
+
+namespace qtx {
+
+constexpr int kClassZgemm = 0, kClassCgemm = 1, kClassInv = 2, kClassElem = 3;
+constexpr int kNumClasses = 4;
+
+struct KStat {
+  int64_t launches = 0;
+  double ms = 0, flops = 0, bytes = 0;
+};
+
+enum class OpK : uint8_t { Gemm, Inv, Lin, Trans };
+
+// One step of one lane: up to a few independent descriptors of one kind
+// that are issued together (they may share a launch with other lanes').
+struct Op {
+  OpK k = OpK::Gemm;
+  char opa = 'N', opb = 'N';
+  bool fp32 = false;
+  int cfg = 0;
+  int first = 0, count = 0;   // range in the lane's descriptor table of kind k
+  double flops = 0, bytes = 0;
+};
+
+// A lane is an independent solve: one problem restricted to a contiguous
+// chunk of its energies, with its own workspace region.  Its operations are
+// executed in order; different lanes are independent.
+struct Lane {
+  std::vector<Op> ops;
+  std::vector<GemmDesc> gd;
+  std::vector<InvDesc> id;
+  std::vector<LinCombDesc> ld;
+  std::vector<TransDesc> td;
+  size_t next = 0;
+  int problem = -1;
+  int e0 = 0, ec = 0;
+  size_t ws_off = 0, ws_bytes = 0;
+  bool done() const { return next >= ops.size(); }
+};
+
+// Thrown for HIP failures; carries the status for the ABI.
+struct Fail {
+  int st;
+};
+
+class Tuner {
+ public:
+  // Tile configuration for complex products of shape M x N x K.
+  int cfg(int M, int N, int K, bool fp32, hipStream_t s);
+  void set_enabled(bool on) { enabled_ = on; }
+  std::string cache_path() const;
+
+ private:
+  int measure(int b, bool fp32, hipStream_t s);
+  void load();
+  void save() const;
+  bool loaded_ = false;
+  bool enabled_ = true;
+  std::map<std::string, int> table_;
+};
+
+// One kernel launch of a merged schedule.
+struct LaunchRec {
+  enum Kind : uint8_t { Gemm, Panel, Permute, Lin, Trans } kind;
+  char opa, opb;
+  bool fp32;
+  int cfg;        // gemm tile config, or rows-per-thread R for Panel
+  int k0;         // Panel
+  size_t desc_off, prefix_off;
+  int nd, total;
+  int cls;
+  double flops, bytes;
+};
+
+class Executor {
+ public:
+  explicit Executor(hipStream_t s) : s_(s) {}
+  ~Executor();
+  // Advance the lanes by merged rounds until every lane is done or the
+  // arena limit is reached; returns the number of rounds emitted.  The
+  // caller then calls flush() to upload and launch.
+  int build(std::vector<Lane*>& lanes, size_t arena_limit);
+  // Upload and launch what build() produced (graph replay when the same
+  // segment was seen before and graphs are enabled).
+  void flush(bool profile, bool graphs, std::vector<KStat>& stats);
+  void sync_and_collect(std::vector<KStat>& stats);
+  bool empty() const { return recs_.empty(); }
+  void release();
+
+ private:
+  template <class D>
+  size_t put(const std::vector<D>& v);
+  size_t put_prefix(const std::vector<int>& p);
+  void emit_group(std::vector<std::pair<Lane*, Op*>>& ops);
+  void issue(char* dev_arena, bool profile);
+
+  hipStream_t s_;
+  std::vector<char> host_;          // arena being built
+  std::vector<LaunchRec> recs_;
+  // double-buffered device / pinned arenas
+  char* dev_[2] = {nullptr, nullptr};
+  size_t dev_cap_[2] = {0, 0};
+  char* pin_[2] = {nullptr, nullptr};
+  size_t pin_cap_[2] = {0, 0};
+  hipEvent_t done_[2] = {nullptr, nullptr};
+  int slot_ = 0;
+  // profiling
+  struct Pending { int cls; hipEvent_t a, b; double flops, bytes; };
+  std::vector<Pending> pending_;
+  std::vector<hipEvent_t> ev_pool_;
+  // graph cache
+  struct GraphEntry { hipGraphExec_t exec; char* arena; size_t bytes; uint64_t last; };
+  std::unordered_map<uint64_t, GraphEntry> graphs_;
+  std::unordered_map<uint64_t, int> seen_;
+  uint64_t tick_ = 0;
+  hipEvent_t get_event();
+};
+
+}  // namespace qtx

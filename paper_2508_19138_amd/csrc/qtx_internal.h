@@ -1,5 +1,12 @@
-// Host-side internal interfaces of the RGF library: kernel launchers and
-// the argument blocks they take.  Not part of the public C ABI.
+// Internal interfaces of the RGF library: the device descriptors that drive
+// every kernel, and the launchers.  Not part of the public C ABI.
+//
+// Every kernel is descriptor-driven: a launch covers a table of descriptors
+// in device memory, each describing a strided family of independent b x b
+// block operations (one per energy and, optionally, per block index).  The
+// grid is flat; workgroup w finds its descriptor by a binary search over an
+// exclusive prefix sum of workgroups per descriptor.  One launch can thus
+// serve many independent solves of different block size and block count.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -8,83 +15,123 @@
 
 namespace qtx {
 
-constexpr int kMaxGroups = 4;
+// Flat launch over `nd` descriptors of type T: workgroups
+// [prefix[d], prefix[d+1]) belong to descriptor d; total = prefix[nd].
+struct FlatLaunch {
+  const void* desc;     // device, nd descriptors
+  const int* prefix;    // device, nd + 1 entries
+  int nd;
+  int total;
+};
 
-// One independent strided-batched product inside a grouped launch:
-//   D[e] = alpha * op(A[e]) op(B[e]) + beta * C[e]
-// Element e of an operand starts at ptr + e * stride (stride 0 = shared).
-struct GemmGroup {
+// ---- complex products on the matrix cores ----------------------------------
+// D[e,j] = alpha * op(A[e,j]) op(B[e,j]) + beta * C[e,j], e < batch,
+// j < batch2; operand X[e,j] starts at X + e * sX + j * tX (complex128
+// elements).  op(A) is M x K, op(B) is K x N.  C may be null (beta ignored)
+// and may equal D.
+struct GemmDesc {
   const void* A;
   const void* B;
   const void* C;
   void* D;
-  long long sA, sB, sC, sD;   // strides over the first batch index (energy)
-  long long tA, tB, tC, tD;   // strides over the second batch index (block)
-  zc alpha, beta;
-};
-
-// Up to kMaxGroups products sharing the shape, the operations and the
-// leading dimensions are issued as one launch.
-struct GemmArgs {
-  int M, N, K;
+  long long sA, sB, sC, sD;
+  long long tA, tB, tC, tD;
   long long lda, ldb, ldc, ldd;
-  int batch;        // first batch index  (grid y = batch * batch2)
-  int batch2;       // second batch index (0 is read as 1)
-  int ngroups;
-  GemmGroup g[kMaxGroups];
+  zc alpha, beta;
+  int M, N, K;
+  int batch, batch2;
+  int tiles;            // workgroups per matrix (set by the launcher's config)
 };
 
-// opa/opb: 'N' or 'C'.  FP64: complex128 operands on the FP64 matrix cores.
-hipError_t launch_zgemm(char opa, char opb, const GemmArgs& a, hipStream_t s);
-// FP32: complex64 operands on the FP32 matrix cores (alpha/beta rounded).
-hipError_t launch_cgemm(char opa, char opb, const GemmArgs& a, hipStream_t s);
+// Tile configurations of the product kernel (see zgemm.hip); the extra
+// value kGemmInvUpdate selects the general tile under its own kernel symbol
+// for the inverse's rank-kPanel updates (FP64, N x N only).
+constexpr int kGemmConfigs = 3;
+constexpr int kGemmInvUpdate = 7;
+int gemm_tile_m(int cfg);   // kGemmInvUpdate maps to configuration 0
+int gemm_tile_n(int cfg);
+inline int gemm_tiles(int cfg, int M, int N) {
+  return ((M + gemm_tile_m(cfg) - 1) / gemm_tile_m(cfg)) *
+         ((N + gemm_tile_n(cfg) - 1) / gemm_tile_n(cfg));
+}
+// fp32 = false: FP64 matrix cores on complex128.  fp32 = true: operands
+// rounded to complex64, FP32 matrix cores, FP64 epilogue.
+hipError_t launch_gemm(int cfg, bool fp32, char opa, char opb,
+                       const FlatLaunch& l, hipStream_t s);
 
-// ---- Gauss-Jordan inverse with partial pivoting --------------------------
-constexpr int kPanel = 16;   // panel width (columns per factorisation step)
+// ---- Gauss-Jordan inverse with partial pivoting -----------------------------
+constexpr int kPanel = 16;     // columns factored per panel step
+constexpr int kInvThreads = 256;
 
-struct InvWork {
-  void* panel;      // [batch][b][kPanel] complex128
-  void* brow;       // [batch][kPanel][b] complex128
-  int* perm;        // [batch][b]
-  int* used;        // [batch][b]
+// `batch` matrices S[e] (b x b, stride sS) are eliminated in place; the
+// inverses go to X[e] (stride sX).  Per matrix work: panel [b][kPanel],
+// brow [kPanel][b], perm [b], used [b] (strides b*kPanel, kPanel*b, b, b).
+// info[e]: 0, or set once to +code (zero pivot) / -code (non-finite pivot);
+// `reset_info` clears it at the first panel.  code <= 0 means 1 + column.
+struct InvDesc {
+  void* S;
+  void* X;
+  long long sS, sX;
+  void* panel;
+  void* brow;
+  int* perm;
+  int* used;
+  int* info;
+  int code;
+  int reset_info;
+  int b;
+  int batch;
 };
-// In-place GJ on S[e] (stride sS, b x b); result, un-permuted, into X[e].
-// info[e] (may be null): 0 if fine, else set once to +code (zero pivot) or
-// -code (non-finite pivot); code = 1 + column when code_base <= 0, else
-// code_base.
-hipError_t launch_zinv(int b, void* S, long long sS, void* X, long long sX,
-                       int batch, const InvWork& w, int* info, int code_base,
-                       hipStream_t s);
+// Panel factorisation of columns [k0, k0 + kPanel) of every matrix with
+// b > k0 (one workgroup per matrix); R = rows per thread, b <= 256 R.
+hipError_t launch_inv_panel(int R, int k0, const FlatLaunch& l, hipStream_t s);
+// Final permutation X[k][p_j] = S[p_k][j]; 8 rows per workgroup.
+constexpr int kPermRows = 8;
+hipError_t launch_inv_permute(const FlatLaunch& l, hipStream_t s);
 
-// ---- elementwise kernels -------------------------------------------------
-// D[e] = idc(e) * I + sum_t (c_t + d_t * E[e]) * Src_t[e] over b x b blocks,
-// idc(e) = idc0 + idc1 * E[e].  Null sources are skipped; E may be null when
-// every d_t and idc1 is zero.
-struct LinComb {
+// ---- elementwise ------------------------------------------------------------
+// D[e] = idc(e) I + sum_t (c_t + d_t E[e]) Src_t[e]; idc(e) = idc0 + idc1 E[e].
+struct LinCombDesc {
   const void* src[3];
   long long sSrc[3];
   zc c[3], d[3];
   zc idc0, idc1;
   void* D;
   long long sD;
-  const double* E;   // device array, [batch]
+  const double* E;     // device, [batch] (may be null if unused)
+  int b;
+  int batch;
 };
-hipError_t launch_lincomb(int b, int batch, const LinComb& a, hipStream_t s);
-
-// D[e] = a * C[e] + z * Z[e] + g * Z[e]^dagger  (C or Z may be null when its
-// coefficient is zero; C may equal D; Z must not alias D unless g == 0).
-struct TransComb {
+constexpr int kLinChunk = 2048;      // elements per workgroup
+// D[e] = a C[e] + z Z[e] + g Z[e]^dagger (32 x 32 tiles through LDS).
+struct TransDesc {
   const void* C;
   const void* Z;
   void* D;
   long long sC, sZ, sD;
   zc a, z, g;
+  int b;
+  int batch;
 };
-hipError_t launch_transcomb(int b, int batch, const TransComb& t, hipStream_t s);
+constexpr int kTransTile = 32;
+hipError_t launch_lincomb(const FlatLaunch& l, hipStream_t s);
+hipError_t launch_transcomb(const FlatLaunch& l, hipStream_t s);
 
-// Count of non-finite entries over `count` complex128 values (device),
-// accumulated into *flag (device int).
-hipError_t launch_nonfinite_scan(const void* p, long long count, int* flag,
-                                 hipStream_t s);
+// workgroups per matrix of the elementwise kernels
+__host__ __device__ inline int lincomb_chunks(int b) { return (int)(((long long)b * b + kLinChunk - 1) / kLinChunk); }
+__host__ __device__ inline int trans_tiles(int b) {
+  const int t = (b + kTransTile - 1) / kTransTile;
+  return t * t;
+}
+
+// Device-side binary search of the descriptor owning workgroup w.
+__device__ __forceinline__ int find_desc(const int* prefix, int nd, int w) {
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= w) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
 
 }  // namespace qtx

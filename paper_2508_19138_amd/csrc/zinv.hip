@@ -15,22 +15,18 @@
 // every other column j is then the rank-kPanel update
 //     A[:, j] += Panel''[:, :] * A[pivot rows, j]
 // where Panel'' equals the eliminated panel except that 1 is subtracted at
-// each (pivot row, its column).  That update is one complex GEMM on the
-// matrix cores (beta = 1, in place).  The gathered pivot rows have their
-// panel columns set to zero, so the panel columns pass through unchanged.
+// each (pivot row, its column).  That update is a complex GEMM on the matrix
+// cores (beta = 1, in place) issued by the host between panel launches.  The
+// gathered pivot rows have their panel columns set to zero, so the panel
+// columns pass through the update unchanged.
 #include "qtx_internal.h"
 
 namespace qtx {
 namespace {
 
-constexpr int kInvThreads = 256;
-
 template <int R>
 __global__ __launch_bounds__(kInvThreads)
-void gj_panel_kernel(double2* __restrict__ S, long long sS, int b, int k0,
-                     double2* __restrict__ panel, double2* __restrict__ brow,
-                     int* __restrict__ perm, int* __restrict__ used,
-                     int* __restrict__ info, int code_base) {
+void gj_panel_kernel(FlatLaunch L, int k0) {
   constexpr int NB = kPanel;
   __shared__ double redv[kInvThreads / 64];
   __shared__ int redr[kInvThreads / 64];
@@ -38,14 +34,18 @@ void gj_panel_kernel(double2* __restrict__ S, long long sS, int b, int k0,
   __shared__ double2 prow[NB];
   __shared__ int pivs[NB];
 
-  const int e = blockIdx.x;
+  const int di = find_desc(L.prefix, L.nd, blockIdx.x);
+  const InvDesc& d = ((const InvDesc*)L.desc)[di];
+  const int e = blockIdx.x - L.prefix[di];
+  const int b = d.b;
+  if (k0 >= b) return;                       // this matrix has no such panel
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  double2* A = S + e * sS;
-  int* pe = perm + (long long)e * b;
-  int* ue = used + (long long)e * b;
-  double2* pan = panel + (long long)e * b * NB;
-  double2* br = brow + (long long)e * NB * b;
+  double2* A = (double2*)d.S + e * d.sS;
+  int* pe = d.perm + (long long)e * b;
+  int* ue = d.used + (long long)e * b;
+  double2* pan = (double2*)d.panel + (long long)e * b * NB;
+  double2* br = (double2*)d.brow + (long long)e * NB * b;
   const int nbe = min(NB, b - k0);
 
   double2 a[R][NB];
@@ -67,7 +67,7 @@ void gj_panel_kernel(double2* __restrict__ S, long long sS, int b, int k0,
     }
   }
 
-  int first_bad = 0;   // set by thread 0 only
+  int first_bad = 0;   // meaningful in thread 0 only
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     if (c >= nbe) continue;      // uniform across the workgroup
@@ -102,10 +102,12 @@ void gj_panel_kernel(double2* __restrict__ S, long long sS, int b, int k0,
       if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
       bad |= redbad[w];
     }
-    // bi is a valid unused row whenever b - k0 - c > 0 rows remain unused.
+    // An unused row always remains (b - k0 - c > 0), so bi is a valid row
+    // unless every candidate was non-finite; then row 0 keeps indices in
+    // range and the failure is reported through info.
     const int p = (bi == 0x7fffffff) ? 0 : bi;
     if (t == 0 && first_bad == 0) {
-      const int code = code_base > 0 ? code_base : 1 + k0 + c;
+      const int code = d.code > 0 ? d.code : 1 + k0 + c;
       if (bad) first_bad = -code;
       else if (bv <= 0.0) first_bad = code;
     }
@@ -158,7 +160,11 @@ void gj_panel_kernel(double2* __restrict__ S, long long sS, int b, int k0,
   }
   if (t == 0) {
     for (int c = 0; c < nbe; ++c) pe[k0 + c] = pivs[c];
-    if (info && first_bad != 0 && info[e] == 0) info[e] = first_bad;
+    if (d.info) {
+      int* inf = d.info + e;
+      const int cur = (k0 == 0 && d.reset_info) ? 0 : *inf;
+      if (cur == 0) *inf = first_bad;
+    }
   }
   // gathered pivot rows of the original matrix (panel columns zeroed)
   for (int c = 0; c < NB; ++c) {
@@ -171,16 +177,19 @@ void gj_panel_kernel(double2* __restrict__ S, long long sS, int b, int k0,
   }
 }
 
-// X[k][c] = Y[p_k][pinv(c)] with pinv(p_j) = j.
+// X[k][c] = Y[p_k][pinv(c)] with pinv(p_j) = j; kPermRows rows per workgroup.
 __global__ __launch_bounds__(256)
-void gj_permute_kernel(const double2* __restrict__ Y, long long sY,
-                       double2* __restrict__ X, long long sX, int b,
-                       const int* __restrict__ perm, int rows_per_block) {
-  extern __shared__ int sh[];
-  int* pinv = sh;
-  int* pk = sh + b;
-  const int e = blockIdx.y;
-  const int* pe = perm + (long long)e * b;
+void gj_permute_kernel(FlatLaunch L) {
+  __shared__ int pinv[1024];
+  __shared__ int pk[1024];
+  const int di = find_desc(L.prefix, L.nd, blockIdx.x);
+  const InvDesc& d = ((const InvDesc*)L.desc)[di];
+  const int b = d.b;
+  const int chunks = (b + kPermRows - 1) / kPermRows;
+  const int local = blockIdx.x - L.prefix[di];
+  const int e = local / chunks;
+  const int r0 = (local % chunks) * kPermRows;
+  const int* pe = d.perm + (long long)e * b;
   // Pivots are distinct rows unless a non-finite column was met (flagged
   // through info); starting from the identity keeps every index in range.
   for (int j = threadIdx.x; j < b; j += blockDim.x) {
@@ -191,10 +200,9 @@ void gj_permute_kernel(const double2* __restrict__ Y, long long sY,
   __syncthreads();
   for (int j = threadIdx.x; j < b; j += blockDim.x) pinv[pk[j]] = j;
   __syncthreads();
-  const double2* Ye = Y + e * sY;
-  double2* Xe = X + e * sX;
-  const int r0 = blockIdx.x * rows_per_block;
-  const int r1 = min(b, r0 + rows_per_block);
+  const double2* Ye = (const double2*)d.S + e * d.sS;
+  double2* Xe = (double2*)d.X + e * d.sX;
+  const int r1 = min(b, r0 + kPermRows);
   for (int k = r0; k < r1; ++k) {
     const long long src = (long long)pk[k] * b;
     for (int c = threadIdx.x; c < b; c += blockDim.x)
@@ -202,52 +210,23 @@ void gj_permute_kernel(const double2* __restrict__ Y, long long sY,
   }
 }
 
-template <int R>
-hipError_t launch_panel(int b, void* S, long long sS, int k0, int batch,
-                        const InvWork& w, int* info, int code_base,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(gj_panel_kernel<R>, dim3(batch), dim3(kInvThreads), 0, s,
-                     (double2*)S, sS, b, k0, (double2*)w.panel,
-                     (double2*)w.brow, w.perm, w.used, info, code_base);
+}  // namespace
+
+hipError_t launch_inv_panel(int R, int k0, const FlatLaunch& l, hipStream_t s) {
+  if (l.total <= 0) return hipSuccess;
+  switch (R) {
+    case 1: hipLaunchKernelGGL(gj_panel_kernel<1>, dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
+    case 2: hipLaunchKernelGGL(gj_panel_kernel<2>, dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
+    case 3: hipLaunchKernelGGL(gj_panel_kernel<3>, dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
+    case 4: hipLaunchKernelGGL(gj_panel_kernel<4>, dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_zinv(int b, void* S, long long sS, void* X, long long sX,
-                       int batch, const InvWork& w, int* info, int code_base,
-                       hipStream_t s) {
-  if (batch <= 0 || b <= 0) return hipSuccess;
-  const int R = (b + kInvThreads - 1) / kInvThreads;
-  if (R > 4) return hipErrorInvalidValue;     // b <= 1024
-  for (int k0 = 0; k0 < b; k0 += kPanel) {
-    hipError_t err;
-    switch (R) {
-      case 1: err = launch_panel<1>(b, S, sS, k0, batch, w, info, code_base, s); break;
-      case 2: err = launch_panel<2>(b, S, sS, k0, batch, w, info, code_base, s); break;
-      case 3: err = launch_panel<3>(b, S, sS, k0, batch, w, info, code_base, s); break;
-      default: err = launch_panel<4>(b, S, sS, k0, batch, w, info, code_base, s); break;
-    }
-    if (err != hipSuccess) return err;
-    if (b > kPanel) {
-      GemmArgs g{};
-      g.M = b; g.N = b; g.K = kPanel;
-      g.lda = kPanel; g.ldb = b; g.ldc = b; g.ldd = b;
-      g.batch = batch; g.ngroups = 1;
-      g.g[0].A = w.panel; g.g[0].sA = (long long)b * kPanel;
-      g.g[0].B = w.brow;  g.g[0].sB = (long long)kPanel * b;
-      g.g[0].C = S;       g.g[0].sC = sS;
-      g.g[0].D = S;       g.g[0].sD = sS;
-      g.g[0].alpha = zc{1.0, 0.0};
-      g.g[0].beta = zc{1.0, 0.0};
-      err = launch_zgemm('N', 'N', g, s);
-      if (err != hipSuccess) return err;
-    }
-  }
-  const int rpb = 8;
-  dim3 grid((b + rpb - 1) / rpb, batch);
-  hipLaunchKernelGGL(gj_permute_kernel, grid, dim3(256), 2 * b * sizeof(int), s,
-                     (const double2*)S, sS, (double2*)X, sX, b, w.perm, rpb);
+hipError_t launch_inv_permute(const FlatLaunch& l, hipStream_t s) {
+  if (l.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gj_permute_kernel, dim3(l.total), dim3(256), 0, s, l);
   return hipGetLastError();
 }
 
