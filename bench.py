@@ -47,6 +47,9 @@ def parse():
                     help="energies in the CPU-oracle sample (0 = skip)")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-launch HIP events")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, copy a 1 GiB device buffer three times "
+                         "(reference kernel for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -149,6 +152,14 @@ def main():
         inv = ctx.kernel_stats("inverse")
         elem = ctx.kernel_stats("elementwise")
     ctx.close()
+    if args.copy_calibration:
+        x = torch.empty(1 << 26, dtype=torch.complex128, device="cuda:0")   # 1 GiB
+        x.fill_(1.0)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
 
     cpu = None
     if args.cpu_energies > 0:

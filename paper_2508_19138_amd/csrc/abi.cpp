@@ -529,16 +529,20 @@ qtx_status qtx_rgf_zinv(qtx_rgf_ctx* c, int32_t b, void* A, void* X, int32_t* in
   try {
     HIPCHK(c, hipSetDevice(c->device));
     const size_t pan = (size_t)batch * b * kPanel * 16;
+    const size_t span = (size_t)batch * b * kSuper * 16;
     const size_t ints = (size_t)batch * b * 4;
-    HIPCHK(c, hipMalloc(&work, 2 * pan + 2 * ints + 1024));
+    HIPCHK(c, hipMalloc(&work, 2 * pan + 2 * span + 2 * ints + 4096));
     Lane L;
     InvDesc d{};
     d.S = A; d.sS = (long long)b * b;
     d.X = X; d.sX = (long long)b * b;
-    d.panel = work;
-    d.brow = (char*)work + pan;
-    d.perm = (int*)((char*)work + 2 * pan);
-    d.used = (int*)((char*)work + 2 * pan + ints);
+    char* w = (char*)work;
+    d.panel = w;
+    d.brow = w + pan;
+    d.spanel = w + 2 * pan;
+    d.sbrow = w + 2 * pan + span;
+    d.perm = (int*)(w + 2 * pan + 2 * span);
+    d.used = (int*)(w + 2 * pan + 2 * span + ints);
     d.info = info; d.code = 0; d.reset_info = 1;
     d.b = b; d.batch = batch;
     L.id.push_back(d);

@@ -77,14 +77,16 @@ class Emitter {
   }
 
   void inverse(const View& S, long long is, const View& X, long long ix, void* panel,
-               void* brow, int* perm, int* used, int* info, int code, bool reset) {
+               void* brow, void* spanel, void* sbrow, int* perm, int* used, int* info,
+               int code, bool reset) {
     Op o;
     o.k = OpK::Inv;
     o.first = (int)L_.id.size();
     InvDesc d{};
     d.S = S.w(is); d.sS = S.es;
     d.X = X.w(ix); d.sX = X.es;
-    d.panel = panel; d.brow = brow; d.perm = perm; d.used = used;
+    d.panel = panel; d.brow = brow; d.spanel = spanel; d.sbrow = sbrow;
+    d.perm = perm; d.used = used;
     d.info = info; d.code = code; d.reset_info = reset ? 1 : 0;
     d.b = b_; d.batch = ec_;
     L_.id.push_back(d);
@@ -162,7 +164,7 @@ struct Core {
   View xR;                 // workspace [n] per energy
   View tS, tF, tP, tM, tR; // workspace, one block per energy
   View tG[2], tW[2], tY[2];
-  void *panel = nullptr, *brow = nullptr;
+  void *panel = nullptr, *brow = nullptr, *spanel = nullptr, *sbrow = nullptr;
   int *perm = nullptr, *used = nullptr, *info = nullptr;
 };
 
@@ -173,7 +175,8 @@ void run_core(Emitter& s, const Core& k, PrepDiag prep_diag) {
   const int nr = (int)k.rhs.size();
   const zc su = rs(k.su), sl = rs(k.sl);
   auto inv = [&](int i) {
-    s.inverse(k.tS, 0, k.xR, i, k.panel, k.brow, k.perm, k.used, k.info, i + 1, i == 0);
+    s.inverse(k.tS, 0, k.xR, i, k.panel, k.brow, k.spanel, k.sbrow, k.perm, k.used, k.info,
+              i + 1, i == 0);
   };
 
   // ---- forward pass ----------------------------------------------------
@@ -380,7 +383,7 @@ View in_view(const void* p, long long es, long long bs) {
 struct Layout {
   View xR, tS, tF, tP, tM, tR, tG[2], tW[2], tY[2], Uw, Lw;
   View Ad, Bd[2], Bu[2], Tm1, T0, Tp1, Tp2;
-  void *panel, *brow;
+  void *panel, *brow, *spanel, *sbrow;
   int *perm, *used;
   size_t bytes;
 };
@@ -407,6 +410,8 @@ Layout carve_layout(const Plan& q, int ec, char* ws) {
   if (q.general_ul && n > 1) { L.Uw = blocks(n - 1); L.Lw = blocks(n - 1); }
   L.panel = cv.take((size_t)ec * b * kPanel * 16);
   L.brow = cv.take((size_t)ec * b * kPanel * 16);
+  L.spanel = cv.take((size_t)ec * b * kSuper * 16);
+  L.sbrow = cv.take((size_t)ec * b * kSuper * 16);
   L.perm = (int*)cv.take((size_t)ec * b * 4);
   L.used = (int*)cv.take((size_t)ec * b * 4);
   if (q.is_w) {
@@ -487,7 +492,8 @@ void build_lane(Lane& lane, const qtx_rgf_problem& p, const Plan& q, char* ws,
   k.xR = lay.xR;
   k.tS = lay.tS; k.tF = lay.tF; k.tP = lay.tP; k.tM = lay.tM; k.tR = lay.tR;
   for (int r = 0; r < 2; ++r) { k.tG[r] = lay.tG[r]; k.tW[r] = lay.tW[r]; k.tY[r] = lay.tY[r]; }
-  k.panel = lay.panel; k.brow = lay.brow; k.perm = lay.perm; k.used = lay.used;
+  k.panel = lay.panel; k.brow = lay.brow; k.spanel = lay.spanel; k.sbrow = lay.sbrow;
+  k.perm = lay.perm; k.used = lay.used;
   k.info = d_info + e0;
   k.XRd = outv(p.XR.diag, n);
   k.XRu = outv(p.XR.upper, n - 1);

@@ -197,8 +197,10 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
     return;
   }
   if (f.k == OpK::Inv) {
-    // panels k0 = 0, kPanel, ... up to the largest block, each followed by
-    // its rank-kPanel update; one permutation at the end
+    // two-level blocked Gauss-Jordan (see zinv.hip): per super-panel, its
+    // panels each followed by a rank-kPanel update of the super-panel, then
+    // the gather and one rank-kSuper update of the whole matrix; one
+    // permutation at the end
     std::vector<InvDesc> all;
     double fl = 0;
     for (auto& lo : ops) {
@@ -208,38 +210,75 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
     int maxb = 0;
     for (auto& v : all) maxb = std::max(maxb, v.b);
     const int R = (maxb + kInvThreads - 1) / kInvThreads;
-    for (int k0 = 0; k0 < maxb; k0 += kPanel) {
+    bool first = true;
+    for (int K0 = 0; K0 < maxb; K0 += kSuper) {
+      for (int k0 = K0; k0 < std::min(K0 + kSuper, maxb); k0 += kPanel) {
+        std::vector<InvDesc> d;
+        std::vector<int> pre(1, 0);
+        std::vector<GemmDesc> gd;
+        std::vector<int> gpre(1, 0);
+        double by = 0, gby = 0;
+        for (const InvDesc& v : all) {
+          if (v.b <= k0) continue;
+          d.push_back(v);
+          pre.push_back(pre.back() + v.batch);
+          by += 16.0 * 3.0 * v.b * kPanel * v.batch;
+          const int hi = std::min(v.b, K0 + kSuper);
+          const int nbe = std::min(kPanel, v.b - k0);
+          if (hi - K0 > nbe) {
+            GemmDesc g{};
+            g.M = v.b; g.N = hi - K0; g.K = kPanel;
+            g.A = v.panel; g.sA = (long long)v.b * kPanel; g.lda = kPanel;
+            g.B = (double2*)v.brow + K0; g.sB = (long long)kPanel * v.b; g.ldb = v.b;
+            g.C = (double2*)v.S + K0; g.sC = v.sS; g.ldc = v.b;
+            g.D = (double2*)v.S + K0; g.sD = v.sS; g.ldd = v.b;
+            g.alpha = zc{1.0, 0.0};
+            g.beta = zc{1.0, 0.0};
+            g.batch = v.batch; g.batch2 = 1;
+            g.tiles = gemm_tiles(0, g.M, g.N);
+            gd.push_back(g);
+            gpre.push_back(gpre.back() + g.tiles * g.batch);
+            gby += 16.0 * 2.0 * g.M * (double)g.N * g.batch;
+          }
+        }
+        recs_.push_back(LaunchRec{LaunchRec::Panel, 'N', 'N', false, R, k0, put(d), put_prefix(pre),
+                                  (int)d.size(), pre.back(), kClassInv, (first ? fl : 0.0), by});
+        first = false;
+        if (!gd.empty())
+          recs_.push_back(LaunchRec{LaunchRec::Gemm, 'N', 'N', false, kGemmInvUpdate, k0, put(gd),
+                                    put_prefix(gpre), (int)gd.size(), gpre.back(), kClassInv, 0.0, gby});
+      }
+      // gather + rank-kSuper update for matrices larger than one super-panel
       std::vector<InvDesc> d;
       std::vector<int> pre(1, 0);
       std::vector<GemmDesc> gd;
       std::vector<int> gpre(1, 0);
       double by = 0, gby = 0;
       for (const InvDesc& v : all) {
-        if (v.b <= k0) continue;
+        if (v.b <= K0 || v.b <= kSuper) continue;
         d.push_back(v);
-        pre.push_back(pre.back() + v.batch);
-        by += 16.0 * 3.0 * v.b * kPanel * v.batch;
-        if (v.b > kPanel) {
-          GemmDesc g{};
-          g.M = v.b; g.N = v.b; g.K = kPanel;
-          g.A = v.panel; g.sA = (long long)v.b * kPanel; g.lda = kPanel;
-          g.B = v.brow; g.sB = (long long)kPanel * v.b; g.ldb = v.b;
-          g.C = v.S; g.sC = v.sS; g.ldc = v.b;
-          g.D = v.S; g.sD = v.sS; g.ldd = v.b;
-          g.alpha = zc{1.0, 0.0};
-          g.beta = zc{1.0, 0.0};
-          g.batch = v.batch; g.batch2 = 1;
-          g.tiles = gemm_tiles(0, v.b, v.b);
-          gd.push_back(g);
-          gpre.push_back(gpre.back() + g.tiles * g.batch);
-          gby += 16.0 * 2.0 * g.M * (double)g.N * g.batch;
-        }
+        pre.push_back(pre.back() + v.batch * super_gather_chunks(v.b));
+        by += 16.0 * 3.0 * v.b * kSuper * v.batch;
+        GemmDesc g{};
+        g.M = v.b; g.N = v.b; g.K = kSuper;
+        g.A = v.spanel; g.sA = (long long)v.b * kSuper; g.lda = kSuper;
+        g.B = v.sbrow; g.sB = (long long)kSuper * v.b; g.ldb = v.b;
+        g.C = v.S; g.sC = v.sS; g.ldc = v.b;
+        g.D = v.S; g.sD = v.sS; g.ldd = v.b;
+        g.alpha = zc{1.0, 0.0};
+        g.beta = zc{1.0, 0.0};
+        g.batch = v.batch; g.batch2 = 1;
+        g.tiles = gemm_tiles(0, g.M, g.N);
+        gd.push_back(g);
+        gpre.push_back(gpre.back() + g.tiles * g.batch);
+        gby += 16.0 * 2.0 * g.M * (double)g.N * g.batch;
       }
-      recs_.push_back(LaunchRec{LaunchRec::Panel, 'N', 'N', false, R, k0, put(d), put_prefix(pre),
-                                (int)d.size(), pre.back(), kClassInv, (k0 == 0 ? fl : 0.0), by});
-      if (!gd.empty())
-        recs_.push_back(LaunchRec{LaunchRec::Gemm, 'N', 'N', false, kGemmInvUpdate, k0, put(gd), put_prefix(gpre),
-                                  (int)gd.size(), gpre.back(), kClassInv, 0.0, gby});
+      if (!d.empty()) {
+        recs_.push_back(LaunchRec{LaunchRec::Gather, 'N', 'N', false, 0, K0, put(d), put_prefix(pre),
+                                  (int)d.size(), pre.back(), kClassInv, 0.0, by});
+        recs_.push_back(LaunchRec{LaunchRec::Gemm, 'N', 'N', false, kGemmInvUpdate, K0, put(gd),
+                                  put_prefix(gpre), (int)gd.size(), gpre.back(), kClassInv, 0.0, gby});
+      }
     }
     std::vector<int> pre(1, 0);
     double by = 0;
@@ -336,6 +375,7 @@ void Executor::issue(char* base, bool profile) {
       case LaunchRec::Gemm: XCHK(launch_gemm(r.cfg, r.fp32, r.opa, r.opb, l, s_)); break;
       case LaunchRec::Panel: XCHK(launch_inv_panel(r.cfg, r.k0, l, s_)); break;
       case LaunchRec::Permute: XCHK(launch_inv_permute(l, s_)); break;
+      case LaunchRec::Gather: XCHK(launch_inv_super_gather(r.k0, l, s_)); break;
       case LaunchRec::Lin: XCHK(launch_lincomb(l, s_)); break;
       case LaunchRec::Trans: XCHK(launch_transcomb(l, s_)); break;
     }

@@ -74,7 +74,7 @@ class Tuner {
 
 // One kernel launch of a merged schedule.
 struct LaunchRec {
-  enum Kind : uint8_t { Gemm, Panel, Permute, Lin, Trans } kind;
+  enum Kind : uint8_t { Gemm, Panel, Gather, Permute, Lin, Trans } kind;
   char opa, opb;
   bool fp32;
   int cfg;        // gemm tile config, or rows-per-thread R for Panel

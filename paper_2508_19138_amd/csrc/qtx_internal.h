@@ -61,11 +61,13 @@ hipError_t launch_gemm(int cfg, bool fp32, char opa, char opb,
 
 // ---- Gauss-Jordan inverse with partial pivoting -----------------------------
 constexpr int kPanel = 16;     // columns factored per panel step
+constexpr int kSuper = 64;     // columns per super-panel (two-level blocking)
 constexpr int kInvThreads = 256;
 
 // `batch` matrices S[e] (b x b, stride sS) are eliminated in place; the
-// inverses go to X[e] (stride sX).  Per matrix work: panel [b][kPanel],
-// brow [kPanel][b], perm [b], used [b] (strides b*kPanel, kPanel*b, b, b).
+// inverses go to X[e] (stride sX).  Per-matrix work buffers (element strides
+// in brackets): panel [b*kPanel], brow [kPanel*b], spanel [b*kSuper],
+// sbrow [kSuper*b] (complex128), perm [b], used [b] (int).
 // info[e]: 0, or set once to +code (zero pivot) / -code (non-finite pivot);
 // `reset_info` clears it at the first panel.  code <= 0 means 1 + column.
 struct InvDesc {
@@ -74,6 +76,8 @@ struct InvDesc {
   long long sS, sX;
   void* panel;
   void* brow;
+  void* spanel;
+  void* sbrow;
   int* perm;
   int* used;
   int* info;
@@ -82,9 +86,23 @@ struct InvDesc {
   int b;
   int batch;
 };
+// Bytes of inverse work buffers per matrix of size b.
+inline size_t inv_work_bytes(int b) {
+  return (size_t)b * (2 * kPanel + 2 * kSuper) * 16 + (size_t)b * 8;
+}
 // Panel factorisation of columns [k0, k0 + kPanel) of every matrix with
-// b > k0 (one workgroup per matrix); R = rows per thread, b <= 256 R.
+// b > k0 (one workgroup per matrix); R = rows per thread, b <= 256 R.  The
+// pivot rows are gathered into brow for the columns [k0 & ~(kSuper-1),
+// + kSuper) of the current super-panel.
 hipError_t launch_inv_panel(int R, int k0, const FlatLaunch& l, hipStream_t s);
+// After the last panel of the super-panel starting at K0: spanel = the
+// eliminated super-panel columns minus the identity at their pivot rows,
+// sbrow = the pivot rows outside the super-panel (zero inside).
+constexpr int kGatherItems = 2048;   // elements per workgroup
+hipError_t launch_inv_super_gather(int K0, const FlatLaunch& l, hipStream_t s);
+__host__ __device__ inline int super_gather_chunks(int b) {
+  return (int)((2LL * b * kSuper + kGatherItems - 1) / kGatherItems);
+}
 // Final permutation X[k][p_j] = S[p_k][j]; 8 rows per workgroup.
 constexpr int kPermRows = 8;
 hipError_t launch_inv_permute(const FlatLaunch& l, hipStream_t s);

@@ -9,16 +9,19 @@
 // and A^{-1} = (P A)^{-1} P, i.e.  A^{-1}[k][p_j] = Y[p_k][j]; the final
 // kernel applies that permutation while copying into the destination.
 //
-// Blocking: the columns are processed in panels of kPanel.  One workgroup
-// per matrix factors the panel (rows held in registers, one row per thread
-// and pass), producing the eliminated panel columns in place.  The effect on
-// every other column j is then the rank-kPanel update
-//     A[:, j] += Panel''[:, :] * A[pivot rows, j]
-// where Panel'' equals the eliminated panel except that 1 is subtracted at
-// each (pivot row, its column).  That update is a complex GEMM on the matrix
-// cores (beta = 1, in place) issued by the host between panel launches.  The
-// gathered pivot rows have their panel columns set to zero, so the panel
-// columns pass through the update unchanged.
+// Blocking, two levels.  Eliminating a set K of columns with pivot rows pK
+// changes every other column j by the rank-|K| update
+//     A[:, j] += Panel''[:, K] * A[pK, j]
+// where Panel'' is the eliminated block of columns minus the identity at the
+// (pivot row, column) positions; this holds however the columns of K were
+// eliminated.  So the columns are taken in super-panels of kSuper, each made
+// of panels of kPanel.  One workgroup per matrix factors a panel (rows held
+// in registers, one row per thread and pass) and gathers its pivot rows
+// restricted to the super-panel; a rank-kPanel product updates the rest of
+// the super-panel only.  After the last panel, the eliminated super-panel
+// and its pivot rows outside it are gathered and one rank-kSuper product on
+// the matrix cores updates the whole matrix.  Gathered pivot rows carry
+// zeros in the columns being eliminated, so those pass through unchanged.
 #include "qtx_internal.h"
 
 namespace qtx {
@@ -47,6 +50,8 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
   double2* pan = (double2*)d.panel + (long long)e * b * NB;
   double2* br = (double2*)d.brow + (long long)e * NB * b;
   const int nbe = min(NB, b - k0);
+  const int lo = k0 - k0 % kSuper;                // current super-panel
+  const int hi = min(b, lo + kSuper);
 
   double2 a[R][NB];
   int u[R];      // row already used as a pivot
@@ -166,13 +171,53 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
       if (cur == 0) *inf = first_bad;
     }
   }
-  // gathered pivot rows of the original matrix (panel columns zeroed)
+  // pivot rows within the super-panel (this panel's columns zeroed)
   for (int c = 0; c < NB; ++c) {
     const int p = (c < nbe) ? pivs[c] : -1;
-    for (int j = t; j < b; j += kInvThreads) {
+    for (int j = lo + t; j < hi; j += kInvThreads) {
       double2 v = make_double2(0.0, 0.0);
       if (p >= 0 && (j < k0 || j >= k0 + nbe)) v = A[(long long)p * b + j];
       br[(long long)c * b + j] = v;
+    }
+  }
+}
+
+// spanel[r][c] = A[r][K0 + c] - (r == p_{K0+c}),  sbrow[c][j] = A[p_{K0+c}][j]
+// outside [K0, K0 + kSuper) and 0 inside; c beyond the matrix are zero.
+__global__ __launch_bounds__(256)
+void gj_super_gather_kernel(FlatLaunch L, int K0) {
+  const int di = find_desc(L.prefix, L.nd, blockIdx.x);
+  const InvDesc& d = ((const InvDesc*)L.desc)[di];
+  const int b = d.b;
+  const int chunks = super_gather_chunks(b);
+  const int local = blockIdx.x - L.prefix[di];
+  const long long e = local / chunks;
+  const long long q0 = (long long)(local % chunks) * kGatherItems;
+  const double2* A = (const double2*)d.S + e * d.sS;
+  const int* pe = d.perm + e * b;
+  double2* sp = (double2*)d.spanel + e * (long long)b * kSuper;
+  double2* sb = (double2*)d.sbrow + e * (long long)kSuper * b;
+  const int spe = min(kSuper, b - K0);
+  const long long half = (long long)b * kSuper;
+  const long long q1 = min(q0 + kGatherItems, 2 * half);
+  for (long long q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+    if (q < half) {
+      const int r = (int)(q / kSuper), c = (int)(q % kSuper);
+      double2 v = make_double2(0.0, 0.0);
+      if (c < spe) {
+        v = A[(long long)r * b + K0 + c];
+        if (pe[K0 + c] == r) v.x -= 1.0;
+      }
+      sp[q] = v;
+    } else {
+      const long long qq = q - half;
+      const int c = (int)(qq / b), j = (int)(qq % b);
+      double2 v = make_double2(0.0, 0.0);
+      if (c < spe && (j < K0 || j >= K0 + spe)) {
+        const int p = pe[K0 + c];
+        if (p >= 0 && p < b) v = A[(long long)p * b + j];
+      }
+      sb[qq] = v;
     }
   }
 }
@@ -221,6 +266,12 @@ hipError_t launch_inv_panel(int R, int k0, const FlatLaunch& l, hipStream_t s) {
     case 4: hipLaunchKernelGGL(gj_panel_kernel<4>, dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_inv_super_gather(int K0, const FlatLaunch& l, hipStream_t s) {
+  if (l.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gj_super_gather_kernel, dim3(l.total), dim3(256), 0, s, l, K0);
   return hipGetLastError();
 }
 
