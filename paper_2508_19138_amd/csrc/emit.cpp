@@ -159,6 +159,11 @@ struct Core {
   int n = 0;
   View U, L;               // U_i = su * U[i], L_i = sl * L[i]
   double su = 1.0, sl = 1.0;
+  // Optional stored adjoints: U_i = (suh * Uh[i])^dag, L_i = (slh * Lh[i])^dag.
+  // With them every product with U or L reads its other operand in the
+  // orientation the matrix cores handle fastest (see Src below).
+  View Uh, Lh;
+  double suh = 1.0, slh = 1.0;
   std::vector<Rhs> rhs;
   View XRd, XRu, XRl;
   View xR;                 // workspace [n] per energy
@@ -168,59 +173,112 @@ struct Core {
   int *perm = nullptr, *used = nullptr, *info = nullptr;
 };
 
+// One product operand: value = sg * op(v[i]), op = 'N' (as stored) or 'C'
+// (adjoint of the stored block).  Products whose operands are both stored
+// as-is run markedly slower on the matrix-core kernel than products with one
+// adjoint operand (measured on gfx950), so operands that have an exact
+// adjoint relation are read through it: anti-Hermitian blocks
+// (B^s, x^s_i, X^s_i and the bracket W of the forward step, B = -B^dag) and
+// the couplings U, L of a Hermitian H (U = -H_u = (-H_l)^dag, L = (-H_u)^dag).
+struct Src {
+  View v;
+  long long i;
+  char op;
+  double sg;
+};
+inline Src SN(const View& v, long long i, double sg = 1.0) { return Src{v, i, 'N', sg}; }
+inline Src SC(const View& v, long long i, double sg = 1.0) { return Src{v, i, 'C', sg}; }
+// anti-Hermitian block as an operand: B = -B^dag
+inline Src SAH(const View& v, long long i) { return Src{v, i, 'C', -1.0}; }
+
+struct Prod {             // D = alpha * a b + beta * C
+  View D;
+  long long id;
+  Src a, b;
+  const View* C;
+  long long ic;
+  double alpha, beta;
+};
+
+// Emit independent products; those sharing operand ops share one operation.
+void prods(Emitter& s, std::initializer_list<Prod> ps) {
+  const char combos[4][2] = {{'N', 'N'}, {'N', 'C'}, {'C', 'N'}, {'C', 'C'}};
+  for (const auto& cb : combos) {
+    Term t[4];
+    int cnt = 0;
+    for (const Prod& p : ps) {
+      if (p.a.op != cb[0] || p.b.op != cb[1]) continue;
+      t[cnt++] = Term{{p.a.v, p.a.i}, {p.b.v, p.b.i}, p.C, p.ic, p.D, p.id,
+                      rs(p.alpha * p.a.sg * p.b.sg), rs(p.beta)};
+    }
+    if (cnt == 1) s.gemm(cb[0], cb[1], {t[0]});
+    else if (cnt == 2) s.gemm(cb[0], cb[1], {t[0], t[1]});
+    else if (cnt == 3) s.gemm(cb[0], cb[1], {t[0], t[1], t[2]});
+    else if (cnt == 4) s.gemm(cb[0], cb[1], {t[0], t[1], t[2], t[3]});
+  }
+}
+
 // Forward and backward passes, given a callback that writes Mt_ii into tS.
 template <class PrepDiag>
 void run_core(Emitter& s, const Core& k, PrepDiag prep_diag) {
   const int n = k.n;
   const int nr = (int)k.rhs.size();
-  const zc su = rs(k.su), sl = rs(k.sl);
+  const bool uh = k.Uh.ok(), lh = k.Lh.ok();
+  auto Ur = [&](long long i) { return uh ? SC(k.Uh, i, k.suh) : SN(k.U, i, k.su); };   // U_i
+  auto Lr = [&](long long i) { return lh ? SC(k.Lh, i, k.slh) : SN(k.L, i, k.sl); };   // L_i
+  auto LHr = [&](long long i) { return lh ? SN(k.Lh, i, k.slh) : SC(k.L, i, k.sl); };  // L_i^dag
   auto inv = [&](int i) {
     s.inverse(k.tS, 0, k.xR, i, k.panel, k.brow, k.spanel, k.sbrow, k.perm, k.used, k.info,
               i + 1, i == 0);
   };
+  const View* none = nullptr;
 
   // ---- forward pass ----------------------------------------------------
   prep_diag(0);
   inv(0);
-  if (nr == 2) {
-    s.gemm('N', 'N', {Term{{k.xR, 0}, {k.rhs[0].Bd, 0}, nullptr, 0, k.tG[0], 0, kOne, kZero},
-                      Term{{k.xR, 0}, {k.rhs[1].Bd, 0}, nullptr, 0, k.tG[1], 0, kOne, kZero}});
-    s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.xR, 0}, nullptr, 0, k.rhs[0].Xd, 0, kOne, kZero},
-                      Term{{k.tG[1], 0}, {k.xR, 0}, nullptr, 0, k.rhs[1].Xd, 0, kOne, kZero}});
-  } else if (nr == 1) {
-    s.gemm('N', 'N', {Term{{k.xR, 0}, {k.rhs[0].Bd, 0}, nullptr, 0, k.tG[0], 0, kOne, kZero}});
-    s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.xR, 0}, nullptr, 0, k.rhs[0].Xd, 0, kOne, kZero}});
+  if (nr >= 1) {
+    // x^s_0 = x_0 B_00 x_0^dag
+    if (nr == 2)
+      prods(s, {Prod{k.tG[0], 0, SN(k.xR, 0), SAH(k.rhs[0].Bd, 0), none, 0, 1.0, 0.0},
+                Prod{k.tG[1], 0, SN(k.xR, 0), SAH(k.rhs[1].Bd, 0), none, 0, 1.0, 0.0}});
+    else
+      prods(s, {Prod{k.tG[0], 0, SN(k.xR, 0), SAH(k.rhs[0].Bd, 0), none, 0, 1.0, 0.0}});
+    if (nr == 2)
+      prods(s, {Prod{k.rhs[0].Xd, 0, SN(k.tG[0], 0), SC(k.xR, 0), none, 0, 1.0, 0.0},
+                Prod{k.rhs[1].Xd, 0, SN(k.tG[1], 0), SC(k.xR, 0), none, 0, 1.0, 0.0}});
+    else
+      prods(s, {Prod{k.rhs[0].Xd, 0, SN(k.tG[0], 0), SC(k.xR, 0), none, 0, 1.0, 0.0}});
   }
   for (int i = 1; i < n; ++i) {
     // F = L_{i-1} x_{i-1};  Mt_ii - F U_{i-1}  -> inverse -> x_i
-    s.gemm('N', 'N', {Term{{k.L, i - 1}, {k.xR, i - 1}, nullptr, 0, k.tF, 0, sl, kZero}});
+    prods(s, {Prod{k.tF, 0, Lr(i - 1), SN(k.xR, i - 1), none, 0, 1.0, 0.0}});
     prep_diag(i);
-    s.gemm('N', 'N', {Term{{k.tF, 0}, {k.U, i - 1}, &k.tS, 0, k.tS, 0, rs(-k.su), kOne}});
+    prods(s, {Prod{k.tS, 0, SN(k.tF, 0), Ur(i - 1), &k.tS, 0, -1.0, 1.0}});
     inv(i);
     if (nr == 0) continue;
-    // W = B_ii + L xs_{i-1} L^dag - y + y^dag;  xs_i = x_i W x_i^dag
+    // W = B_ii + L x^s_{i-1} L^dag - y + y^dag;  x^s_i = x_i W x_i^dag
     if (nr == 2) {
-      s.gemm('N', 'N', {Term{{k.L, i - 1}, {k.rhs[0].Xd, i - 1}, nullptr, 0, k.tG[0], 0, sl, kZero},
-                        Term{{k.L, i - 1}, {k.rhs[1].Xd, i - 1}, nullptr, 0, k.tG[1], 0, sl, kZero}});
-      s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.L, i - 1}, &k.rhs[0].Bd, i, k.tW[0], 0, sl, kOne},
-                        Term{{k.tG[1], 0}, {k.L, i - 1}, &k.rhs[1].Bd, i, k.tW[1], 0, sl, kOne}});
+      prods(s, {Prod{k.tG[0], 0, Lr(i - 1), SAH(k.rhs[0].Xd, i - 1), none, 0, 1.0, 0.0},
+                Prod{k.tG[1], 0, Lr(i - 1), SAH(k.rhs[1].Xd, i - 1), none, 0, 1.0, 0.0}});
+      prods(s, {Prod{k.tW[0], 0, SN(k.tG[0], 0), LHr(i - 1), &k.rhs[0].Bd, i, 1.0, 1.0},
+                Prod{k.tW[1], 0, SN(k.tG[1], 0), LHr(i - 1), &k.rhs[1].Bd, i, 1.0, 1.0}});
     } else {
-      s.gemm('N', 'N', {Term{{k.L, i - 1}, {k.rhs[0].Xd, i - 1}, nullptr, 0, k.tG[0], 0, sl, kZero}});
-      s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.L, i - 1}, &k.rhs[0].Bd, i, k.tW[0], 0, sl, kOne}});
+      prods(s, {Prod{k.tG[0], 0, Lr(i - 1), SAH(k.rhs[0].Xd, i - 1), none, 0, 1.0, 0.0}});
+      prods(s, {Prod{k.tW[0], 0, SN(k.tG[0], 0), LHr(i - 1), &k.rhs[0].Bd, i, 1.0, 1.0}});
     }
     for (int r = 0; r < nr; ++r) {
       if (!k.rhs[r].Bu.ok()) continue;
-      s.gemm('N', 'N', {Term{{k.tF, 0}, {k.rhs[r].Bu, i - 1}, nullptr, 0, k.tY[r], 0, kOne, kZero}});
+      prods(s, {Prod{k.tY[r], 0, SN(k.tF, 0), SN(k.rhs[r].Bu, i - 1), none, 0, 1.0, 0.0}});
       s.antiherm(k.tW[r], 0, &k.tW[r], 0, k.tY[r], 0, kMinus, kOne);
     }
     if (nr == 2) {
-      s.gemm('N', 'N', {Term{{k.xR, i}, {k.tW[0], 0}, nullptr, 0, k.tG[0], 0, kOne, kZero},
-                        Term{{k.xR, i}, {k.tW[1], 0}, nullptr, 0, k.tG[1], 0, kOne, kZero}});
-      s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.xR, i}, nullptr, 0, k.rhs[0].Xd, i, kOne, kZero},
-                        Term{{k.tG[1], 0}, {k.xR, i}, nullptr, 0, k.rhs[1].Xd, i, kOne, kZero}});
+      prods(s, {Prod{k.tG[0], 0, SN(k.xR, i), SAH(k.tW[0], 0), none, 0, 1.0, 0.0},
+                Prod{k.tG[1], 0, SN(k.xR, i), SAH(k.tW[1], 0), none, 0, 1.0, 0.0}});
+      prods(s, {Prod{k.rhs[0].Xd, i, SN(k.tG[0], 0), SC(k.xR, i), none, 0, 1.0, 0.0},
+                Prod{k.rhs[1].Xd, i, SN(k.tG[1], 0), SC(k.xR, i), none, 0, 1.0, 0.0}});
     } else {
-      s.gemm('N', 'N', {Term{{k.xR, i}, {k.tW[0], 0}, nullptr, 0, k.tG[0], 0, kOne, kZero}});
-      s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.xR, i}, nullptr, 0, k.rhs[0].Xd, i, kOne, kZero}});
+      prods(s, {Prod{k.tG[0], 0, SN(k.xR, i), SAH(k.tW[0], 0), none, 0, 1.0, 0.0}});
+      prods(s, {Prod{k.rhs[0].Xd, i, SN(k.tG[0], 0), SC(k.xR, i), none, 0, 1.0, 0.0}});
     }
   }
 
@@ -228,38 +286,38 @@ void run_core(Emitter& s, const Core& k, PrepDiag prep_diag) {
   s.copy(k.XRd, n - 1, k.xR, n - 1);
   for (int i = n - 2; i >= 0; --i) {
     // P = x_i U_i,  M = X_{i+1} L_i
-    s.gemm('N', 'N', {Term{{k.xR, i}, {k.U, i}, nullptr, 0, k.tP, 0, su, kZero},
-                      Term{{k.XRd, i + 1}, {k.L, i}, nullptr, 0, k.tM, 0, sl, kZero}});
+    prods(s, {Prod{k.tP, 0, SN(k.xR, i), Ur(i), none, 0, 1.0, 0.0},
+              Prod{k.tM, 0, SN(k.XRd, i + 1), Lr(i), none, 0, 1.0, 0.0}});
     // X_{i,i+1} = -P X_{i+1} (= -Q),  X_{i+1,i} = -M x_i
-    s.gemm('N', 'N', {Term{{k.tP, 0}, {k.XRd, i + 1}, nullptr, 0, k.XRu, i, kMinus, kZero},
-                      Term{{k.tM, 0}, {k.xR, i}, nullptr, 0, k.XRl, i, kMinus, kZero}});
+    prods(s, {Prod{k.XRu, i, SN(k.tP, 0), SN(k.XRd, i + 1), none, 0, -1.0, 0.0},
+              Prod{k.XRl, i, SN(k.tM, 0), SN(k.xR, i), none, 0, -1.0, 0.0}});
     // R = Q L_i = -X_{i,i+1} L_i
-    s.gemm('N', 'N', {Term{{k.XRu, i}, {k.L, i}, nullptr, 0, k.tR, 0, rs(-k.sl), kZero}});
+    prods(s, {Prod{k.tR, 0, SN(k.XRu, i), Lr(i), none, 0, -1.0, 0.0}});
     // X_i = x_i + R x_i
-    s.gemm('N', 'N', {Term{{k.tR, 0}, {k.xR, i}, &k.xR, i, k.XRd, i, kOne, kOne}});
+    prods(s, {Prod{k.XRd, i, SN(k.tR, 0), SN(k.xR, i), &k.xR, i, 1.0, 1.0}});
     if (nr == 0) continue;
     if (nr == 2) {
-      // T1 = P X^s_{i+1},  Z = R xs_i
-      s.gemm('N', 'N', {Term{{k.tP, 0}, {k.rhs[0].Xd, i + 1}, nullptr, 0, k.tG[0], 0, kOne, kZero},
-                        Term{{k.tP, 0}, {k.rhs[1].Xd, i + 1}, nullptr, 0, k.tG[1], 0, kOne, kZero},
-                        Term{{k.tR, 0}, {k.rhs[0].Xd, i}, nullptr, 0, k.tW[0], 0, kOne, kZero},
-                        Term{{k.tR, 0}, {k.rhs[1].Xd, i}, nullptr, 0, k.tW[1], 0, kOne, kZero}});
-      // X^s_{i,i+1} = -T1 - xs_i M^dag
-      s.gemm('N', 'C', {Term{{k.rhs[0].Xd, i}, {k.tM, 0}, &k.tG[0], 0, k.rhs[0].Xu, i, kMinus, kMinus},
-                        Term{{k.rhs[1].Xd, i}, {k.tM, 0}, &k.tG[1], 0, k.rhs[1].Xu, i, kMinus, kMinus}});
-      // X^s_ii = xs_i + T1 P^dag (+ Z - Z^dag below)
-      s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.tP, 0}, &k.rhs[0].Xd, i, k.rhs[0].Xd, i, kOne, kOne},
-                        Term{{k.tG[1], 0}, {k.tP, 0}, &k.rhs[1].Xd, i, k.rhs[1].Xd, i, kOne, kOne}});
+      // T1 = P X^s_{i+1},  Z = R x^s_i
+      prods(s, {Prod{k.tG[0], 0, SN(k.tP, 0), SAH(k.rhs[0].Xd, i + 1), none, 0, 1.0, 0.0},
+                Prod{k.tG[1], 0, SN(k.tP, 0), SAH(k.rhs[1].Xd, i + 1), none, 0, 1.0, 0.0},
+                Prod{k.tW[0], 0, SN(k.tR, 0), SAH(k.rhs[0].Xd, i), none, 0, 1.0, 0.0},
+                Prod{k.tW[1], 0, SN(k.tR, 0), SAH(k.rhs[1].Xd, i), none, 0, 1.0, 0.0}});
+      // X^s_{i,i+1} = -T1 - x^s_i M^dag
+      prods(s, {Prod{k.rhs[0].Xu, i, SN(k.rhs[0].Xd, i), SC(k.tM, 0), &k.tG[0], 0, -1.0, -1.0},
+                Prod{k.rhs[1].Xu, i, SN(k.rhs[1].Xd, i), SC(k.tM, 0), &k.tG[1], 0, -1.0, -1.0}});
+      // X^s_ii = x^s_i + T1 P^dag (+ Z - Z^dag below)
+      prods(s, {Prod{k.rhs[0].Xd, i, SN(k.tG[0], 0), SC(k.tP, 0), &k.rhs[0].Xd, i, 1.0, 1.0},
+                Prod{k.rhs[1].Xd, i, SN(k.tG[1], 0), SC(k.tP, 0), &k.rhs[1].Xd, i, 1.0, 1.0}});
       const View D2[2] = {k.rhs[0].Xd, k.rhs[1].Xd};
       const long long ii[2] = {i, i}, zz[2] = {0, 0};
       const View* C2[2] = {&k.rhs[0].Xd, &k.rhs[1].Xd};
       const View Z2[2] = {k.tW[0], k.tW[1]};
       s.antiherm2(2, D2, ii, C2, ii, Z2, zz, kOne, kMinus);
     } else {
-      s.gemm('N', 'N', {Term{{k.tP, 0}, {k.rhs[0].Xd, i + 1}, nullptr, 0, k.tG[0], 0, kOne, kZero},
-                        Term{{k.tR, 0}, {k.rhs[0].Xd, i}, nullptr, 0, k.tW[0], 0, kOne, kZero}});
-      s.gemm('N', 'C', {Term{{k.rhs[0].Xd, i}, {k.tM, 0}, &k.tG[0], 0, k.rhs[0].Xu, i, kMinus, kMinus}});
-      s.gemm('N', 'C', {Term{{k.tG[0], 0}, {k.tP, 0}, &k.rhs[0].Xd, i, k.rhs[0].Xd, i, kOne, kOne}});
+      prods(s, {Prod{k.tG[0], 0, SN(k.tP, 0), SAH(k.rhs[0].Xd, i + 1), none, 0, 1.0, 0.0},
+                Prod{k.tW[0], 0, SN(k.tR, 0), SAH(k.rhs[0].Xd, i), none, 0, 1.0, 0.0}});
+      prods(s, {Prod{k.rhs[0].Xu, i, SN(k.rhs[0].Xd, i), SC(k.tM, 0), &k.tG[0], 0, -1.0, -1.0}});
+      prods(s, {Prod{k.rhs[0].Xd, i, SN(k.tG[0], 0), SC(k.tP, 0), &k.rhs[0].Xd, i, 1.0, 1.0}});
       s.antiherm(k.rhs[0].Xd, i, &k.rhs[0].Xd, i, k.tW[0], 0, kOne, kMinus);
     }
     for (int r = 0; r < nr; ++r) {
@@ -267,9 +325,9 @@ void run_core(Emitter& s, const Core& k, PrepDiag prep_diag) {
       if (h.Bu.ok()) {
         // V = x_i B_{i,i+1};  X^s_{i,i+1} += V X_{i+1}^dag;  X^s_ii -= Y - Y^dag
         // with Y = V Q^dag = -V X_{i,i+1}^dag
-        s.gemm('N', 'N', {Term{{k.xR, i}, {h.Bu, i}, nullptr, 0, k.tY[r], 0, kOne, kZero}});
-        s.gemm('N', 'C', {Term{{k.tY[r], 0}, {k.XRd, i + 1}, &h.Xu, i, h.Xu, i, kOne, kOne}});
-        s.gemm('N', 'C', {Term{{k.tY[r], 0}, {k.XRu, i}, nullptr, 0, k.tW[r], 0, kOne, kZero}});
+        prods(s, {Prod{k.tY[r], 0, SN(k.xR, i), SN(h.Bu, i), none, 0, 1.0, 0.0}});
+        prods(s, {Prod{h.Xu, i, SN(k.tY[r], 0), SC(k.XRd, i + 1), &h.Xu, i, 1.0, 1.0}});
+        prods(s, {Prod{k.tW[r], 0, SN(k.tY[r], 0), SC(k.XRu, i), none, 0, 1.0, 0.0}});
         s.antiherm(h.Xd, i, &h.Xd, i, k.tW[r], 0, kOne, kMinus);
       }
     }
@@ -550,6 +608,9 @@ void build_lane(Lane& lane, const qtx_rgf_problem& p, const Plan& q, char* ws,
       k.U = lay.Uw; k.L = lay.Lw; k.su = 1.0; k.sl = 1.0;
     } else {
       k.U = Hu; k.L = HL; k.su = -1.0; k.sl = -1.0;
+      // H Hermitian: U_i = -H_u = (-H_l)^dag and L_i = -H_l = (-H_u)^dag
+      k.Uh = HL; k.suh = -1.0;
+      k.Lh = Hu; k.slh = -1.0;
     }
     s.set_fp32(q.fp32);
     run_core(s, k, [&](int i) {

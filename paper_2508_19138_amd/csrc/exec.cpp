@@ -77,16 +77,16 @@ void Tuner::save() const {
 static int heuristic_cfg(int b) { return b <= 32 ? 2 : (b >= 384 ? 1 : 0); }
 
 int Tuner::measure(int b, bool fp32, hipStream_t s) {
-  // time each configuration on a batch of b x b x b products large enough
-  // to fill the chip; operands are zero-filled scratch
+  // time each configuration on a batch of b x b x b products that fills the
+  // chip several times over; operands hold a nonzero byte pattern
   const long long blk = (long long)b * b;
-  int batch = std::max(1, std::min(512, (int)(4096 * 4096LL / blk)));
+  const int batch = std::max(1, std::min(1024, (int)(8192LL * 4096 / blk)));
   void* buf = nullptr;
   if (hipMalloc(&buf, (size_t)(3 * batch) * blk * 16 + 4096) != hipSuccess) {
     (void)hipGetLastError();
     return heuristic_cfg(b);
   }
-  XCHK(hipMemsetAsync(buf, 0, (size_t)(3 * batch) * blk * 16, s));
+  XCHK(hipMemsetAsync(buf, 0x3f, (size_t)(3 * batch) * blk * 16, s));
   GemmDesc d{};
   d.A = buf;
   d.B = (char*)buf + (size_t)batch * blk * 16;
@@ -97,44 +97,48 @@ int Tuner::measure(int b, bool fp32, hipStream_t s) {
   d.beta = zc{0.0, 0.0};
   d.M = b; d.N = b; d.K = b;
   d.batch = batch; d.batch2 = 1;
-  void* ddesc = nullptr;
-  XCHK(hipMalloc(&ddesc, sizeof(GemmDesc) + 64));
+  void* dmem = nullptr;
+  XCHK(hipMalloc(&dmem, sizeof(GemmDesc) + 256));
+  int* dpre = (int*)((char*)dmem + ((sizeof(GemmDesc) + 63) & ~size_t(63)));
   hipEvent_t a, z;
   XCHK(hipEventCreate(&a));
   XCHK(hipEventCreate(&z));
-  int best = heuristic_cfg(b);
-  float best_ms = 1e30f;
+  float t[kGemmConfigs];
   for (int cfg = 0; cfg < kGemmConfigs; ++cfg) {
+    t[cfg] = 1e30f;
     if (cfg == 1 && b < 128) continue;
     d.tiles = gemm_tiles(cfg, b, b);
     int pre[2] = {0, d.tiles * batch};
-    XCHK(hipMemcpy(ddesc, &d, sizeof(d), hipMemcpyHostToDevice));
-    int* dpre = (int*)((char*)ddesc + sizeof(GemmDesc));
-    (void)dpre;
-    void* dp = nullptr;
-    XCHK(hipMalloc(&dp, sizeof(pre)));
-    XCHK(hipMemcpy(dp, pre, sizeof(pre), hipMemcpyHostToDevice));
-    FlatLaunch l{ddesc, (const int*)dp, 1, pre[1]};
+    XCHK(hipMemcpy(dmem, &d, sizeof(d), hipMemcpyHostToDevice));
+    XCHK(hipMemcpy(dpre, pre, sizeof(pre), hipMemcpyHostToDevice));
+    FlatLaunch l{dmem, dpre, 1, pre[1]};
     XCHK(launch_gemm(cfg, fp32, 'N', 'N', l, s));   // warm
-    XCHK(hipEventRecord(a, s));
-    for (int r = 0; r < 3; ++r) XCHK(launch_gemm(cfg, fp32, 'N', 'N', l, s));
-    XCHK(hipEventRecord(z, s));
-    XCHK(hipEventSynchronize(z));
-    float ms = 0;
-    XCHK(hipEventElapsedTime(&ms, a, z));
-    XCHK(hipFree(dp));
-    if (ms < best_ms) { best_ms = ms; best = cfg; }
+    for (int r = 0; r < 5; ++r) {
+      XCHK(hipEventRecord(a, s));
+      XCHK(launch_gemm(cfg, fp32, 'N', 'N', l, s));
+      XCHK(hipEventRecord(z, s));
+      XCHK(hipEventSynchronize(z));
+      float ms = 0;
+      XCHK(hipEventElapsedTime(&ms, a, z));
+      t[cfg] = std::min(t[cfg], ms);
+    }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(z);
-  (void)hipFree(ddesc);
+  (void)hipFree(dmem);
   (void)hipFree(buf);
+  // the general tile unless another one is clearly faster
+  int best = 0;
+  for (int cfg = 1; cfg < kGemmConfigs; ++cfg)
+    if (t[cfg] < 0.97f * t[best]) best = cfg;
   return best;
 }
 
 int Tuner::cfg(int M, int N, int K, bool fp32, hipStream_t s) {
   const int b = std::max(M, N);
   if (K < 32) return heuristic_cfg(std::min(b, 64));   // thin updates
+  const char* force = std::getenv("QTX_GEMM_CFG");      // fixed tile for all products
+  if (force && *force >= '0' && *force < '0' + kGemmConfigs) return *force - '0';
   if (!enabled_) return heuristic_cfg(b);
   if (!loaded_) load();
   char key[64];

@@ -1,9 +1,8 @@
 // Complex strided-batched products on the gfx950 matrix cores.
 //
 // A workgroup computes one BM x BN tile of D for one matrix of one
-// descriptor.  Operand tiles are staged through LDS in a k-major layout
-// (As[k][m], Bs[k][n]) so that the 16 lanes feeding one MFMA row read
-// contiguous memory.  Complex numbers stay interleaved (re, im): each lane
+// descriptor.  Operand tiles are staged through LDS in the layout in which
+// they are read from HBM (see zgemm_kernel) and double buffered.  Complex numbers stay interleaved (re, im): each lane
 // reads one complex per fragment and the complex product is four real MFMAs
 //     Cr += ar*br - ai*bi,   Ci += ar*bi + ai*br.
 // MFMA operand layout (measured on gfx950, both 16x16x4 f64 and f32): lane l
@@ -51,8 +50,10 @@ struct Cfg {
   static constexpr int kWN = BN / WGN;
   static constexpr int kTM = kWM / 16;
   static constexpr int kTN = kWN / 16;
-  static constexpr int kLdA = BM + 1;
-  static constexpr int kLdB = BN + 1;
+  // LDS elements per buffer: a k-major tile [BK][BM+1] or a row-major tile
+  // [BM][BK+1], whichever the operand uses (one element of row padding)
+  static constexpr int kSzA = (BK * (BM + 1) > BM * (BK + 1)) ? BK * (BM + 1) : BM * (BK + 1);
+  static constexpr int kSzB = (BK * (BN + 1) > BN * (BK + 1)) ? BK * (BN + 1) : BN * (BK + 1);
   static constexpr int kALoads = BM * BK / kThreads;
   static constexpr int kBLoads = BN * BK / kThreads;
   static_assert(BM * BK % kThreads == 0 && BN * BK % kThreads == 0, "tile");
@@ -72,6 +73,24 @@ __device__ __forceinline__ int xcd_remap(int w, int G) {
 
 // TAG only separates kernel symbols (1 = rank-kPanel updates of the
 // inverse) so that profilers report the two uses apart.
+// Thread -> element maps of the operand tiles.  Tiles whose rows are
+// contiguous in HBM along the LDS minor index (A^dagger: [k][m], B: [k][n])
+// are read in 16-complex (256-byte) segments, 16 lanes per segment and four
+// rows per wave instruction; the transposed cases (A: [m][k], B^dagger:
+// [n][k]) read 16 consecutive k of one row.
+template <int BK, int BW, int TRANS>
+__device__ __forceinline__ void tile_index(int q, int& w, int& k) {
+  if (TRANS) {            // global row = w (BW of them), contiguous along k
+    w = q / BK;
+    k = q % BK;
+  } else {                // global row = k, contiguous along w
+    constexpr int SEG = BW < 16 ? BW : 16;
+    const int off = q % SEG;
+    k = (q / SEG) % BK;
+    w = (q / (SEG * BK)) * SEG + off;
+  }
+}
+
 template <class P, class T, int OPA, int OPB, int TAG>
 __global__ __launch_bounds__(T::kThreads)
 void zgemm_kernel(FlatLaunch L) {
@@ -79,8 +98,14 @@ void zgemm_kernel(FlatLaunch L) {
   typedef typename P::acc_t Acc;
   typedef typename P::real_t R;
   constexpr int BM = T::BM, BN = T::BN, BK = T::BK, WGN = T::WGN;
-  __shared__ Lt As[2][BK][T::kLdA];
-  __shared__ Lt Bs[2][BK][T::kLdB];
+  // Each operand tile keeps the layout in which it arrives from HBM, so the
+  // LDS stores are contiguous: A (row = m) and B^dagger (row = n) are stored
+  // row-major with pitch BK+1, A^dagger and B (row = k) k-major with pitch
+  // BM+1 / BN+1.  The pitches make the 16-lane fragment reads conflict-free.
+  __shared__ Lt As[2][T::kSzA];
+  __shared__ Lt Bs[2][T::kSzB];
+  auto ia = [](int k, int m) { return OPA == 0 ? m * (BK + 1) + k : k * (BM + 1) + m; };
+  auto ib = [](int k, int n) { return OPB == 1 ? n * (BK + 1) + k : k * (BN + 1) + n; };
 
   const int w = xcd_remap(blockIdx.x, gridDim.x);
   const int di = find_desc(L.prefix, L.nd, w);
@@ -106,12 +131,33 @@ void zgemm_kernel(FlatLaunch L) {
 
   double2 ra[T::kALoads], rb[T::kBLoads];
 
+  // whole tile inside the matrices: loads need no bounds checks
+  const bool full = (m0 + BM <= M) && (n0 + BN <= N) && (K % BK == 0);
   auto load_tiles = [&](int k0) {
+    if (full) {
+#pragma unroll
+      for (int r = 0; r < T::kALoads; ++r) {
+        const int q = tid + r * T::kThreads;
+        int m, k;
+        tile_index<BK, BM, OPA == 0>(q, m, k);
+        const int gm = m0 + m, gk = k0 + k;
+        ra[r] = (OPA == 0) ? A[(long long)gm * lda + gk] : A[(long long)gk * lda + gm];
+      }
+#pragma unroll
+      for (int r = 0; r < T::kBLoads; ++r) {
+        const int q = tid + r * T::kThreads;
+        int n, k;
+        tile_index<BK, BN, OPB == 1>(q, n, k);
+        const int gn = n0 + n, gk = k0 + k;
+        rb[r] = (OPB == 0) ? B[(long long)gk * ldb + gn] : B[(long long)gn * ldb + gk];
+      }
+      return;
+    }
 #pragma unroll
     for (int r = 0; r < T::kALoads; ++r) {
       const int q = tid + r * T::kThreads;
       int m, k;
-      if (OPA == 0) { m = q / BK; k = q % BK; } else { k = q / BM; m = q % BM; }
+      tile_index<BK, BM, OPA == 0>(q, m, k);
       const int gm = m0 + m, gk = k0 + k;
       double2 v = make_double2(0.0, 0.0);
       if (gm < M && gk < K)
@@ -122,7 +168,7 @@ void zgemm_kernel(FlatLaunch L) {
     for (int r = 0; r < T::kBLoads; ++r) {
       const int q = tid + r * T::kThreads;
       int n, k;
-      if (OPB == 0) { k = q / BN; n = q % BN; } else { n = q / BK; k = q % BK; }
+      tile_index<BK, BN, OPB == 1>(q, n, k);
       const int gn = n0 + n, gk = k0 + k;
       double2 v = make_double2(0.0, 0.0);
       if (gn < N && gk < K)
@@ -135,19 +181,19 @@ void zgemm_kernel(FlatLaunch L) {
     for (int r = 0; r < T::kALoads; ++r) {
       const int q = tid + r * T::kThreads;
       int m, k;
-      if (OPA == 0) { m = q / BK; k = q % BK; } else { k = q / BM; m = q % BM; }
+      tile_index<BK, BM, OPA == 0>(q, m, k);
       Lt v = P::cvt(ra[r]);
       if (OPA == 1) v.y = -v.y;
-      As[buf][k][m] = v;
+      As[buf][ia(k, m)] = v;
     }
 #pragma unroll
     for (int r = 0; r < T::kBLoads; ++r) {
       const int q = tid + r * T::kThreads;
       int n, k;
-      if (OPB == 0) { k = q / BN; n = q % BN; } else { n = q / BK; k = q % BK; }
+      tile_index<BK, BN, OPB == 1>(q, n, k);
       Lt v = P::cvt(rb[r]);
       if (OPB == 1) v.y = -v.y;
-      Bs[buf][k][n] = v;
+      Bs[buf][ib(k, n)] = v;
     }
   };
 
@@ -173,9 +219,9 @@ void zgemm_kernel(FlatLaunch L) {
       const int kidx = kk * 4 + lk;
       Lt a[T::kTM], b[T::kTN];
 #pragma unroll
-      for (int i = 0; i < T::kTM; ++i) a[i] = As[buf][kidx][wm * T::kWM + i * 16 + lrow];
+      for (int i = 0; i < T::kTM; ++i) a[i] = As[buf][ia(kidx, wm * T::kWM + i * 16 + lrow)];
 #pragma unroll
-      for (int j = 0; j < T::kTN; ++j) b[j] = Bs[buf][kidx][wn * T::kWN + j * 16 + lrow];
+      for (int j = 0; j < T::kTN; ++j) b[j] = Bs[buf][ib(kidx, wn * T::kWN + j * 16 + lrow)];
 #pragma unroll
       for (int i = 0; i < T::kTM; ++i) {
         const R nai = -a[i].y;
