@@ -146,8 +146,48 @@ qtx_status qtx_rgf_solve_batch(qtx_rgf_ctx* ctx, qtx_rgf_problem* problems,
                                int32_t n_problems);
 
 /* Release the context's workspace, streams and events.  Caller memory is
- * untouched.  Waits for work in flight on the context's stream. */
+ * untouched.  Waits for work in flight, including every problem submitted
+ * to the request loop. */
 qtx_status qtx_rgf_destroy(qtx_rgf_ctx* ctx);
+
+/* ---- request loop (continuous batching) -------------------------------- */
+
+/* Completion record of one submitted problem. */
+typedef struct {
+  uint64_t ticket;      /* as returned by qtx_rgf_submit                       */
+  int32_t status;       /* qtx_status of the problem                           */
+  int32_t fail_energy;  /* first failing energy, or -1                         */
+  int32_t fail_block;   /* block of that failure, or -1                        */
+  int32_t n_energies;
+  double queue_s;       /* submission -> first lane admitted to the GPU        */
+  double latency_s;     /* submission -> all its work observed complete        */
+} qtx_rgf_completion;
+
+/* Queue one problem for the context's request loop and return at once.  The
+ * loop (a host thread with its own HIP stream, workspace and launch arena,
+ * started on first use) admits queued problems in arrival order as soon as
+ * workspace frees up, and runs every admitted problem's remaining work in
+ * the same merged launches as the others, so problems that arrive while
+ * others are running overlap with them on the device.  A problem's result is
+ * the same as when it is solved alone (same kernels, tiles and order of
+ * operations per problem).  The problem structure is copied (including its
+ * host energies); every device buffer it points to must stay valid and
+ * unmodified until its completion is returned by qtx_rgf_poll.  Workspace of
+ * the loop: the context's budget (0 = half of the free device memory when
+ * the loop starts).  Errors: QTX_ERR_INVALID_ARG (checked as in
+ * qtx_rgf_solve_batch), QTX_ERR_NOMEM if one energy of the problem cannot
+ * fit the loop's workspace. */
+qtx_status qtx_rgf_submit(qtx_rgf_ctx* ctx, const qtx_rgf_problem* problem,
+                          uint64_t* ticket);
+
+/* Return up to `cap` completion records (in completion order) into `out`,
+ * waiting up to `wait_ms` milliseconds for at least one (0 = do not wait,
+ * -1 = wait until one arrives or nothing is outstanding).  *n_out receives
+ * the number returned; *n_pending (may be NULL) the number of submitted
+ * problems not yet returned.  QTX_ERR_HIP if the loop stopped on a runtime
+ * error (outstanding problems are then returned with that status). */
+qtx_status qtx_rgf_poll(qtx_rgf_ctx* ctx, qtx_rgf_completion* out, int32_t cap,
+                        int32_t* n_out, int32_t* n_pending, int32_t wait_ms);
 
 /* Static string for a status code. */
 const char* qtx_rgf_status_string(qtx_status s);

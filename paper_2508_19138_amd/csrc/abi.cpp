@@ -16,80 +16,15 @@
 #include <vector>
 
 #include "../../include/qtx_rgf.h"
+#include "ctx.h"
 #include "emit.h"
 #include "exec.h"
 
 using namespace qtx;
 
-struct qtx_rgf_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  uint64_t budget = 0;
-  uint32_t flags = 0;
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  char* aux = nullptr;
-  size_t aux_bytes = 0;
-  std::string err;
-  std::vector<KStat> stats = std::vector<KStat>(kNumClasses);
-  std::unique_ptr<Executor> exe;
-  Tuner tuner;
-  bool graphs = true;
-  bool busy = false;
-};
-
 namespace {
 
-#define HIPCHK(ctx, expr)                                                    \
-  do {                                                                       \
-    hipError_t e_ = (expr);                                                  \
-    if (e_ != hipSuccess) {                                                  \
-      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);        \
-      throw Fail{QTX_ERR_HIP};                                               \
-    }                                                                        \
-  } while (0)
-
 constexpr size_t kArenaLimit = 32u << 20;    // descriptor bytes per segment
-
-// First-fit allocator over [0, cap) with 256-byte granularity.
-class Regions {
- public:
-  explicit Regions(size_t cap) { free_[0] = cap; }
-  bool alloc(size_t bytes, size_t* off) {
-    bytes = (bytes + 255) & ~size_t(255);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        *off = it->first;
-        const size_t rest = it->second - bytes;
-        const size_t o = it->first + bytes;
-        free_.erase(it);
-        if (rest) free_[o] = rest;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    bytes = (bytes + 255) & ~size_t(255);
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-
- private:
-  std::map<size_t, size_t> free_;
-};
 
 size_t budget_now(qtx_rgf_ctx* c) {
   if (c->budget) return c->budget;
@@ -116,7 +51,9 @@ void ensure(qtx_rgf_ctx* c, char** p, size_t* have, size_t need) {
   *have = need;
 }
 
-std::string validate(const qtx_rgf_problem& p) {
+}  // namespace
+
+std::string qtx::validate_problem(const qtx_rgf_problem& p) {
   if (p.kind != QTX_KIND_G && p.kind != QTX_KIND_W) return "unknown kind";
   if (p.precision != QTX_FP64 && p.precision != QTX_MIXED) return "unknown precision";
   if (p.n_blocks < 1 || p.block_size < 1 || p.n_energies < 1)
@@ -145,6 +82,8 @@ std::string validate(const qtx_rgf_problem& p) {
   return "";
 }
 
+namespace {
+
 struct BusyGuard {
   qtx_rgf_ctx* c;
   explicit BusyGuard(qtx_rgf_ctx* c_) : c(c_) { c->busy = true; }
@@ -163,8 +102,8 @@ void run_lanes_to_end(qtx_rgf_ctx* c, std::vector<Lane*>& lanes) {
 qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
   const bool prof = (c->flags & QTX_FLAG_PROFILE) != 0;
   std::vector<Plan> plans(np);
-  size_t n_e_tot = 0, hl_tot = 0;
-  std::vector<size_t> e_off(np), hl_off(np, (size_t)-1);
+  size_t n_e_tot = 0;
+  std::vector<size_t> e_off(np);
   for (int i = 0; i < np; ++i) {
     probs[i].status = QTX_OK;
     probs[i].fail_energy = -1;
@@ -172,18 +111,13 @@ qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
     plans[i] = make_plan(probs[i]);
     e_off[i] = n_e_tot;
     n_e_tot += probs[i].n_energies;
-    if (plans[i].need_hl) {
-      hl_off[i] = hl_tot;
-      hl_tot += ((size_t)(probs[i].n_blocks - 1) * probs[i].block_size * probs[i].block_size * 16 + 255) & ~size_t(255);
-    }
   }
-  // aux: energies | info | H lower blocks
+  // aux: energies | info
   const size_t eb = ((n_e_tot * 8) + 255) & ~size_t(255);
   const size_t ib = ((n_e_tot * 4) + 255) & ~size_t(255);
-  ensure(c, &c->aux, &c->aux_bytes, eb + ib + hl_tot + 256);
+  ensure(c, &c->aux, &c->aux_bytes, eb + ib + 256);
   double* d_E = (double*)c->aux;
   int* d_info = (int*)(c->aux + eb);
-  char* d_hl = c->aux + eb + ib;
   {
     std::vector<double> hE(n_e_tot, 0.0);
     for (int i = 0; i < np; ++i)
@@ -221,19 +155,6 @@ qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
   const size_t cap = std::min(budget, total + 4096);
   ensure(c, &c->ws, &c->ws_bytes, std::max(cap, largest + 4096));
 
-  // H lower blocks where absent: one prologue pass
-  {
-    std::vector<std::unique_ptr<Lane>> pro;
-    std::vector<Lane*> lp;
-    for (int i = 0; i < np; ++i)
-      if (plans[i].need_hl) {
-        pro.emplace_back(new Lane());
-        build_hl_lane(*pro.back(), probs[i], d_hl + hl_off[i]);
-        lp.push_back(pro.back().get());
-      }
-    if (!lp.empty()) run_lanes_to_end(c, lp);
-  }
-
   // admission and merged execution
   Regions reg(std::max(cap, largest + 4096));
   std::vector<std::unique_ptr<Lane>> active;
@@ -252,8 +173,7 @@ qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
       L->ws_bytes = pd.bytes;
       const qtx_rgf_problem& p = probs[pd.prob];
       build_lane(*L, p, plans[pd.prob], c->ws + off, pd.e0, pd.ec, d_E + e_off[pd.prob],
-                 d_info + e_off[pd.prob], plans[pd.prob].need_hl ? d_hl + hl_off[pd.prob] : nullptr,
-                 c->tuner, c->stream);
+                 d_info + e_off[pd.prob], c->tuner, c->stream);
       active.push_back(std::move(L));
       ++next;
     }
@@ -266,13 +186,12 @@ qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
     // with lanes waiting, stop the segment once a lane finishes so that its
     // memory can be handed to the next lane
     if (next < pending.size()) {
-      while (true) {
-        c->exe->build(lp, kArenaLimit);
-        bool fin = false;
+      bool fin = false;
+      while (!fin) {
+        c->exe->build(lp, kArenaLimit, 1 << 30, true);
         for (Lane* l : lp) fin |= l->done();
         if (c->exe->empty()) break;
         c->exe->flush(prof, c->graphs, c->stats);
-        if (fin) break;
       }
     } else {
       run_lanes_to_end(c, lp);
@@ -364,6 +283,7 @@ qtx_status qtx_rgf_destroy(qtx_rgf_ctx* c) {
   if (!c) return QTX_ERR_INVALID_ARG;
   if (c->busy) return QTX_ERR_BUSY;
   (void)hipSetDevice(c->device);
+  qtx::stop_server(c);                   // drains the request loop first
   (void)hipStreamSynchronize(c->stream);
   c->exe.reset();
   if (c->ws) (void)hipFree(c->ws);
@@ -379,7 +299,7 @@ qtx_status qtx_rgf_solve_batch(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int32_t n
   c->err.clear();
   if (np < 0 || (np > 0 && !probs)) { c->err = "bad problem array"; return QTX_ERR_INVALID_ARG; }
   for (int i = 0; i < np; ++i) {
-    const std::string m = validate(probs[i]);
+    const std::string m = validate_problem(probs[i]);
     if (!m.empty()) { c->err = "problem " + std::to_string(i) + ": " + m; return QTX_ERR_INVALID_ARG; }
   }
   if (np == 0) return QTX_OK;

@@ -439,7 +439,7 @@ View in_view(const void* p, long long es, long long bs) {
 
 // The lane's workspace layout; with ws == nullptr only the size is computed.
 struct Layout {
-  View xR, tS, tF, tP, tM, tR, tG[2], tW[2], tY[2], Uw, Lw;
+  View xR, tS, tF, tP, tM, tR, tG[2], tW[2], tY[2], Uw, Lw, Hl;
   View Ad, Bd[2], Bu[2], Tm1, T0, Tp1, Tp2;
   void *panel, *brow, *spanel, *sbrow;
   int *perm, *used;
@@ -466,6 +466,11 @@ Layout carve_layout(const Plan& q, int ec, char* ws) {
     if (q.bt_rhs[r]) L.tY[r] = blocks(1);
   }
   if (q.general_ul && n > 1) { L.Uw = blocks(n - 1); L.Lw = blocks(n - 1); }
+  if (q.need_hl) {              // H lower = H upper^dag, energy independent
+    L.Hl.p = (const double2*)cv.take((size_t)(n - 1) * blk * 16);
+    L.Hl.es = 0;
+    L.Hl.bs = blk;
+  }
   L.panel = cv.take((size_t)ec * b * kPanel * 16);
   L.brow = cv.take((size_t)ec * b * kPanel * 16);
   L.spanel = cv.take((size_t)ec * b * kSuper * 16);
@@ -508,32 +513,30 @@ Plan make_plan(const qtx_rgf_problem& p) {
 
 size_t lane_bytes(const Plan& q, int ec) { return carve_layout(q, ec, nullptr).bytes; }
 
-void build_hl_lane(Lane& lane, const qtx_rgf_problem& p, void* Hl) {
-  const int n = p.n_blocks, b = p.block_size;
-  const long long blk = (long long)b * b;
-  Op o;
-  o.k = OpK::Trans;
-  o.first = (int)lane.td.size();
-  for (int i = 0; i < n - 1; ++i) {
-    TransDesc t{};
-    t.Z = (const double2*)p.H.upper + i * blk;
-    t.D = (double2*)Hl + i * blk;
-    t.a = kZero; t.z = kZero; t.g = kOne;
-    t.b = b; t.batch = 1;
-    lane.td.push_back(t);
-  }
-  o.count = (int)lane.td.size() - o.first;
-  o.bytes = 32.0 * blk * (n - 1);
-  if (o.count) lane.ops.push_back(o);
-}
-
 void build_lane(Lane& lane, const qtx_rgf_problem& p, const Plan& q, char* ws,
-                int e0, int ec, const double* d_E, int* d_info, const void* Hl,
-                Tuner& tuner, hipStream_t strm) {
+                int e0, int ec, const double* d_E, int* d_info, Tuner& tuner,
+                hipStream_t strm) {
   const int n = q.n, b = q.b;
   const long long blk = (long long)b * b;
   Layout lay = carve_layout(q, ec, ws);
   Emitter s(lane, tuner, strm, b, ec);
+  if (q.need_hl) {
+    // the lane's own copy of H lower = H upper^dagger
+    Op o;
+    o.k = OpK::Trans;
+    o.first = (int)lane.td.size();
+    for (int i = 0; i < n - 1; ++i) {
+      TransDesc t{};
+      t.Z = (const double2*)p.H.upper + i * blk;
+      t.D = lay.Hl.w(i);
+      t.a = kZero; t.z = kZero; t.g = kOne;
+      t.b = b; t.batch = 1;
+      lane.td.push_back(t);
+    }
+    o.count = (int)lane.td.size() - o.first;
+    o.bytes = 32.0 * blk * (n - 1);
+    lane.ops.push_back(o);
+  }
 
   auto outv = [&](void* ptr, long long per_e) {
     View v;
@@ -583,7 +586,7 @@ void build_lane(Lane& lane, const qtx_rgf_problem& p, const Plan& q, char* ws,
     const double* E = d_E + e0;
     const View Hd = in_view(p.H.diag, 0, blk);
     const View Hu = in_view(p.H.upper, 0, blk);
-    const View HL = p.H.lower ? in_view(p.H.lower, 0, blk) : in_view(Hl, 0, blk);
+    const View HL = p.H.lower ? in_view(p.H.lower, 0, blk) : lay.Hl;
     const View Sd = in_view(p.S.diag, 0, blk);
     const View SRd = inv_(p.sigma_r.diag, n);
     if (q.general_ul && n > 1) {

@@ -22,13 +22,10 @@ size_t lane_bytes(const Plan& q, int ec);
 
 // Operations of one lane (energies e0 .. e0+ec-1 of problem p) whose
 // workspace is ws[0 .. lane_bytes(q, ec)).  d_E: the problem's energies on
-// the device (G-type), d_info: the problem's per-energy status words, Hl:
-// the problem's H lower blocks when H.lower is absent.
+// the device (G-type), d_info: the problem's per-energy status words.  When
+// H.lower is absent the lane builds its own H.upper^dagger first.
 void build_lane(Lane& lane, const qtx_rgf_problem& p, const Plan& q, char* ws,
-                int e0, int ec, const double* d_E, int* d_info, const void* Hl,
-                Tuner& tuner, hipStream_t s);
-
-// Operations that write H.upper^dagger into Hl (one lane, no energy axis).
-void build_hl_lane(Lane& lane, const qtx_rgf_problem& p, void* Hl);
+                int e0, int ec, const double* d_E, int* d_info, Tuner& tuner,
+                hipStream_t s);
 
 }  // namespace qtx

@@ -140,6 +140,7 @@ int Tuner::cfg(int M, int N, int K, bool fp32, hipStream_t s) {
   const char* force = std::getenv("QTX_GEMM_CFG");      // fixed tile for all products
   if (force && *force >= '0' && *force < '0' + kGemmConfigs) return *force - '0';
   if (!enabled_) return heuristic_cfg(b);
+  std::lock_guard<std::mutex> g(mu_);
   if (!loaded_) load();
   char key[64];
   std::snprintf(key, sizeof key, "gfx950/%s/b%d", fp32 ? "c64" : "c128", b);
@@ -325,12 +326,13 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
                             (int)d.size(), pre.back(), kClassElem, 0.0, by});
 }
 
-int Executor::build(std::vector<Lane*>& lanes, size_t arena_limit) {
+int Executor::build(std::vector<Lane*>& lanes, size_t arena_limit, int max_rounds,
+                    bool stop_on_finish) {
   int rounds = 0;
   struct Head { uint64_t sig; Lane* l; Op* o; };
   std::vector<Head> heads;
   std::vector<std::pair<Lane*, Op*>> grp;
-  while (host_.size() < arena_limit) {
+  while (host_.size() < arena_limit && rounds < max_rounds) {
     heads.clear();
     for (Lane* l : lanes)
       if (!l->done()) heads.push_back(Head{signature(l->ops[l->next]), l, &l->ops[l->next]});
@@ -348,9 +350,14 @@ int Executor::build(std::vector<Lane*>& lanes, size_t arena_limit) {
       emit_group(grp);
       i = j;
     }
+    bool fin = false;
     for (Lane* l : lanes)
-      if (!l->done()) l->next++;
+      if (!l->done()) {
+        l->next++;
+        fin |= l->done();
+      }
     ++rounds;
+    if (fin && stop_on_finish) break;
   }
   return rounds;
 }

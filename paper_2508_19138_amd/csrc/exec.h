@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <map>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -67,6 +68,7 @@ class Tuner {
   int measure(int b, bool fp32, hipStream_t s);
   void load();
   void save() const;
+  std::mutex mu_;            // the request loop and callers share the tuner
   bool loaded_ = false;
   bool enabled_ = true;
   std::map<std::string, int> table_;
@@ -92,7 +94,8 @@ class Executor {
   // Advance the lanes by merged rounds until every lane is done or the
   // arena limit is reached; returns the number of rounds emitted.  The
   // caller then calls flush() to upload and launch.
-  int build(std::vector<Lane*>& lanes, size_t arena_limit);
+  int build(std::vector<Lane*>& lanes, size_t arena_limit, int max_rounds = 1 << 30,
+            bool stop_on_finish = false);
   // Upload and launch what build() produced (graph replay when the same
   // segment was seen before and graphs are enabled).
   void flush(bool profile, bool graphs, std::vector<KStat>& stats);

@@ -56,6 +56,13 @@ class Problem(ctypes.Structure):
     ]
 
 
+class Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("fail_energy", ctypes.c_int32), ("fail_block", ctypes.c_int32),
+                ("n_energies", ctypes.c_int32), ("queue_s", ctypes.c_double),
+                ("latency_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -109,6 +116,13 @@ def lib():
     L.qtx_rgf_zinv.argtypes = [c_ctx, ctypes.c_int32, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
     L.qtx_rgf_zinv.restype = ctypes.c_int
+    L.qtx_rgf_submit.argtypes = [c_ctx, ctypes.POINTER(Problem),
+                                 ctypes.POINTER(ctypes.c_uint64)]
+    L.qtx_rgf_submit.restype = ctypes.c_int
+    L.qtx_rgf_poll.argtypes = [c_ctx, ctypes.POINTER(Completion), ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    L.qtx_rgf_poll.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -118,7 +132,7 @@ def exported_symbols():
             "qtx_rgf_status_string", "qtx_rgf_last_error",
             "qtx_rgf_flops_per_energy", "qtx_rgf_kernel_stats",
             "qtx_rgf_reset_stats", "qtx_rgf_zgemm", "qtx_rgf_cgemm",
-            "qtx_rgf_zinv"]
+            "qtx_rgf_zinv", "qtx_rgf_submit", "qtx_rgf_poll"]
 
 
 def status_string(st):
@@ -192,6 +206,28 @@ class Context:
             p.fail_energy = arr[i].fail_energy
             p.fail_block = arr[i].fail_block
         return self._check(st, "qtx_rgf_solve_batch")
+
+    def submit(self, problem):
+        """Queue one problem on the request loop; returns its ticket.  The
+        caller keeps the problem's device buffers alive until its completion
+        has been polled."""
+        t = ctypes.c_uint64()
+        st = lib().qtx_rgf_submit(self._h, ctypes.byref(problem), ctypes.byref(t))
+        self._check(st, "qtx_rgf_submit")
+        return t.value
+
+    def poll(self, cap=64, wait_ms=0):
+        """Return (completions, n_pending); each completion is a dict."""
+        out = (Completion * max(cap, 1))()
+        n, pend = ctypes.c_int32(), ctypes.c_int32()
+        st = lib().qtx_rgf_poll(self._h, out, cap, ctypes.byref(n),
+                                ctypes.byref(pend), wait_ms)
+        self._check(st, "qtx_rgf_poll")
+        res = [{"ticket": out[i].ticket, "status": out[i].status,
+                "fail_energy": out[i].fail_energy, "fail_block": out[i].fail_block,
+                "n_energies": out[i].n_energies, "queue_s": out[i].queue_s,
+                "latency_s": out[i].latency_s} for i in range(n.value)]
+        return res, pend.value
 
     def kernel_stats(self, cls):
         n = ctypes.c_int64()

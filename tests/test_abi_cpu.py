@@ -36,14 +36,17 @@ def test_library_exports_every_declared_symbol():
     assert sorted(Q.exported_symbols()) == _declared()
 
 
-def test_problem_struct_layout_matches_c(tmp_path):
+@pytest.mark.parametrize("cname,pystruct", [("qtx_rgf_problem", "Problem"),
+                                             ("qtx_rgf_completion", "Completion")])
+def test_struct_layout_matches_c(tmp_path, cname, pystruct):
     """Compile a tiny C program against the header (gcc, host only) and
     compare sizeof/offsetof with the ctypes mirror."""
-    fields = [f[0] for f in Q.Problem._fields_]
+    S = getattr(Q, pystruct)
+    fields = [f[0] for f in S._fields_]
     prog = ["#include <stdio.h>", "#include <stddef.h>", '#include "qtx_rgf.h"',
-            "int main(void){", 'printf("%zu\\n", sizeof(qtx_rgf_problem));']
+            "int main(void){", 'printf("%%zu\\n", sizeof(%s));' % cname]
     for f in fields:
-        prog.append('printf("%%zu\\n", offsetof(qtx_rgf_problem, %s));' % f)
+        prog.append('printf("%%zu\\n", offsetof(%s, %s));' % (cname, f))
     prog.append("return 0;}")
     c = tmp_path / "layout.c"
     c.write_text("\n".join(prog))
@@ -51,9 +54,9 @@ def test_problem_struct_layout_matches_c(tmp_path):
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)],
                    check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
-    assert int(out[0]) == ctypes.sizeof(Q.Problem)
+    assert int(out[0]) == ctypes.sizeof(S)
     for f, off in zip(fields, out[1:]):
-        assert int(off) == getattr(Q.Problem, f).offset, f
+        assert int(off) == getattr(S, f).offset, f
 
 
 @pytest.mark.parametrize("n,b", [(1, 8), (2, 32), (8, 32), (32, 512), (17, 100)])
