@@ -12,6 +12,17 @@ Prints one JSON line: energy-points/s, ms per step, the roofline of the
 dominant kernel (complex FP64 GEMM on the matrix cores, HIP-event timed on
 its launch stream inside the library) and the CPU oracle's rate on a bounded
 sample of the same workload.
+
+Other workloads (one JSON line each, not part of the default run):
+  --mode mixed   the same workload with complex64 FP32-matrix-core products
+                 and FP64 inverses; per-output error against the FP64 path on
+                 every energy and against the CPU oracle on sampled energies.
+  --mode uneven  512 independent single-energy solves of mixed block size
+                 {64..768}, block count 8..128, half G-type, half W-type:
+                 merged batches against a per-solve loop.
+  --mode serve   a Poisson stream of G-type requests of mixed shape through
+                 the request loop (qtx_rgf_submit/poll) against a per-solve
+                 loop on the same arrival trace: throughput, p50/p99 latency.
 """
 
 import argparse
@@ -37,6 +48,8 @@ MEASURED_TRAFFIC_BYTES_PER_LAUNCH = None
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--mode", default="plain",
+                    choices=["plain", "mixed", "uneven", "serve"])
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-blocks", type=int, default=32)
@@ -50,6 +63,15 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy a 1 GiB device buffer three times "
                          "(reference kernel for HBM byte counters)")
+    ap.add_argument("--solves", type=int, default=512, help="uneven: solve count")
+    ap.add_argument("--wave-gib", type=float, default=140.0,
+                    help="uneven: device memory for the inputs/outputs of one wave")
+    ap.add_argument("--requests", type=int, default=1000, help="serve: requests per rate")
+    ap.add_argument("--rates", default="50,100,200,400", help="serve: arrivals per second")
+    ap.add_argument("--pool-gib", type=float, default=96.0,
+                    help="serve: device memory for requests admitted by the client")
+    ap.add_argument("--ws-gib", type=float, default=64.0,
+                    help="uneven/serve: library workspace budget")
     return ap.parse_args()
 
 
@@ -96,16 +118,25 @@ def cpu_baseline(p, n_cpu):
                       "%.1f s" % (len(idx), len(E_all), idx, dt)}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py runs on exactly one GPU; --gpus %d is not supported "
-              "(energies shard across GPUs with no exchange, see the design notes)"
-              % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def _gemm_roofline(ctx, cls, peak, label):
+    st = ctx.kernel_stats(cls)
+    if not st["launches"]:
+        return None
+    avg_ms = st["ms"] / st["launches"]
+    fl_launch = st["flops"] / st["launches"]
+    ach = fl_launch / (avg_ms * 1e-3) / 1e12
+    return {"bound": "mfma", "kernel": label,
+            "achieved": round(ach, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+            "traffic": MEASURED_TRAFFIC_BYTES_PER_LAUNCH if cls == "zgemm" else None,
+            "launches": st["launches"], "avg_launch_ms": round(avg_ms, 4),
+            "algorithmic_flops_per_launch": fl_launch,
+            "algorithmic_bytes_per_launch": st["bytes"] / st["launches"]}
+
+
+def run_plain(args, mixed=False):
     import torch
     from paper_2508_19138_amd import qtx_rgf as Q
-    assert torch.cuda.is_available(), "bench.py needs the GPU"
     n, b, n_e = args.n_blocks, args.block_size, args.energies
 
     p, H, (sr, sl, sg) = build_inputs(n, b, n_e, args.seed)
@@ -117,8 +148,9 @@ def main():
     torch.cuda.synchronize()
 
     ctx = Q.Context(0, profile=not args.no_profile)
+    prec = Q.QTX_MIXED if mixed else Q.QTX_FP64
     prob = Q.make_g_problem(E, H, (sr, None, None), (sl, None, None),
-                            (sg, None, None), XR, XL, XG)
+                            (sg, None, None), XR, XL, XG, precision=prec)
     for _ in range(args.warmup):
         ctx.solve_batch([prob])
         assert prob.status == 0, prob.status
@@ -135,23 +167,24 @@ def main():
     eps = n_e * args.steps / dt
     flops_e = Q.flops_per_energy(Q.QTX_KIND_G, n, b, 2, False)
     tflops = flops_e * n_e * args.steps / dt / 1e12
-    roof = None
+    roof, kt = None, None
     if not args.no_profile:
-        st = ctx.kernel_stats("zgemm")
-        if st["launches"]:
-            avg_ms = st["ms"] / st["launches"]
-            fl_launch = st["flops"] / st["launches"]
-            ach = fl_launch / (avg_ms * 1e-3) / 1e12
-            roof = {"bound": "mfma", "kernel": "zgemm_kernel (complex FP64, 4 real MFMA per complex product)",
-                    "achieved": round(ach, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(ach / FP64_MFMA_PEAK_TFLOPS, 4),
-                    "traffic": MEASURED_TRAFFIC_BYTES_PER_LAUNCH,
-                    "launches": st["launches"], "avg_launch_ms": round(avg_ms, 4),
-                    "algorithmic_flops_per_launch": fl_launch,
-                    "algorithmic_bytes_per_launch": st["bytes"] / st["launches"]}
-        inv = ctx.kernel_stats("inverse")
-        elem = ctx.kernel_stats("elementwise")
+        if mixed:
+            roof = _gemm_roofline(ctx, "cgemm", FP32_MFMA_PEAK_TFLOPS,
+                                  "cgemm_kernel (complex64 operands, 4 real FP32 MFMA per complex product)")
+        else:
+            roof = _gemm_roofline(ctx, "zgemm", FP64_MFMA_PEAK_TFLOPS,
+                                  "zgemm_kernel (complex FP64, 4 real MFMA per complex product)")
+        kt = {k: round(ctx.kernel_stats(k)["ms"], 1)
+              for k in ("zgemm", "cgemm", "inverse", "elementwise")}
+        if mixed:
+            kt["fp64_zgemm_tflops"] = _tf(ctx.kernel_stats("zgemm"))
+            kt["fp32_cgemm_tflops"] = _tf(ctx.kernel_stats("cgemm"))
     ctx.close()
+    errors = None
+    if mixed:
+        with Q.Context(0, budget_bytes=8 << 30) as ctx64:
+            errors = mixed_errors(ctx64, p, E, H, (sr, sl, sg), (XR, XL, XG), args)
     if args.copy_calibration:
         x = torch.empty(1 << 26, dtype=torch.complex128, device="cuda:0")   # 1 GiB
         x.fill_(1.0)
@@ -162,7 +195,7 @@ def main():
         del x, y
 
     cpu = None
-    if args.cpu_energies > 0:
+    if args.cpu_energies > 0 and not mixed:
         cpu = cpu_baseline(p, args.cpu_energies)
 
     out = {
@@ -170,10 +203,11 @@ def main():
         "value": round(eps, 4), "unit": "energy-points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "plain FP64 batched RGF (G-type): complex128 block-tridiagonal, "
+        "dtype": "c64-mfma/f64" if mixed else "f64", "data": "synthetic",
+        "config": {"workload": "%s batched RGF (G-type): complex128 block-tridiagonal, "
                                "%d blocks of %dx%d, %d energies on [-2,2], block-diagonal Sigma, "
-                               "outputs G^R/G^</G^> diag+upper+lower" % (n, b, b, n_e),
+                               "outputs G^R/G^</G^> diag+upper+lower"
+                               % ("mixed-precision" if mixed else "plain FP64", n, b, b, n_e),
                    "n_blocks": n, "block_size": b, "n_energies": n_e, "seed": args.seed},
         "tflops": round(tflops, 3),
         "pct_fp64_mfma_peak": round(100.0 * tflops / FP64_MFMA_PEAK_TFLOPS, 2),
@@ -181,10 +215,404 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    if not args.no_profile:
-        out["kernel_time_ms"] = {"zgemm": round(st["ms"], 1), "inverse": round(inv["ms"], 1),
-                                 "elementwise": round(elem["ms"], 1)}
+    if mixed:
+        out["mode"] = "mixed"
+        out["errors"] = errors
+    if kt is not None:
+        out["kernel_time_ms"] = kt
     print(json.dumps(out), flush=True)
+
+
+def _tf(st):
+    return round(st["flops"] / (st["ms"] * 1e-3) / 1e12, 3) if st["ms"] else None
+
+
+def _rel_blocks(x, y):
+    """max over blocks of ||x - y||_F / ||y||_F (blocks on the last two axes)."""
+    import torch
+    d = torch.linalg.matrix_norm(x - y)
+    r = torch.linalg.matrix_norm(y)
+    return float((d / torch.clamp(r, min=1e-300)).max())
+
+
+def mixed_errors(ctx, p, E, H, sig, Xmix, args):
+    """Per-output error of the mixed-precision result: against the FP64
+    library path on every energy, and against the CPU oracle on sampled
+    energies."""
+    import torch
+    from paper_2508_19138_amd import qtx_rgf as Q
+    from paper_2508_19138_amd import synth
+    from oracle import rgf_selected, assemble_g
+    n, b, n_e = p["n"], p["b"], len(E)
+    sr, sl, sg = sig
+    names = ("G^R", "G^<", "G^>")
+    parts = ("diag", "upper", "lower")
+    vs_fp64 = {}
+    ch = 8                                    # FP64 reference in energy chunks
+    for e0 in range(0, n_e, ch):
+        e1 = min(n_e, e0 + ch)
+        X64 = tuple(tuple(torch.empty_like(t[e0:e1]) for t in T) for T in Xmix)
+        Ec = np.ascontiguousarray(E[e0:e1])
+        prob = Q.make_g_problem(Ec, H, (sr[e0:e1], None, None), (sl[e0:e1], None, None),
+                                (sg[e0:e1], None, None), *X64)
+        ctx.solve_batch([prob])
+        torch.cuda.synchronize()
+        for nm, A, B in zip(names, Xmix, X64):
+            for pt, a, bb in zip(parts, A, B):
+                k = "%s %s" % (nm, pt)
+                vs_fp64[k] = max(vs_fp64.get(k, 0.0), _rel_blocks(a[e0:e1], bb))
+        del X64
+    vs_oracle = {}
+    idx = [0, n_e // 2]
+    srs, sls, sgs = p["sigma_scalars"]
+    z = np.zeros((n - 1, b, b), np.complex128)
+    for e in idx:
+        A = assemble_g(E[e], p["H"], (synth.eye_blocks(srs[e], b), None, None))
+        XR, XS = rgf_selected(A, [(synth.eye_blocks(sls[e], b), z, z),
+                                  (synth.eye_blocks(sgs[e], b), z, z)])
+        for nm, ref, mix in zip(names, [XR] + list(XS), Xmix):
+            for pt, r, m in zip(parts, ref, mix):
+                key = "%s %s" % (nm, pt)
+                err = _rel_blocks(m[e].cpu(), torch.from_numpy(np.asarray(r)))
+                vs_oracle[key] = max(vs_oracle.get(key, 0.0), err)
+    return {"metric": "max over blocks of ||X_mixed - X_ref||_F / ||X_ref||_F",
+            "vs_fp64_library_all_energies": vs_fp64,
+            "vs_cpu_oracle": vs_oracle, "oracle_energy_indices": idx}
+
+
+# ------------------------------------------------------------ uneven batch --
+
+def _cn_dev(gen, shape, var):
+    import torch
+    z = torch.randn(shape, dtype=torch.complex128, device="cuda:0", generator=gen)
+    return z * np.sqrt(var)
+
+
+def _herm_bt_dev(gen, n, b, scale=1.0):
+    """Device draw of the Hermitian block-tridiagonal generator: H_ii =
+    (X + X^dagger)/2, X ~ CN(0, 1/b); H_{i,i+1} ~ CN(0, 0.25/b); lower =
+    upper^dagger (left to the library: passed as NULL)."""
+    X = _cn_dev(gen, (n, b, b), 1.0 / b)
+    d = 0.5 * (X + X.conj().transpose(1, 2))
+    del X
+    u = _cn_dev(gen, (max(n - 1, 0), b, b), 0.25 / b)
+    if scale != 1.0:
+        d, u = d * scale, u * scale
+    return d.contiguous(), u.contiguous()
+
+
+def _eye_dev(scal, b):
+    """[n_e, n] complex scalars -> [n_e, n, b, b] multiples of the identity."""
+    import torch
+    s = torch.from_numpy(np.ascontiguousarray(scal)).to("cuda:0")
+    out = torch.zeros(s.shape + (b, b), dtype=torch.complex128, device="cuda:0")
+    out.diagonal(dim1=-2, dim2=-1).copy_(s[..., None].expand(s.shape + (b,)))
+    return out
+
+
+def _outs_dev(n_e, n, b):
+    import torch
+    e = lambda k: torch.empty((n_e, k, b, b), dtype=torch.complex128, device="cuda:0")
+    return (e(n), e(n - 1), e(n - 1))
+
+
+def _solve_bytes(spec, n_e=1):
+    n, b = spec["n"], spec["b"]
+    blk = 16 * b * b
+    if spec["kind"] == "G":
+        return blk * (2 * n + 3 * n * n_e + 9 * n * n_e)
+    return blk * (2 * n + 5 * n * n_e + 9 * n * n_e)
+
+
+def _uneven_problem(spec):
+    """Inputs/outputs of one single-energy solve drawn on the device with the
+    G-type / W-type generators (same distributions as the seeded host
+    generators used by the tests)."""
+    import torch
+    from paper_2508_19138_amd import qtx_rgf as Q
+    from paper_2508_19138_amd import synth
+    n, b = spec["n"], spec["b"]
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(spec["seed"])
+    E = np.array([spec["E"]])
+    keep = {"E": E}
+    if spec["kind"] == "G":
+        Hd, Hu = _herm_bt_dev(gen, n, b)
+        sr, sl, sg = synth.g_sigma_scalars(E, n)
+        keep["ins"] = ((Hd, Hu, None), (_eye_dev(sr, b), None, None),
+                       (_eye_dev(sl, b), None, None), (_eye_dev(sg, b), None, None))
+        keep["outs"] = (_outs_dev(1, n, b), _outs_dev(1, n, b), _outs_dev(1, n, b))
+        keep["prob"] = Q.make_g_problem(E, *keep["ins"], *keep["outs"])
+    else:
+        Vd, Vu = _herm_bt_dev(gen, n, b, 0.5)
+        Phd, Phu = _herm_bt_dev(gen, n, b, 0.5)
+        eye = torch.eye(b, dtype=torch.complex128, device="cuda:0")
+        Prd = (0.5 * (Phd + 0.1 * spec["E"] * eye) - 0.01j * eye)[None].contiguous()
+        Pru = (0.5 * Phu)[None].contiguous()
+        Prl = Pru[0].conj().transpose(1, 2)[None].contiguous()
+        del Phd, Phu
+        f = synth.fermi(E)
+        fb = synth.one_minus_fermi(E)
+        Pl = _eye_dev(np.broadcast_to((1j * 0.02 * f)[:, None], (1, n)), b)
+        Pg = _eye_dev(np.broadcast_to((-1j * 0.02 * fb)[:, None], (1, n)), b)
+        keep["ins"] = ((Vd, Vu, None), (Prd, Pru, Prl), (Pl, None, None), (Pg, None, None))
+        keep["outs"] = (_outs_dev(1, n, b), _outs_dev(1, n, b), _outs_dev(1, n, b))
+        keep["prob"] = Q.make_w_problem(*keep["ins"], *keep["outs"])
+    return keep
+
+
+def run_uneven(args):
+    import torch
+    from paper_2508_19138_amd import qtx_rgf as Q
+    from paper_2508_19138_amd import synth
+    specs = synth.uneven_specs(args.seed, args.solves)
+    cap = int(args.wave_gib * 2 ** 30)
+    waves, cur, used = [], [], 0
+    for sp in specs:
+        by = _solve_bytes(sp)
+        if cur and used + by > cap:
+            waves.append(cur)
+            cur, used = [], 0
+        cur.append(sp)
+        used += by
+    if cur:
+        waves.append(cur)
+    flops = {id(sp): Q.flops_per_energy(Q.QTX_KIND_G if sp["kind"] == "G" else Q.QTX_KIND_W,
+                                        sp["n"], sp["b"], 2, sp["kind"] == "W", False)
+             for sp in specs}
+    ws = int(args.ws_gib * 2 ** 30)
+    ctx = Q.Context(0, budget_bytes=ws, profile=False)
+    # warm-up: tile tuning for every block size and both kinds, then the
+    # first wave once (workspace growth) -- untimed
+    for b in sorted({sp["b"] for sp in specs}):
+        for kind in ("G", "W"):
+            w = _uneven_problem({"kind": kind, "n": 3, "b": b, "E": 0.1, "seed": 1})
+            ctx.solve_batch([w["prob"]])
+    t_merged, t_loop, tf_total = 0.0, 0.0, 0.0
+    for wi, wave in enumerate(waves):
+        probs = [_uneven_problem(sp) for sp in wave]
+        torch.cuda.synchronize()
+        if wi == 0:
+            ctx.solve_batch([k["prob"] for k in probs])
+            torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.solve_batch([k["prob"] for k in probs])
+        torch.cuda.synchronize()
+        t_merged += time.perf_counter() - t0
+        assert st == Q.QTX_OK, st
+        t0 = time.perf_counter()
+        for k in probs:
+            ctx.solve_batch([k["prob"]])
+        torch.cuda.synchronize()
+        t_loop += time.perf_counter() - t0
+        tf_total += sum(flops[id(sp)] for sp in wave)
+        print("wave %d/%d: %d solves, merged %.3f s, loop %.3f s (cumulative)"
+              % (wi + 1, len(waves), len(wave), t_merged, t_loop), file=sys.stderr, flush=True)
+        del probs
+        torch.cuda.empty_cache()
+    ctx.close()
+    n_sol = len(specs)
+    out = {
+        "mode": "uneven",
+        "metric": "RGF energy-points/s + % FP64 MFMA peak; p50/p99 solve latency",
+        "value": round(n_sol / t_merged, 3), "unit": "energy-points/s", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batched uneven solves: %d independent single-energy complex128 "
+                               "RGF solves, b from {64,128,256,384,512,768}, n from 8..128, "
+                               "half G-type half W-type (W with W^< W^> outputs), merged "
+                               "batches in %d memory waves" % (n_sol, len(waves)),
+                   "solves": n_sol, "waves": len(waves), "seed": args.seed},
+        "merged": {"s": round(t_merged, 3), "energy_points_per_s": round(n_sol / t_merged, 3),
+                   "tflops": round(tf_total / t_merged / 1e12, 3),
+                   "pct_fp64_mfma_peak": round(100 * tf_total / t_merged / 1e12 / FP64_MFMA_PEAK_TFLOPS, 2)},
+        "per_solve_loop": {"s": round(t_loop, 3), "energy_points_per_s": round(n_sol / t_loop, 3),
+                           "tflops": round(tf_total / t_loop / 1e12, 3)},
+        "speedup_merged_vs_loop": round(t_loop / t_merged, 3),
+        "total_canonical_tflop": round(tf_total / 1e12, 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
+# ----------------------------------------------------------------- serving --
+
+def _serve_trace(args, rate):
+    rng = np.random.default_rng(args.seed + int(rate))
+    R = args.requests
+    gaps = rng.exponential(1.0 / rate, size=R)
+    arr = np.cumsum(gaps) - gaps[0]
+    reqs = []
+    for i in range(R):
+        reqs.append({"n": int(rng.integers(8, 65)), "b": int(rng.choice([128, 192, 256])),
+                     "ne": int(rng.integers(1, 17)), "t": float(arr[i]),
+                     "e0": float(rng.uniform(-2.0, 1.0))})
+    return reqs
+
+
+class _ServeInputs:
+    """Shared read-only H per block size (prefix views per block count);
+    per-request self-energies and outputs are made when the client admits
+    the request."""
+
+    def __init__(self, seed):
+        import torch
+        self.H = {}
+        for b in (128, 192, 256):
+            gen = torch.Generator(device="cuda:0")
+            gen.manual_seed(seed + b)
+            self.H[b] = _herm_bt_dev(gen, 64, b)
+
+    def make(self, r):
+        from paper_2508_19138_amd import qtx_rgf as Q
+        from paper_2508_19138_amd import synth
+        n, b, ne = r["n"], r["b"], r["ne"]
+        E = np.ascontiguousarray(np.linspace(r["e0"], r["e0"] + 1.0, ne))
+        sr, sl, sg = synth.g_sigma_scalars(E, n)
+        Hd, Hu = self.H[b]
+        ins = ((Hd[:n], Hu[:n - 1], None), (_eye_dev(sr, b), None, None),
+               (_eye_dev(sl, b), None, None), (_eye_dev(sg, b), None, None))
+        outs = (_outs_dev(ne, n, b), _outs_dev(ne, n, b), _outs_dev(ne, n, b))
+        return {"E": E, "ins": ins, "outs": outs,
+                "prob": Q.make_g_problem(E, *ins, *outs)}
+
+
+def _req_bytes(r):
+    return 16 * r["b"] * r["b"] * r["ne"] * r["n"] * 12
+
+
+def _lat_summary(lat, n_e_tot, t_span):
+    lat = np.asarray(lat)
+    return {"energy_points_per_s": round(n_e_tot / t_span, 2),
+            "requests_per_s": round(len(lat) / t_span, 2),
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+            "mean_latency_s": round(float(lat.mean()), 4), "span_s": round(t_span, 3)}
+
+
+def _serve_run(ctx, inputs, reqs, cap, served):
+    """Replay the arrival trace; returns (latencies, span).  served: submit
+    to the request loop; otherwise solve each request alone, in arrival
+    order, as soon as the previous one is done."""
+    import torch
+    R = len(reqs)
+    lat = [None] * R
+    queue, nxt, used, done = [], 0, 0, 0
+    live = {}
+    t0 = time.perf_counter()
+    last = t0
+    while done < R:
+        now = time.perf_counter() - t0
+        while nxt < R and reqs[nxt]["t"] <= now:
+            queue.append(nxt)
+            nxt += 1
+        if served:
+            while queue and (used + _req_bytes(reqs[queue[0]]) <= cap or not live):
+                i = queue.pop(0)
+                k = inputs.make(reqs[i])
+                torch.cuda.current_stream().synchronize()     # inputs written
+                live[ctx.submit(k["prob"])] = (i, k)
+                used += _req_bytes(reqs[i])
+            wait = 1 if (nxt < R or queue) else 50
+            cs, _ = ctx.poll(cap=64, wait_ms=wait)
+            tn = time.perf_counter()
+            for c in cs:
+                i, k = live.pop(c["ticket"])
+                assert c["status"] == 0, c
+                lat[i] = (tn - t0) - reqs[i]["t"]
+                used -= _req_bytes(reqs[i])
+                done += 1
+                last = tn
+        else:
+            if not queue:
+                dt = reqs[nxt]["t"] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                continue
+            i = queue.pop(0)
+            k = inputs.make(reqs[i])
+            torch.cuda.current_stream().synchronize()         # inputs written
+            ctx.solve_batch([k["prob"]])
+            assert k["prob"].status == 0
+            tn = time.perf_counter()
+            lat[i] = (tn - t0) - reqs[i]["t"]
+            done += 1
+            last = tn
+            del k
+    return lat, last - t0
+
+
+def run_serve(args):
+    import torch
+    from paper_2508_19138_amd import qtx_rgf as Q
+    rates = [float(x) for x in args.rates.split(",") if x]
+    ws = int(args.ws_gib * 2 ** 30)
+    cap = int(args.pool_gib * 2 ** 30)
+    inputs = _ServeInputs(args.seed)
+    results = []
+    ctx_s = Q.Context(0, budget_bytes=ws)
+    ctx_l = Q.Context(0, budget_bytes=ws)
+    # warm-up (tile tuning, workspace, request-loop start): untimed
+    warm = [{"n": 8, "b": b, "ne": 2, "t": 0.0, "e0": -0.5} for b in (128, 192, 256)]
+    for r in warm:
+        k = inputs.make(r)
+        torch.cuda.synchronize()
+        ctx_l.solve_batch([k["prob"]])
+        t = ctx_s.submit(k["prob"])
+        while True:
+            cs, _ = ctx_s.poll(cap=4, wait_ms=100)
+            if any(c["ticket"] == t for c in cs):
+                break
+    for rate in rates:
+        reqs = _serve_trace(args, rate)
+        n_e_tot = sum(r["ne"] for r in reqs)
+        row = {"rate_per_s": rate, "requests": len(reqs), "energy_points": n_e_tot}
+        for name, ctx, served in (("served", ctx_s, True), ("per_solve_loop", ctx_l, False)):
+            lat, span = _serve_run(ctx, inputs, reqs, cap, served)
+            row[name] = _lat_summary(lat, n_e_tot, span)
+            print("rate %g %s: %s" % (rate, name, row[name]), file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+        row["throughput_ratio_served_vs_loop"] = round(
+            row["served"]["energy_points_per_s"] / row["per_solve_loop"]["energy_points_per_s"], 3)
+        results.append(row)
+    ctx_s.close()
+    ctx_l.close()
+    top = results[-1]
+    out = {
+        "mode": "serve",
+        "metric": "RGF energy-points/s + % FP64 MFMA peak; p50/p99 solve latency",
+        "value": top["served"]["energy_points_per_s"], "unit": "energy-points/s",
+        "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "serving stream: Poisson arrivals, %d G-type requests per rate, "
+                               "each n in 8..64 blocks of b in {128,192,256}, 1..16 energies "
+                               "in a window of width 1 in [-2,2]; client admits requests into "
+                               "%.0f GiB of device memory in arrival order; latency = arrival "
+                               "to observed completion" % (args.requests, args.pool_gib),
+                   "rates_per_s": rates, "seed": args.seed},
+        "rates": results,
+    }
+    print(json.dumps(out), flush=True)
+
+
+FP32_MFMA_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU; --gpus %d is not supported "
+              "(energies shard across GPUs with no exchange, see the design notes)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.mode == "plain":
+        run_plain(args)
+    elif args.mode == "mixed":
+        run_plain(args, mixed=True)
+    elif args.mode == "uneven":
+        run_uneven(args)
+    else:
+        run_serve(args)
 
 
 if __name__ == "__main__":

@@ -132,8 +132,11 @@ typedef struct {
  * and kept below `hbm_budget_bytes` (0 = 90% of the free device memory at
  * creation); a batch larger than the budget is processed in energy chunks.
  * `hip_stream` is a hipStream_t to launch on (NULL = a stream owned by the
- * context).  `flags` bit 0 (QTX_FLAG_PROFILE) records per-kernel-class
- * launch timings (see qtx_rgf_kernel_stats). */
+ * context, created non-blocking: it does not wait for work the caller
+ * queued on other streams, so inputs must be complete -- e.g. the caller's
+ * stream synchronised -- before a problem is solved or submitted).  `flags`
+ * bit 0 (QTX_FLAG_PROFILE) records per-kernel-class launch timings (see
+ * qtx_rgf_kernel_stats). */
 #define QTX_FLAG_PROFILE 1u
 qtx_status qtx_rgf_create(qtx_rgf_ctx** out, int device,
                           uint64_t hbm_budget_bytes, void* hip_stream,

@@ -50,6 +50,7 @@ class Job:
                         (G.dev(p["P_l"][0]), None, None),
                         (G.dev(p["P_g"][0]), None, None))
             self.prob = Q.make_w_problem(*self.ins, self.XR, self.XL, self.XG)
+        torch.cuda.synchronize()          # fills done before the library's stream reads
 
     def results(self):
         torch.cuda.synchronize()
