@@ -25,14 +25,4 @@ __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -
 __device__ __forceinline__ double2 cscale(zc s, double2 a) {
   return make_double2(s.re * a.x - s.im * a.y, s.re * a.y + s.im * a.x);
 }
-// 1/z = conj(z) / |z|^2, with a scaling step so that |z|^2 neither
-// overflows nor underflows for representable z.
-__device__ __forceinline__ double2 crecip(double2 z) {
-  double s = fmax(fabs(z.x), fabs(z.y));
-  if (s == 0.0) return make_double2(1.0 / s, 0.0);   // inf: caller flags it
-  double xr = z.x / s, xi = z.y / s;
-  double d = s * (xr * xr + xi * xi);
-  return make_double2(xr / d, -xi / d);
-}
-
 }  // namespace qtx

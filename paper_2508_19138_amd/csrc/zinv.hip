@@ -27,14 +27,68 @@
 namespace qtx {
 namespace {
 
+// Pivot search key of a candidate row r with |z|^2 = v (finite, >= 0): the
+// bits of v with the low 10 mantissa bits replaced by 1023 - r.  Keys order
+// as v (to 42 mantissa bits) and then by lowest row, so the maximum key is
+// the partial-pivoting choice and names its row; non-candidates use -1.
+__device__ __forceinline__ double pivot_key(double v, int r) {
+  const unsigned long long u = ((unsigned long long)__double_as_longlong(v) & ~1023ull) |
+                               (unsigned long long)(1023 - r);
+  return __longlong_as_double((long long)u);
+}
+__device__ __forceinline__ int pivot_row(double key) {
+  return 1023 - (int)((unsigned long long)__double_as_longlong(key) & 1023ull);
+}
+
+// x moved across lanes by a DPP pattern (both 32-bit halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffff), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Maximum over the 64 lanes of a wave, returned in every lane: within rows
+// of 16 lanes by DPP (quad xor 1, quad xor 2, half-row mirror, row mirror,
+// after which every lane holds its row's maximum), then across the four
+// rows through scalar reads of one lane per row.
+__device__ __forceinline__ double lane_read(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_max(double x) {
+  x = fmax(x, dpp_move<0xB1>(x));     // quad_perm [1,0,3,2]
+  x = fmax(x, dpp_move<0x4E>(x));     // quad_perm [2,3,0,1]
+  x = fmax(x, dpp_move<0x141>(x));    // row_half_mirror
+  x = fmax(x, dpp_move<0x140>(x));    // row_mirror
+  return fmax(fmax(lane_read(x, 0), lane_read(x, 16)), fmax(lane_read(x, 32), lane_read(x, 48)));
+}
+
+// One division: z is scaled by an exact power of two so that |z'|^2 lies in
+// [1, 8), then 1/z = conj(z') / |z'|^2 scaled back.
+__device__ __forceinline__ double2 crecip_scaled(double2 z) {
+  const double s = fmax(fabs(z.x), fabs(z.y));
+  if (s == 0.0) return make_double2(1.0 / s, 0.0);   // inf: caller flags it
+  int ex;
+  (void)frexp(s, &ex);
+  const double xr = ldexp(z.x, -ex), xi = ldexp(z.y, -ex);
+  const double r = 1.0 / (xr * xr + xi * xi);
+  return make_double2(ldexp(xr * r, -ex), ldexp(-xi * r, -ex));
+}
+
 template <int R>
 __global__ __launch_bounds__(kInvThreads)
 void gj_panel_kernel(FlatLaunch L, int k0) {
   constexpr int NB = kPanel;
-  __shared__ double redv[kInvThreads / 64];
-  __shared__ int redr[kInvThreads / 64];
-  __shared__ int redbad[kInvThreads / 64];
-  __shared__ double2 prow[NB];
+  constexpr int NW = kInvThreads / 64;
+  // per column: each wave publishes its best key and that candidate's row;
+  // double buffered by column parity so one barrier per column suffices
+  __shared__ double keyS[2][NW];
+  __shared__ int badS[2][NW];
+  __shared__ double2 rowS[2][NW][NB];
   __shared__ int pivs[NB];
 
   const int di = find_desc(L.prefix, L.nd, blockIdx.x);
@@ -52,20 +106,43 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
   const int nbe = min(NB, b - k0);
   const int lo = k0 - k0 % kSuper;                // current super-panel
   const int hi = min(b, lo + kSuper);
+  const int code0 = d.code;
 
+  // Panel rows move between HBM and registers through LDS: 16 lanes per
+  // row in HBM (256-byte segments), one row per thread in registers.
+  __shared__ double2 stage[kInvThreads][NB + 1];
+  __shared__ int pcS[kInvThreads];
   double2 a[R][NB];
   int u[R];      // row already used as a pivot
   int pc[R];     // panel column this row pivots (-1 if none)
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int r = t + q * kInvThreads;
+    const int r0 = q * kInvThreads;
+    const int r = r0 + t;
     pc[q] = -1;
     u[q] = 1;
-    if (r < b) {
-      u[q] = (k0 == 0) ? 0 : ue[r];
+    if (r < b) u[q] = (k0 == 0) ? 0 : ue[r];
+    if (r0 < b) {                           // uniform across the workgroup
+      // unconditional loads (out-of-range entries read element 0 and are
+      // replaced by zero) so that all of them are in flight together
+      double2 v[NB];
 #pragma unroll
-      for (int c = 0; c < NB; ++c)
-        a[q][c] = (c < nbe) ? A[(long long)r * b + k0 + c] : make_double2(0.0, 0.0);
+      for (int i = 0; i < NB; ++i) {
+        const int idx = t + i * kInvThreads;
+        const int rl = idx / NB, c = idx % NB;
+        const bool ok = (r0 + rl < b) && (c < nbe);
+        v[i] = A[ok ? (long long)(r0 + rl) * b + k0 + c : 0];
+        if (!ok) v[i] = make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int idx = t + i * kInvThreads;
+        stage[idx / NB][idx % NB] = v[i];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < NB; ++c) a[q][c] = stage[t][c];
+      __syncthreads();
     } else {
 #pragma unroll
       for (int c = 0; c < NB; ++c) a[q][c] = make_double2(0.0, 0.0);
@@ -76,9 +153,9 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     if (c >= nbe) continue;      // uniform across the workgroup
+    const int par = c & 1;
     // ---- pivot search over unused rows -------------------------------
-    double bv = -1.0;
-    int bi = 0x7fffffff;
+    double key = -1.0;
     int bad = 0;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -86,50 +163,55 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
       if (r < b && !u[q]) {
         const double v = a[q][c].x * a[q][c].x + a[q][c].y * a[q][c].y;
         if (!(v <= 1.7976931348623157e308)) bad = 1;     // NaN or Inf
-        else if (v > bv) { bv = v; bi = r; }
+        else key = fmax(key, pivot_key(v, r));
       }
     }
+    const double wk = wave_max(key);
+    // the lane holding the wave's best candidate (keys are distinct) stores
+    // that row for the other waves
+    if (wk >= 0.0 && key == wk) {
+      const int qs = (pivot_row(wk) - t) / kInvThreads;
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ov = __shfl_xor(bv, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      const int ob = __shfl_xor(bad, off, 64);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-      bad |= ob;
+      for (int q = 0; q < R; ++q)
+        if (q == qs) {
+#pragma unroll
+          for (int cc = 0; cc < NB; ++cc) rowS[par][wave][cc] = a[q][cc];
+        }
     }
-    if (lane == 0) { redv[wave] = bv; redr[wave] = bi; redbad[wave] = bad; }
+    const int wbad = __any(bad);
+    if (lane == 0) { keyS[par][wave] = wk; badS[par][wave] = wbad; }
     __syncthreads();
-    bv = redv[0]; bi = redr[0]; bad = redbad[0];
+    double bk = keyS[par][0];
+    int bw = 0, anybad = badS[par][0];
 #pragma unroll
-    for (int w = 1; w < kInvThreads / 64; ++w) {
-      const double ov = redv[w];
-      const int oi = redr[w];
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-      bad |= redbad[w];
+    for (int w = 1; w < NW; ++w) {
+      const double ok = keyS[par][w];
+      if (ok > bk) { bk = ok; bw = w; }
+      anybad |= badS[par][w];
     }
-    // An unused row always remains (b - k0 - c > 0), so bi is a valid row
-    // unless every candidate was non-finite; then row 0 keeps indices in
-    // range and the failure is reported through info.
-    const int p = (bi == 0x7fffffff) ? 0 : bi;
+    // An unused row always remains (b - k0 - c > 0), so a candidate exists
+    // unless every one was non-finite; then row 0 keeps indices in range
+    // and the failure is reported through info.
+    int p = (bk >= 0.0) ? pivot_row(bk) : 0;
+    if (p >= b) p = 0;
+    double2 prow[NB];
+#pragma unroll
+    for (int cc = 0; cc < NB; ++cc) prow[cc] = rowS[par][bw][cc];
     if (t == 0 && first_bad == 0) {
-      const int code = d.code > 0 ? d.code : 1 + k0 + c;
-      if (bad) first_bad = -code;
-      else if (bv <= 0.0) first_bad = code;
+      const int code = code0 > 0 ? code0 : 1 + k0 + c;
+      const double pv = prow[c].x * prow[c].x + prow[c].y * prow[c].y;
+      if (anybad || bk < 0.0) first_bad = -code;
+      else if (pv <= 0.0) first_bad = code;
     }
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int r = t + q * kInvThreads;
-      if (r == p) {
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc) prow[cc] = a[q][cc];
+    for (int q = 0; q < R; ++q)
+      if (t + q * kInvThreads == p) {
         u[q] = 1;
         pc[q] = c;
       }
-    }
     if (t == 0) pivs[c] = p;
-    __syncthreads();
     // ---- eliminate column k0 + c from every row ---------------------
-    const double2 inv = crecip(prow[c]);
+    const double2 inv = crecip_scaled(prow[c]);
     double2 ps[NB];
 #pragma unroll
     for (int cc = 0; cc < NB; ++cc) ps[cc] = (cc == c) ? inv : cmul(prow[cc], inv);
@@ -148,37 +230,59 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
       }
     }
   }
+  __syncthreads();                 // pivs[] complete before the write-back
 
-  // ---- write back the panel, Panel'' and the gathered pivot rows ---------
+  // ---- pivot rows within the super-panel (this panel's columns zeroed):
+  // they lie outside the panel columns, so they are read before the panel
+  // is written back
+  constexpr int kG = NB * kSuper / kInvThreads;
+  static_assert(NB * kSuper % kInvThreads == 0, "gather split");
+  double2 gv[kG];
+#pragma unroll
+  for (int g = 0; g < kG; ++g) {
+    const int idx = t + g * kInvThreads;
+    const int c = idx / kSuper, j = lo + idx % kSuper;
+    const int p = (c < nbe) ? pivs[c] : -1;
+    const bool ok = (j < hi) && (p >= 0) && (j < k0 || j >= k0 + nbe);
+    gv[g] = A[ok ? (long long)p * b + j : 0];
+    if (!ok) gv[g] = make_double2(0.0, 0.0);
+  }
+
+  // ---- write back the panel and Panel'' (panel minus I at the pivots) ----
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int r = t + q * kInvThreads;
-    if (r >= b) continue;
-    ue[r] = u[q];
+    const int r0 = q * kInvThreads;
+    if (r0 >= b) continue;                  // uniform across the workgroup
+    if (r0 + t < b) ue[r0 + t] = u[q];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      if (c < nbe) A[(long long)r * b + k0 + c] = a[q][c];
-      double2 v = a[q][c];
-      if (pc[q] == c) v.x -= 1.0;
-      pan[(long long)r * NB + c] = v;
+    for (int c = 0; c < NB; ++c) stage[t][c] = a[q][c];
+    pcS[t] = pc[q];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int idx = t + i * kInvThreads;
+      const int rl = idx / NB, c = idx % NB;
+      const int r = r0 + rl;
+      if (r < b) {
+        double2 v = stage[rl][c];
+        if (c < nbe) A[(long long)r * b + k0 + c] = v;
+        if (pcS[rl] == c) v.x -= 1.0;
+        pan[(long long)r * NB + c] = v;
+      }
     }
+    __syncthreads();
   }
-  if (t == 0) {
-    for (int c = 0; c < nbe; ++c) pe[k0 + c] = pivs[c];
-    if (d.info) {
-      int* inf = d.info + e;
-      const int cur = (k0 == 0 && d.reset_info) ? 0 : *inf;
-      if (cur == 0) *inf = first_bad;
-    }
+  if (t < nbe) pe[k0 + t] = pivs[t];
+  if (t == 0 && d.info) {
+    int* inf = d.info + e;
+    const int cur = (k0 == 0 && d.reset_info) ? 0 : *inf;
+    if (cur == 0) *inf = first_bad;
   }
-  // pivot rows within the super-panel (this panel's columns zeroed)
-  for (int c = 0; c < NB; ++c) {
-    const int p = (c < nbe) ? pivs[c] : -1;
-    for (int j = lo + t; j < hi; j += kInvThreads) {
-      double2 v = make_double2(0.0, 0.0);
-      if (p >= 0 && (j < k0 || j >= k0 + nbe)) v = A[(long long)p * b + j];
-      br[(long long)c * b + j] = v;
-    }
+#pragma unroll
+  for (int g = 0; g < kG; ++g) {
+    const int idx = t + g * kInvThreads;
+    const int c = idx / kSuper, j = lo + idx % kSuper;
+    if (j < hi) br[(long long)c * b + j] = gv[g];
   }
 }
 
