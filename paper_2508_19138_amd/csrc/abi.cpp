@@ -35,9 +35,9 @@ size_t budget_now(qtx_rgf_ctx* c) {
 
 void ensure(qtx_rgf_ctx* c, char** p, size_t* have, size_t need) {
   if (*have >= need) return;
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->pool->sync();
   if (*p) {
-    c->exe->release();              // cached graphs refer to the old memory
+    c->pool->release();             // cached graphs refer to the old memory
     (void)hipFree(*p);
     *p = nullptr;
     *have = 0;
@@ -92,10 +92,11 @@ struct BusyGuard {
 
 void run_lanes_to_end(qtx_rgf_ctx* c, std::vector<Lane*>& lanes) {
   const bool prof = (c->flags & QTX_FLAG_PROFILE) != 0;
+  Executor& x = c->pool->exe(0);
   while (true) {
-    c->exe->build(lanes, kArenaLimit);
-    if (c->exe->empty()) break;
-    c->exe->flush(prof, c->graphs, c->stats);
+    x.build(lanes, kArenaLimit);
+    if (x.empty()) break;
+    x.flush(prof, c->graphs, c->stats);
   }
 }
 
@@ -155,12 +156,16 @@ qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
   const size_t cap = std::min(budget, total + 4096);
   ensure(c, &c->ws, &c->ws_bytes, std::max(cap, largest + 4096));
 
-  // admission and merged execution
+  // admission and merged execution: lanes are admitted in order while
+  // their workspace fits; each goes to the executor (stream) of its shape
+  // class, where lanes of the class share launches
   Regions reg(std::max(cap, largest + 4096));
+  Pool& P = *c->pool;
+  P.fork();
   std::vector<std::unique_ptr<Lane>> active;
+  std::vector<std::pair<Lane*, int>> fin;
   size_t next = 0;
-  while (next < pending.size() || !active.empty()) {
-    // admit in order while the next lane fits
+  while (next < pending.size() || P.busy()) {
     while (next < pending.size()) {
       const Pend& pd = pending[next];
       size_t off = 0;
@@ -172,42 +177,38 @@ qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
       L->ws_off = off;
       L->ws_bytes = pd.bytes;
       const qtx_rgf_problem& p = probs[pd.prob];
+      // a batch starts all its lanes together: lanes of every block size
+      // with the same operation structure share one stream in lockstep
+      const uint64_t cls = lane_class(plans[pd.prob], p, false);
+      const int xi = P.place(cls);
       build_lane(*L, p, plans[pd.prob], c->ws + off, pd.e0, pd.ec, d_E + e_off[pd.prob],
-                 d_info + e_off[pd.prob], c->tuner, c->stream);
+                 d_info + e_off[pd.prob], c->tuner, P.stream(xi));
+      L->cls = cls;                    // before add: the pool keys on it
+      P.add(L.get(), xi);
       active.push_back(std::move(L));
       ++next;
     }
-    if (active.empty()) {
+    if (!P.busy()) {
       c->err = "workspace admission stalled";
       throw Fail{QTX_ERR_NOMEM};
     }
-    std::vector<Lane*> lp;
-    for (auto& l : active) lp.push_back(l.get());
-    // with lanes waiting, stop the segment once a lane finishes so that its
-    // memory can be handed to the next lane
-    if (next < pending.size()) {
-      bool fin = false;
-      while (!fin) {
-        c->exe->build(lp, kArenaLimit, 1 << 30, true);
-        for (Lane* l : lp) fin |= l->done();
-        if (c->exe->empty()) break;
-        c->exe->flush(prof, c->graphs, c->stats);
-      }
-    } else {
-      run_lanes_to_end(c, lp);
+    // with lanes waiting for memory, a segment stops once a lane finishes
+    // so that its region is handed on promptly
+    P.step(kArenaLimit, 1 << 30, next < pending.size(), prof, c->graphs, c->stats, fin);
+    for (auto& f : fin) {
+      reg.release(f.first->ws_off, f.first->ws_bytes);
+      for (size_t i = 0; i < active.size(); ++i)
+        if (active[i].get() == f.first) {
+          active.erase(active.begin() + i);
+          break;
+        }
     }
-    for (size_t i = 0; i < active.size();) {
-      if (active[i]->done()) {
-        reg.release(active[i]->ws_off, active[i]->ws_bytes);
-        active.erase(active.begin() + i);
-      } else {
-        ++i;
-      }
-    }
+    fin.clear();
   }
+  P.join();
   std::vector<int> h_info(n_e_tot);
   HIPCHK(c, hipMemcpyAsync(h_info.data(), d_info, sizeof(int) * n_e_tot, hipMemcpyDeviceToHost, c->stream));
-  c->exe->sync_and_collect(c->stats);
+  P.sync_and_collect(c->stats);
   qtx_status worst = QTX_OK;
   for (int i = 0; i < np; ++i) {
     for (int e = 0; e < probs[i].n_energies; ++e) {
@@ -274,7 +275,16 @@ qtx_status qtx_rgf_create(qtx_rgf_ctx** out, int device, uint64_t budget, void* 
     }
     c->own_stream = true;
   }
-  c->exe.reset(new Executor(c->stream));
+  const char* ns = std::getenv("QTX_STREAMS");
+  int n_streams = ns ? std::atoi(ns) : 4;
+  n_streams = std::max(1, std::min(8, n_streams));
+  try {
+    c->pool.reset(new Pool(c->stream, n_streams));
+  } catch (const Fail&) {
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return QTX_ERR_HIP;
+  }
   *out = c;
   return QTX_OK;
 }
@@ -285,7 +295,7 @@ qtx_status qtx_rgf_destroy(qtx_rgf_ctx* c) {
   (void)hipSetDevice(c->device);
   qtx::stop_server(c);                   // drains the request loop first
   (void)hipStreamSynchronize(c->stream);
-  c->exe.reset();
+  c->pool.reset();
   if (c->ws) (void)hipFree(c->ws);
   if (c->aux) (void)hipFree(c->aux);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -308,8 +318,7 @@ qtx_status qtx_rgf_solve_batch(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int32_t n
     HIPCHK(c, hipSetDevice(c->device));
     return solve(c, probs, np);
   } catch (const Fail& f) {
-    (void)hipStreamSynchronize(c->stream);
-    try { c->exe->sync_and_collect(c->stats); } catch (...) {}
+    try { c->pool->sync_and_collect(c->stats); } catch (...) {}
     return (qtx_status)f.st;
   } catch (...) {
     c->err = "internal error";
@@ -411,7 +420,7 @@ qtx_status gemm_abi(bool fp32, qtx_rgf_ctx* c, char opa, char opb, int32_t m, in
     L.ops.push_back(o);
     std::vector<Lane*> lp{&L};
     run_lanes_to_end(c, lp);
-    c->exe->sync_and_collect(c->stats);
+    c->pool->exe(0).sync_and_collect(c->stats);
   } catch (const Fail& f) {
     return (qtx_status)f.st;
   }
@@ -473,7 +482,7 @@ qtx_status qtx_rgf_zinv(qtx_rgf_ctx* c, int32_t b, void* A, void* X, int32_t* in
     L.ops.push_back(o);
     std::vector<Lane*> lp{&L};
     run_lanes_to_end(c, lp);
-    c->exe->sync_and_collect(c->stats);
+    c->pool->exe(0).sync_and_collect(c->stats);
     HIPCHK(c, hipFree(work));
   } catch (const Fail& f) {
     if (work) (void)hipFree(work);

@@ -26,7 +26,7 @@ struct qtx_rgf_ctx {
   size_t aux_bytes = 0;
   std::string err;
   std::vector<qtx::KStat> stats = std::vector<qtx::KStat>(qtx::kNumClasses);
-  std::unique_ptr<qtx::Executor> exe;
+  std::unique_ptr<qtx::Pool> pool;       // executors on the context's streams
   qtx::Tuner tuner;
   bool graphs = true;
   bool busy = false;

@@ -663,6 +663,26 @@ void build_lane(Lane& lane, const qtx_rgf_problem& p, const Plan& q, char* ws,
       }
     }
   }
+  lane.cls = lane_class(q, p, true);
+  lane.work = 0;
+  for (const Op& o : lane.ops) lane.work += o.flops;
+}
+
+uint64_t lane_class(const Plan& q, const qtx_rgf_problem& p, bool by_block_size) {
+  // everything that shapes the operation sequence except the block count
+  // (and, optionally, the block size)
+  uint64_t k = by_block_size ? (uint64_t)q.b : 0;
+  k = k * 2 + q.is_w;
+  k = k * 2 + q.fp32;
+  k = k * 2 + q.general_ul;
+  k = k * 2 + q.need_hl;
+  k = k * 2 + q.bt_rhs[0];
+  k = k * 2 + q.bt_rhs[1];
+  k = k * 4 + (uint64_t)q.nr;
+  k = k * 2 + (p.WR_diag != nullptr);
+  k = k * 2 + (p.S.diag != nullptr);
+  k = k * 2 + (p.V.lower != nullptr);
+  return k;
 }
 
 }  // namespace qtx

@@ -28,4 +28,10 @@ void build_lane(Lane& lane, const qtx_rgf_problem& p, const Plan& q, char* ws,
                 int e0, int ec, const double* d_E, int* d_info, Tuner& tuner,
                 hipStream_t s);
 
+// Shape class of a problem's lanes: lanes of one class have the same
+// operation sequence up to its length (block count) and, without
+// `by_block_size`, up to the block size of its operands; lanes of one class
+// started together run in lockstep and share every launch.
+uint64_t lane_class(const Plan& q, const qtx_rgf_problem& p, bool by_block_size);
+
 }  // namespace qtx

@@ -81,6 +81,8 @@ int Tuner::measure(int b, bool fp32, hipStream_t s) {
   // chip several times over; operands hold a nonzero byte pattern
   const long long blk = (long long)b * b;
   const int batch = std::max(1, std::min(1024, (int)(8192LL * 4096 / blk)));
+  // timings are taken with the device otherwise idle (once per shape)
+  XCHK(hipDeviceSynchronize());
   void* buf = nullptr;
   if (hipMalloc(&buf, (size_t)(3 * batch) * blk * 16 + 4096) != hipSuccess) {
     (void)hipGetLastError();
@@ -171,17 +173,45 @@ static uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603u
 }
 
 // Signature: operations that may share a launch.
+// Products of any shape and tile preference share a launch: every tile
+// configuration accumulates each output element over k in the same order
+// (chunks of four in increasing k), so the tile chosen for a launch does
+// not change any result.
 static uint64_t signature(const Op& o) {
   uint64_t k = (uint64_t)o.k;
   if (o.k == OpK::Gemm)
     k |= ((uint64_t)(o.opa == 'C') << 8) | ((uint64_t)(o.opb == 'C') << 9) |
-         ((uint64_t)o.fp32 << 10) | ((uint64_t)o.cfg << 12);
+         ((uint64_t)o.fp32 << 10);
   return k;
+}
+
+// Tile configuration of a merged product launch: the tuned choice of its
+// largest product, moved to smaller tiles while the launch would not cover
+// the chip's compute units twice.
+static int group_cfg(const std::vector<std::pair<Lane*, Op*>>& ops) {
+  constexpr int kFill = 2 * 256;
+  const Op* big = ops[0].second;
+  for (auto& lo : ops)
+    if (lo.second->flops > big->flops) big = lo.second;
+  auto tiles = [&](int cfg) {
+    long long t = 0;
+    for (auto& lo : ops)
+      for (int q = 0; q < lo.second->count; ++q) {
+        const GemmDesc& g = lo.first->gd[lo.second->first + q];
+        t += (long long)gemm_tiles(cfg, g.M, g.N) * g.batch * std::max(1, g.batch2);
+      }
+    return t;
+  };
+  int cfg = big->cfg;
+  if (cfg == 1 && tiles(1) < kFill) cfg = 0;
+  if (cfg == 0 && tiles(0) < kFill) cfg = 2;
+  return cfg;
 }
 
 void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
   const Op& f = *ops[0].second;
   if (f.k == OpK::Gemm) {
+    const int cfg = group_cfg(ops);
     std::vector<GemmDesc> d;
     std::vector<int> pre(1, 0);
     double fl = 0, by = 0;
@@ -189,14 +219,14 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
       const Op* o = lo.second;
       for (int q = 0; q < o->count; ++q) {
         GemmDesc g = lo.first->gd[o->first + q];
-        g.tiles = gemm_tiles(o->cfg, g.M, g.N);
+        g.tiles = gemm_tiles(cfg, g.M, g.N);
         d.push_back(g);
         pre.push_back(pre.back() + g.tiles * g.batch * std::max(1, g.batch2));
       }
       fl += o->flops;
       by += o->bytes;
     }
-    LaunchRec r{LaunchRec::Gemm, f.opa, f.opb, f.fp32, f.cfg, 0, put(d), put_prefix(pre),
+    LaunchRec r{LaunchRec::Gemm, f.opa, f.opb, f.fp32, cfg, 0, put(d), put_prefix(pre),
                 (int)d.size(), pre.back(), f.fp32 ? kClassCgemm : kClassZgemm, fl, by};
     recs_.push_back(r);
     return;
@@ -327,7 +357,7 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
 }
 
 int Executor::build(std::vector<Lane*>& lanes, size_t arena_limit, int max_rounds,
-                    bool stop_on_finish) {
+                    bool stop_on_finish, int max_launches) {
   int rounds = 0;
   struct Head { uint64_t sig; Lane* l; Op* o; };
   std::vector<Head> heads;
@@ -358,6 +388,7 @@ int Executor::build(std::vector<Lane*>& lanes, size_t arena_limit, int max_round
       }
     ++rounds;
     if (fin && stop_on_finish) break;
+    if ((int)recs_.size() >= max_launches) break;
   }
   return rounds;
 }
@@ -502,5 +533,139 @@ void Executor::release() {
 }
 
 Executor::~Executor() { release(); }
+
+bool Executor::slot_ready() const {
+  const hipEvent_t e = done_[slot_];
+  return !e || hipEventQuery(e) == hipSuccess;
+}
+
+void Executor::wait_slot() {
+  if (done_[slot_]) XCHK(hipEventSynchronize(done_[slot_]));
+}
+
+// ------------------------------------------------------------------- pool --
+
+Pool::Pool(hipStream_t main, int n) {
+  n = std::max(1, n);
+  x_.resize(n);
+  for (int i = 0; i < n; ++i) {
+    X& x = x_[i];
+    if (i == 0) {
+      x.s = main;
+    } else {
+      XCHK(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
+      x.own = true;
+    }
+    x.exe.reset(new Executor(x.s));
+    XCHK(hipEventCreateWithFlags(&x.rel, hipEventDisableTiming));
+    XCHK(hipEventCreateWithFlags(&x.ev, hipEventDisableTiming));
+    x.waited.assign(n, 0);
+  }
+}
+
+Pool::~Pool() {
+  for (X& x : x_) {
+    if (x.s) (void)hipStreamSynchronize(x.s);
+    x.exe.reset();
+    if (x.rel) (void)hipEventDestroy(x.rel);
+    if (x.ev) (void)hipEventDestroy(x.ev);
+    if (x.own) (void)hipStreamDestroy(x.s);
+  }
+}
+
+int Pool::place(uint64_t cls) {
+  auto it = cls_x_.find(cls);
+  if (it != cls_x_.end()) return it->second;
+  int best = 0;
+  for (int i = 1; i < size(); ++i)
+    if (x_[i].load < x_[best].load) best = i;
+  return best;
+}
+
+void Pool::add(Lane* l, int xi) {
+  X& x = x_[xi];
+  for (int j = 0; j < size(); ++j) {
+    if (j == xi || x_[j].rel_count == x.waited[j]) continue;
+    XCHK(hipStreamWaitEvent(x.s, x_[j].rel, 0));
+    x.waited[j] = x_[j].rel_count;
+  }
+  x.lanes.push_back(l);
+  x.load += l->work;
+  cls_x_[l->cls] = xi;
+  cls_n_[l->cls]++;
+}
+
+bool Pool::busy() const {
+  for (const X& x : x_)
+    if (!x.lanes.empty()) return true;
+  return false;
+}
+
+void Pool::step(size_t arena_limit, int max_rounds, bool stop_on_finish, bool profile,
+                bool graphs, std::vector<KStat>& stats,
+                std::vector<std::pair<Lane*, int>>& done) {
+  bool issued = false;
+  int first_busy = -1, n_busy = 0;
+  for (const X& x : x_) n_busy += !x.lanes.empty();
+  const int cap = n_busy > 1 ? kPoolSegLaunches : (1 << 30);
+  for (int i = 0; i < size(); ++i) {
+    X& x = x_[i];
+    if (x.lanes.empty()) continue;
+    if (!x.exe->slot_ready()) {
+      if (first_busy < 0) first_busy = i;
+      continue;
+    }
+    x.exe->build(x.lanes, arena_limit, max_rounds, stop_on_finish, cap);
+    x.exe->flush(profile, graphs, stats);
+    issued = true;
+    bool fin = false;
+    for (size_t k = 0; k < x.lanes.size();) {
+      Lane* l = x.lanes[k];
+      if (l->done()) {
+        done.push_back({l, i});
+        x.load -= l->work;
+        if (--cls_n_[l->cls] == 0) {
+          cls_n_.erase(l->cls);
+          cls_x_.erase(l->cls);
+        }
+        x.lanes.erase(x.lanes.begin() + k);
+        fin = true;
+      } else {
+        ++k;
+      }
+    }
+    if (x.lanes.empty()) x.load = 0;
+    if (fin) {
+      XCHK(hipEventRecord(x.rel, x.s));
+      x.rel_count++;
+    }
+  }
+  if (!issued && first_busy >= 0) x_[first_busy].exe->wait_slot();
+}
+
+void Pool::fork() {
+  if (size() == 1) return;
+  XCHK(hipEventRecord(x_[0].ev, x_[0].s));
+  for (int i = 1; i < size(); ++i) XCHK(hipStreamWaitEvent(x_[i].s, x_[0].ev, 0));
+}
+
+void Pool::join() {
+  for (int i = 1; i < size(); ++i) {
+    XCHK(hipEventRecord(x_[i].ev, x_[i].s));
+    XCHK(hipStreamWaitEvent(x_[0].s, x_[i].ev, 0));
+  }
+}
+
+void Pool::sync_and_collect(std::vector<KStat>& stats) {
+  for (X& x : x_) x.exe->sync_and_collect(stats);
+}
+
+void Pool::sync() {
+  for (X& x : x_) XCHK(hipStreamSynchronize(x.s));
+}
+
+void Pool::release() {
+  for (X& x : x_) x.exe->release();
+}
 
 }  // namespace qtx

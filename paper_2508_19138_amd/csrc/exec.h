@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -49,6 +50,8 @@ struct Lane {
   int problem = -1;
   int e0 = 0, ec = 0;
   size_t ws_off = 0, ws_bytes = 0;
+  uint64_t cls = 0;          // shape class (lanes of one class run in lockstep)
+  double work = 0;           // flops of all its operations
   bool done() const { return next >= ops.size(); }
 };
 
@@ -94,14 +97,19 @@ class Executor {
   // Advance the lanes by merged rounds until every lane is done or the
   // arena limit is reached; returns the number of rounds emitted.  The
   // caller then calls flush() to upload and launch.
+  // A segment also ends after the round in which it reaches max_launches.
   int build(std::vector<Lane*>& lanes, size_t arena_limit, int max_rounds = 1 << 30,
-            bool stop_on_finish = false);
+            bool stop_on_finish = false, int max_launches = 1 << 30);
   // Upload and launch what build() produced (graph replay when the same
   // segment was seen before and graphs are enabled).
   void flush(bool profile, bool graphs, std::vector<KStat>& stats);
   void sync_and_collect(std::vector<KStat>& stats);
   bool empty() const { return recs_.empty(); }
   void release();
+  // The arena slot the next eager flush uses is free (no wait needed).
+  bool slot_ready() const;
+  void wait_slot();
+  hipStream_t stream() const { return s_; }
 
  private:
   template <class D>
@@ -130,6 +138,59 @@ class Executor {
   std::unordered_map<uint64_t, int> seen_;
   uint64_t tick_ = 0;
   hipEvent_t get_event();
+};
+
+// Executors on several streams advancing disjoint sets of lanes.  Lanes of
+// one shape class go to the same executor, where they run in lockstep and
+// share launches; different classes overlap on the device.  A lane whose
+// workspace region was used by a lane of another executor is ordered after
+// it through that executor's release event.
+constexpr int kPoolSegLaunches = 256;
+
+class Pool {
+ public:
+  Pool(hipStream_t main, int n_streams);   // stream 0 is `main` (not owned)
+  ~Pool();
+  int size() const { return (int)x_.size(); }
+  hipStream_t stream(int x) const { return x_[x].s; }
+  Executor& exe(int x) { return *x_[x].exe; }
+  // Executor for a new lane of class `cls` (lanes keep it in l->cls).
+  int place(uint64_t cls);
+  // Lane l (already built) joins executor x; x's stream first waits for
+  // the region releases recorded by the other executors.
+  void add(Lane* l, int x);
+  // Issue one segment on every executor that has lanes and a free arena
+  // slot (if none has, wait for one first).  Lanes that finished are
+  // appended to `done` with their executor; their work is queued, and
+  // their regions may be given to lanes added afterwards.  While several
+  // executors have lanes, segments are cut at kPoolSegLaunches launches:
+  // one host thread feeds every stream, and a long segment would hold it
+  // in the launch calls of one stream (whose hardware queue is full) while
+  // the other streams run dry.
+  void step(size_t arena_limit, int max_rounds, bool stop_on_finish, bool profile,
+            bool graphs, std::vector<KStat>& stats, std::vector<std::pair<Lane*, int>>& done);
+  bool busy() const;
+  void fork();        // every stream waits for the work queued on stream 0
+  void join();        // stream 0 waits for the work queued on the others
+  void sync_and_collect(std::vector<KStat>& stats);
+  void sync();
+  void release();     // graphs and arenas of every executor
+
+ private:
+  struct X {
+    std::unique_ptr<Executor> exe;
+    hipStream_t s = nullptr;
+    bool own = false;
+    std::vector<Lane*> lanes;
+    double load = 0;
+    hipEvent_t rel = nullptr;        // recorded after lanes finished
+    uint64_t rel_count = 0;
+    std::vector<uint64_t> waited;    // rel_count of each other executor seen
+    hipEvent_t ev = nullptr;         // fork/join
+  };
+  std::vector<X> x_;
+  std::map<uint64_t, int> cls_x_;    // class -> executor while it has lanes
+  std::map<uint64_t, int> cls_n_;
 };
 
 }  // namespace qtx

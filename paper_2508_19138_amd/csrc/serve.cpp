@@ -1,15 +1,15 @@
 // Request loop of the RGF library: continuous batching of independently
 // submitted problems (qtx_rgf_submit / qtx_rgf_poll).
 //
-// A host thread owns its own HIP stream, workspace and launch arena.  It
+// A host thread owns its own HIP streams, workspace and launch arenas.  It
 // admits queued problems in arrival order, energy chunk by chunk, whenever
-// workspace frees up, and advances every admitted lane in the same merged
-// launches (exec.cpp): problems that arrive while others run join the next
-// segment of launches and overlap with them.  A segment is cut as soon as a
-// lane finishes so that its workspace can be handed to the next problem; at
-// most two segments are in flight, the older one is waited on before more
-// work is queued.  A problem completes when all of its lanes' segments have
-// completed on the device.
+// workspace frees up, and advances every admitted lane in merged launches
+// (exec.cpp): lanes of one shape class share launches on one stream and
+// different classes run concurrently on the others, so problems that arrive
+// while others run join the next segment of launches and overlap with them.
+// A segment is cut as soon as a lane finishes so that its workspace can be
+// handed to the next problem.  A problem completes when the events recorded
+// after each of its lanes' last operations have completed.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -49,15 +49,16 @@ class Server {
   bool failed() const { return failed_; }
 
  private:
-  struct Seg {
-    hipEvent_t ev;
-    std::vector<Request*> lane_done;   // one entry per lane that finished in it
+  struct Fin {
+    hipEvent_t ev;          // recorded after the lane's last operation
+    Request* r;
   };
   void loop();
   void admit();
-  void finish_segment(Seg& s);
+  void retire(bool block);
   void complete(Request* r);
   void fail_all(int st);
+  hipEvent_t get_event();
 
   qtx_rgf_ctx* c_;
   std::thread th_;
@@ -72,7 +73,7 @@ class Server {
 
   // owned by the loop thread
   hipStream_t s_ = nullptr, s_read_ = nullptr;
-  std::unique_ptr<Executor> exe_;
+  std::unique_ptr<Pool> pool_;
   char* ws_ = nullptr;
   char* aux_ = nullptr;
   size_t ws_cap_ = 0, aux_cap_ = 0;
@@ -81,15 +82,17 @@ class Server {
   std::vector<std::unique_ptr<Request>> admitted_;
   std::vector<std::unique_ptr<Lane>> active_;
   std::unordered_map<Lane*, Request*> owner_;
-  std::deque<Seg> segs_;
+  std::vector<Fin> fin_;
   std::vector<hipEvent_t> ev_pool_;
   std::vector<KStat> stats_ = std::vector<KStat>(kNumClasses);
+  bool by_b_ = true;
 };
 
 namespace {
 constexpr size_t kAuxCap = 64u << 20;        // energies + status words
 constexpr int kRoundsPerSegment = 64;
 constexpr size_t kSegArena = 8u << 20;
+constexpr int kServeStreams = 4;
 
 #define SCHK(expr)                               \
   do {                                           \
@@ -101,7 +104,9 @@ Server::Server(qtx_rgf_ctx* c, size_t ws_budget) : c_(c) {
   SCHK(hipSetDevice(c->device));
   SCHK(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
   SCHK(hipStreamCreateWithFlags(&s_read_, hipStreamNonBlocking));
-  exe_.reset(new Executor(s_));
+  pool_.reset(new Pool(s_, kServeStreams));
+  const char* cp = std::getenv("QTX_SERVE_CLASS");
+  by_b_ = !(cp && std::string(cp) == "shape");
   ws_cap_ = ws_budget;
   if (hipMalloc((void**)&ws_, ws_cap_) != hipSuccess) {
     (void)hipGetLastError();
@@ -121,9 +126,9 @@ Server::~Server() {
   }
   cv_in_.notify_all();
   if (th_.joinable()) th_.join();
-  exe_.reset();
+  pool_.reset();
   for (auto e : ev_pool_) (void)hipEventDestroy(e);
-  for (auto& sg : segs_) (void)hipEventDestroy(sg.ev);
+  for (auto& f : fin_) (void)hipEventDestroy(f.ev);
   if (ws_) (void)hipFree(ws_);
   if (aux_) (void)hipFree(aux_);
   if (s_) (void)hipStreamDestroy(s_);
@@ -188,8 +193,10 @@ void Server::admit() {
       r->aux_len = len;
       r->dE = (double*)(aux_ + off);
       r->dinfo = (int*)(aux_ + off + eb);
-      if (!r->E.empty())
-        SCHK(hipMemcpyAsync(r->dE, r->E.data(), sizeof(double) * ne, hipMemcpyHostToDevice, s_));
+      if (!r->E.empty()) {
+        SCHK(hipMemcpyAsync(r->dE, r->E.data(), sizeof(double) * ne, hipMemcpyHostToDevice, s_read_));
+        SCHK(hipStreamSynchronize(s_read_));
+      }
     }
     while (r->next_e0 < ne) {
       const int ec = std::min(r->ec_max, ne - r->next_e0);
@@ -202,7 +209,14 @@ void Server::admit() {
       L->ws_off = off;
       L->ws_bytes = by;
       r->p.energies = r->E.empty() ? nullptr : r->E.data();
-      build_lane(*L, r->p, r->q, ws_ + off, r->next_e0, ec, r->dE, r->dinfo, c_->tuner, s_);
+      // requests arrive at any time, so lanes of one class are rarely in
+      // phase: classes are kept per block size and spread over the streams
+      const uint64_t cls = lane_class(r->q, r->p, by_b_);
+      const int xi = pool_->place(cls);
+      build_lane(*L, r->p, r->q, ws_ + off, r->next_e0, ec, r->dE, r->dinfo, c_->tuner,
+                 pool_->stream(xi));
+      L->cls = cls;                    // before add: the pool keys on it
+      pool_->add(L.get(), xi);
       owner_[L.get()] = r;
       active_.push_back(std::move(L));
       r->lanes_out++;
@@ -252,10 +266,31 @@ void Server::complete(Request* r) {
     }
 }
 
-void Server::finish_segment(Seg& sg) {
-  SCHK(hipEventSynchronize(sg.ev));
-  ev_pool_.push_back(sg.ev);
-  for (Request* r : sg.lane_done) {
+hipEvent_t Server::get_event() {
+  if (!ev_pool_.empty()) {
+    hipEvent_t e = ev_pool_.back();
+    ev_pool_.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  SCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return e;
+}
+
+// Retire finished lanes whose work has completed; with `block`, wait for
+// the oldest one first.
+void Server::retire(bool block) {
+  if (block && !fin_.empty()) SCHK(hipEventSynchronize(fin_.front().ev));
+  for (size_t i = 0; i < fin_.size();) {
+    const hipError_t q = hipEventQuery(fin_[i].ev);
+    if (q == hipErrorNotReady) {
+      ++i;
+      continue;
+    }
+    if (q != hipSuccess) throw Fail{QTX_ERR_HIP};
+    Request* r = fin_[i].r;
+    ev_pool_.push_back(fin_[i].ev);
+    fin_.erase(fin_.begin() + i);
     r->lanes_out--;
     if (r->lanes_out == 0 && r->next_e0 == r->p.n_energies) complete(r);
   }
@@ -286,11 +321,11 @@ void Server::fail_all(int st) {
 void Server::loop() {
   try {
     (void)hipSetDevice(c_->device);
-    std::vector<Lane*> lp;
+    std::vector<std::pair<Lane*, int>> fin;
     while (true) {
       {
         std::unique_lock<std::mutex> g(mu_);
-        if (waiting_.empty() && active_.empty() && segs_.empty() && incoming_.empty()) {
+        if (waiting_.empty() && active_.empty() && fin_.empty() && incoming_.empty()) {
           if (stop_) break;
           cv_in_.wait_for(g, std::chrono::milliseconds(5));
         }
@@ -300,44 +335,28 @@ void Server::loop() {
         }
       }
       admit();
-      if (active_.empty()) {
-        if (!segs_.empty()) {
-          finish_segment(segs_.front());
-          segs_.pop_front();
-        }
+      if (!pool_->busy()) {
+        retire(!fin_.empty());
         continue;
       }
-      lp.clear();
-      for (auto& l : active_) lp.push_back(l.get());
-      exe_->build(lp, kSegArena, kRoundsPerSegment, true);
-      exe_->flush(false, false, stats_);
-      Seg sg;
-      if (!ev_pool_.empty()) { sg.ev = ev_pool_.back(); ev_pool_.pop_back(); }
-      else SCHK(hipEventCreateWithFlags(&sg.ev, hipEventDisableTiming));
-      SCHK(hipEventRecord(sg.ev, s_));
-      for (size_t i = 0; i < active_.size();) {
-        if (active_[i]->done()) {
-          Lane* l = active_[i].get();
-          // its work is queued on the stream: the region may be reused by
-          // lanes whose work is queued later
-          wsr_->release(l->ws_off, l->ws_bytes);
-          sg.lane_done.push_back(owner_[l]);
-          owner_.erase(l);
-          active_.erase(active_.begin() + i);
-        } else {
-          ++i;
-        }
+      pool_->step(kSegArena, kRoundsPerSegment, true, false, false, stats_, fin);
+      for (auto& f : fin) {
+        Lane* l = f.first;
+        // its work is queued on its stream: the region may be reused by
+        // lanes added later (ordered through the pool's release events)
+        wsr_->release(l->ws_off, l->ws_bytes);
+        const hipEvent_t ev = get_event();
+        SCHK(hipEventRecord(ev, pool_->stream(f.second)));
+        fin_.push_back(Fin{ev, owner_[l]});
+        owner_.erase(l);
+        for (size_t i = 0; i < active_.size(); ++i)
+          if (active_[i].get() == l) {
+            active_.erase(active_.begin() + i);
+            break;
+          }
       }
-      segs_.push_back(std::move(sg));
-      while (segs_.size() > 2) {
-        finish_segment(segs_.front());
-        segs_.pop_front();
-      }
-      // report finished problems promptly when nothing else is queued
-      if (segs_.size() == 2 && !segs_.front().lane_done.empty()) {
-        finish_segment(segs_.front());
-        segs_.pop_front();
-      }
+      fin.clear();
+      retire(false);
     }
   } catch (const Fail& f) {
     fail_all(f.st);
