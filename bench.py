@@ -23,6 +23,10 @@ Other workloads (one JSON line each, not part of the default run):
   --mode serve   a Poisson stream of G-type requests of mixed shape through
                  the request loop (qtx_rgf_submit/poll) against a per-solve
                  loop on the same arrival trace: throughput, p50/p99 latency.
+  --mode gemm    the dominant kernel alone at the workload's shape (complex
+                 FP64 products D = A op(B) + C of 512 x 512 blocks, 128 per
+                 launch, each operand orientation), then three copies of a
+                 1 GiB buffer: the run that HBM byte counters are read on.
 """
 
 import argparse
@@ -39,17 +43,21 @@ sys.path.insert(0, ROOT)
 FP64_MFMA_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic factor of the dominant kernel from rocprofv3 PMC counters
-# (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by the copy-kernel
-# calibration); None until measured for the current kernel.
-MEASURED_TRAFFIC_BYTES_PER_LAUNCH = None
+# Measured HBM bytes of the dominant kernel per algorithmic byte: rocprofv3
+# --pmc FETCH_SIZE and WRITE_SIZE on `bench.py --mode gemm` (the product
+# kernel alone at this workload's shape: 512 x 512 blocks, 128 per launch,
+# D = A op(B) + C), each scaled by the same counter on a 1 GiB device copy
+# in the same run (FETCH_SIZE reads 0.500 of the copied bytes, WRITE_SIZE
+# 1.000): 806086 KiB x 2 read + 524288 KiB written per launch against
+# 2097152 KiB algorithmic.  None once the kernel changes.
+MEASURED_TRAFFIC_FACTOR = (806086.0 * 2.0 + 524288.0) / 2097152.0
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--mode", default="plain",
-                    choices=["plain", "mixed", "uneven", "serve"])
+                    choices=["plain", "mixed", "uneven", "serve", "gemm"])
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-blocks", type=int, default=32)
@@ -64,6 +72,8 @@ def parse():
                     help="after the run, copy a 1 GiB device buffer three times "
                          "(reference kernel for HBM byte counters)")
     ap.add_argument("--solves", type=int, default=512, help="uneven: solve count")
+    ap.add_argument("--skip-loop", action="store_true",
+                    help="uneven: time the merged batches only")
     ap.add_argument("--wave-gib", type=float, default=140.0,
                     help="uneven: device memory for the inputs/outputs of one wave")
     ap.add_argument("--requests", type=int, default=1000, help="serve: requests per rate")
@@ -128,7 +138,8 @@ def _gemm_roofline(ctx, cls, peak, label):
     return {"bound": "mfma", "kernel": label,
             "achieved": round(ach, 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(ach / peak, 4),
-            "traffic": MEASURED_TRAFFIC_BYTES_PER_LAUNCH if cls == "zgemm" else None,
+            "traffic": (round(MEASURED_TRAFFIC_FACTOR * st["bytes"] / st["launches"])
+                        if cls == "zgemm" and MEASURED_TRAFFIC_FACTOR else None),
             "launches": st["launches"], "avg_launch_ms": round(avg_ms, 4),
             "algorithmic_flops_per_launch": fl_launch,
             "algorithmic_bytes_per_launch": st["bytes"] / st["launches"]}
@@ -400,11 +411,12 @@ def run_uneven(args):
         torch.cuda.synchronize()
         t_merged += time.perf_counter() - t0
         assert st == Q.QTX_OK, st
-        t0 = time.perf_counter()
-        for k in probs:
-            ctx.solve_batch([k["prob"]])
-        torch.cuda.synchronize()
-        t_loop += time.perf_counter() - t0
+        if not args.skip_loop:
+            t0 = time.perf_counter()
+            for k in probs:
+                ctx.solve_batch([k["prob"]])
+            torch.cuda.synchronize()
+            t_loop += time.perf_counter() - t0
         tf_total += sum(flops[id(sp)] for sp in wave)
         print("wave %d/%d: %d solves, merged %.3f s, loop %.3f s (cumulative)"
               % (wi + 1, len(waves), len(wave), t_merged, t_loop), file=sys.stderr, flush=True)
@@ -425,9 +437,10 @@ def run_uneven(args):
         "merged": {"s": round(t_merged, 3), "energy_points_per_s": round(n_sol / t_merged, 3),
                    "tflops": round(tf_total / t_merged / 1e12, 3),
                    "pct_fp64_mfma_peak": round(100 * tf_total / t_merged / 1e12 / FP64_MFMA_PEAK_TFLOPS, 2)},
-        "per_solve_loop": {"s": round(t_loop, 3), "energy_points_per_s": round(n_sol / t_loop, 3),
-                           "tflops": round(tf_total / t_loop / 1e12, 3)},
-        "speedup_merged_vs_loop": round(t_loop / t_merged, 3),
+        "per_solve_loop": None if args.skip_loop else {
+            "s": round(t_loop, 3), "energy_points_per_s": round(n_sol / t_loop, 3),
+            "tflops": round(tf_total / t_loop / 1e12, 3)},
+        "speedup_merged_vs_loop": None if args.skip_loop else round(t_loop / t_merged, 3),
         "total_canonical_tflop": round(tf_total / 1e12, 3),
     }
     print(json.dumps(out), flush=True)
@@ -596,6 +609,41 @@ def run_serve(args):
 FP32_MFMA_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
 
 
+def run_gemm(args):
+    """Product kernel alone; HIP-event time per launch and algorithmic bytes."""
+    import torch
+    from paper_2508_19138_amd import qtx_rgf as Q
+    b, batch = args.block_size, args.energies
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(args.seed)
+    mk = lambda: torch.randn((batch, b, b), dtype=torch.complex128, device="cuda:0", generator=g)
+    A, B, C = mk(), mk(), mk()
+    D = torch.empty_like(C)
+    torch.cuda.synchronize()
+    rows = []
+    with Q.Context(0, profile=True) as ctx:
+        for opa, opb in (("N", "N"), ("N", "C"), ("C", "N"), ("C", "C")):
+            ctx.zgemm(opa, opb, b, b, b, 1 + 0j, A, b, b * b, B, b, b * b, 1 + 0j, C, b, b * b,
+                      D, b, b * b, batch)
+            ctx.reset_stats()
+            for _ in range(max(1, args.steps)):
+                ctx.zgemm(opa, opb, b, b, b, 1 + 0j, A, b, b * b, B, b, b * b, 1 + 0j, C, b,
+                          b * b, D, b, b * b, batch)
+            st = ctx.kernel_stats("zgemm")
+            ms = st["ms"] / st["launches"]
+            rows.append({"op": opa + opb, "avg_launch_ms": round(ms, 4),
+                         "tflops": round(st["flops"] / st["launches"] / (ms * 1e-3) / 1e12, 3),
+                         "algorithmic_bytes_per_launch": st["bytes"] / st["launches"]})
+    x = torch.empty(1 << 26, dtype=torch.complex128, device="cuda:0")   # 1 GiB
+    x.fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "gemm", "block_size": b, "batch": batch, "products": rows,
+                      "copy_calibration_bytes": 1 << 30}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -611,6 +659,8 @@ def main():
         run_plain(args, mixed=True)
     elif args.mode == "uneven":
         run_uneven(args)
+    elif args.mode == "gemm":
+        run_gemm(args)
     else:
         run_serve(args)
 
