@@ -177,9 +177,10 @@ qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
       L->ws_off = off;
       L->ws_bytes = pd.bytes;
       const qtx_rgf_problem& p = probs[pd.prob];
-      // a batch starts all its lanes together: lanes of every block size
-      // with the same operation structure share one stream in lockstep
-      const uint64_t cls = lane_class(plans[pd.prob], p, false);
+      // lanes of one class (operation structure and block size) start
+      // together and share one stream in lockstep; classes spread over the
+      // pool's streams and overlap one another's latency-bound inverses
+      const uint64_t cls = lane_class(plans[pd.prob], p, c->batch_size_key);
       const int xi = P.place(cls);
       build_lane(*L, p, plans[pd.prob], c->ws + off, pd.e0, pd.ec, d_E + e_off[pd.prob],
                  d_info + e_off[pd.prob], c->tuner, P.stream(xi));
@@ -275,6 +276,8 @@ qtx_status qtx_rgf_create(qtx_rgf_ctx** out, int device, uint64_t budget, void* 
     }
     c->own_stream = true;
   }
+  const char* bk = std::getenv("QTX_BATCH_CLASS");
+  if (bk) c->batch_size_key = std::atoi(bk);
   const char* ns = std::getenv("QTX_STREAMS");
   int n_streams = ns ? std::atoi(ns) : 4;
   n_streams = std::max(1, std::min(8, n_streams));

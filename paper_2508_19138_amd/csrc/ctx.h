@@ -29,6 +29,7 @@ struct qtx_rgf_ctx {
   std::unique_ptr<qtx::Pool> pool;       // executors on the context's streams
   qtx::Tuner tuner;
   bool graphs = true;
+  int batch_size_key = 2;                // lane classes of a batch (lane_class)
   bool busy = false;
   std::unique_ptr<qtx::Server> server;   // request loop (qtx_rgf_submit)
   // defined with the request loop, where Server is complete

@@ -663,15 +663,15 @@ void build_lane(Lane& lane, const qtx_rgf_problem& p, const Plan& q, char* ws,
       }
     }
   }
-  lane.cls = lane_class(q, p, true);
+  lane.cls = lane_class(q, p, 2);
   lane.work = 0;
   for (const Op& o : lane.ops) lane.work += o.flops;
 }
 
-uint64_t lane_class(const Plan& q, const qtx_rgf_problem& p, bool by_block_size) {
-  // everything that shapes the operation sequence except the block count
-  // (and, optionally, the block size)
-  uint64_t k = by_block_size ? (uint64_t)q.b : 0;
+uint64_t lane_class(const Plan& q, const qtx_rgf_problem& p, int size_key) {
+  // everything that shapes the operation sequence except the block count,
+  // and the block size (size_key 2), a block-size bucket (1) or neither (0)
+  uint64_t k = size_key == 2 ? (uint64_t)q.b : size_key == 1 ? (uint64_t)(q.b > 256) : 0;
   k = k * 2 + q.is_w;
   k = k * 2 + q.fp32;
   k = k * 2 + q.general_ul;

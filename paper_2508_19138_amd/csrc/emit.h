@@ -29,9 +29,10 @@ void build_lane(Lane& lane, const qtx_rgf_problem& p, const Plan& q, char* ws,
                 hipStream_t s);
 
 // Shape class of a problem's lanes: lanes of one class have the same
-// operation sequence up to its length (block count) and, without
-// `by_block_size`, up to the block size of its operands; lanes of one class
-// started together run in lockstep and share every launch.
-uint64_t lane_class(const Plan& q, const qtx_rgf_problem& p, bool by_block_size);
+// operation sequence up to its length (block count) and the block size of
+// its operands; size_key 2 also separates block sizes, 1 separates blocks
+// up to 256 from larger ones, 0 neither.  Lanes of one class started
+// together run in lockstep and share every launch.
+uint64_t lane_class(const Plan& q, const qtx_rgf_problem& p, int size_key);
 
 }  // namespace qtx

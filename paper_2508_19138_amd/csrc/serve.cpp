@@ -211,7 +211,7 @@ void Server::admit() {
       r->p.energies = r->E.empty() ? nullptr : r->E.data();
       // requests arrive at any time, so lanes of one class are rarely in
       // phase: classes are kept per block size and spread over the streams
-      const uint64_t cls = lane_class(r->q, r->p, by_b_);
+      const uint64_t cls = lane_class(r->q, r->p, by_b_ ? 2 : 0);
       const int xi = pool_->place(cls);
       build_lane(*L, r->p, r->q, ws_ + off, r->next_e0, ec, r->dE, r->dinfo, c_->tuner,
                  pool_->stream(xi));
