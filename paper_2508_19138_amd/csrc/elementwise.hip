@@ -28,13 +28,34 @@ void lincomb_kernel(FlatLaunch L) {
   const double2* S1 = a.src[1] ? (const double2*)a.src[1] + e * a.sSrc[1] : nullptr;
   const double2* S2 = a.src[2] ? (const double2*)a.src[2] + e * a.sSrc[2] : nullptr;
   const long long q1 = q0 + kLinChunk < nel ? q0 + kLinChunk : nel;
-  for (long long q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+  // each thread owns kLinChunk / 256 elements; all of a source's loads are
+  // issued together (out-of-range slots read element 0 and are dropped)
+  constexpr int kPer = kLinChunk / 256;
+  static_assert(kLinChunk % 256 == 0, "chunk");
+  double2 acc[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const long long q = q0 + threadIdx.x + (long long)k * 256;
     const int r = (int)(q / b), c = (int)(q % b);
-    double2 v = (r == c) ? make_double2(id.re, id.im) : make_double2(0.0, 0.0);
-    if (S0) v = cadd(v, cscale(co[0], S0[q]));
-    if (S1) v = cadd(v, cscale(co[1], S1[q]));
-    if (S2) v = cadd(v, cscale(co[2], S2[q]));
-    D[q] = v;
+    acc[k] = (q < q1 && r == c) ? make_double2(id.re, id.im) : make_double2(0.0, 0.0);
+  }
+  const double2* src[3] = {S0, S1, S2};
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (!src[t]) continue;                      // uniform
+    double2 v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const long long q = q0 + threadIdx.x + (long long)k * 256;
+      v[k] = src[t][q < q1 ? q : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) acc[k] = cadd(acc[k], cscale(co[t], v[k]));
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const long long q = q0 + threadIdx.x + (long long)k * 256;
+    if (q < q1) D[q] = acc[k];
   }
 }
 
@@ -58,23 +79,51 @@ void transcomb_kernel(FlatLaunch L) {
   const bool useZ = (t.z.re != 0.0 || t.z.im != 0.0) && Z;
   const bool useC = (t.a.re != 0.0 || t.a.im != 0.0) && C;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  constexpr int kRows = kTransTile / 8;
+  // loads are issued unconditionally (out-of-range slots read element 0 and
+  // are replaced or dropped) so that each thread's loads overlap
   if (useT) {
     // tile[i][j] = Z[c0 + i][r0 + j]
-    for (int i = ty; i < kTransTile; i += 8) {
-      const int zr = c0 + i, zcol = r0 + tx;
-      tile[i][tx] = (zr < b && zcol < b) ? Z[(long long)zr * b + zcol] : make_double2(0.0, 0.0);
+    double2 v[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int zr = c0 + ty + 8 * k, zcol = r0 + tx;
+      const bool ok = zr < b && zcol < b;
+      v[k] = Z[ok ? (long long)zr * b + zcol : 0];
+      if (!ok) v[k] = make_double2(0.0, 0.0);
     }
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) tile[ty + 8 * k][tx] = v[k];
     __syncthreads();
   }
-  for (int i = ty; i < kTransTile; i += 8) {
-    const int r = r0 + i, c = c0 + tx;
-    if (r >= b || c >= b) continue;
-    const long long q = (long long)r * b + c;
-    double2 v = make_double2(0.0, 0.0);
-    if (useC) v = cscale(t.a, C[q]);
-    if (useZ) v = cadd(v, cscale(t.z, Z[q]));
-    if (useT) v = cadd(v, cscale(t.g, cconj(tile[tx][i])));   // conj(Z[c][r])
-    D[q] = v;
+  double2 acc[kRows];
+  long long qs[kRows];
+  bool oks[kRows];
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    const int r = r0 + ty + 8 * k, c = c0 + tx;
+    oks[k] = r < b && c < b;
+    qs[k] = oks[k] ? (long long)r * b + c : 0;
+    acc[k] = make_double2(0.0, 0.0);
+  }
+  if (useC) {
+    double2 v[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) v[k] = C[qs[k]];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) acc[k] = cscale(t.a, v[k]);
+  }
+  if (useZ) {
+    double2 v[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) v[k] = Z[qs[k]];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) acc[k] = cadd(acc[k], cscale(t.z, v[k]));
+  }
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    if (useT) acc[k] = cadd(acc[k], cscale(t.g, cconj(tile[tx][ty + 8 * k])));   // conj(Z[c][r])
+    if (oks[k]) D[qs[k]] = acc[k];
   }
 }
 

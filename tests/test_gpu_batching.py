@@ -148,3 +148,23 @@ def test_one_energy_over_budget_is_nomem():
         with pytest.raises(Q.QtxError) as ei:
             ctx.solve_batch([s.problem()])
         assert ei.value.status == Q.QTX_ERR_NOMEM
+
+
+def test_stream_pool_is_bitwise_neutral(monkeypatch):
+    """The same mixed batch on one stream and on the default pool of
+    streams (lanes grouped by class, launches split differently) gives the
+    same bits."""
+    specs = _specs(14, 10, bs=(16, 40, 64, 96), ns=(2, 9))
+    solves = [Solve(s) for s in specs]
+    out = {}
+    for n in ("1", "4"):
+        monkeypatch.setenv("QTX_STREAMS", n)
+        with Q.Context(0) as ctx:
+            probs = [s.problem() for s in solves]
+            torch.cuda.synchronize()
+            assert ctx.solve_batch(probs) == Q.QTX_OK
+            out[n] = [s.results() for s in solves]
+    for s, a, b in zip(solves, out["1"], out["4"]):
+        for X, Y in zip(a, b):
+            for x, y in zip(X, Y):
+                assert np.array_equal(x, y), s.spec
