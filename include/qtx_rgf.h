@@ -45,7 +45,18 @@
  * problems of the batch are unaffected.  Outputs of a failing energy are
  * unspecified.  No C++ exception crosses this interface.
  *
- * Threading: a context may be used by one host thread at a time.
+ * Threading: a context may be used by one host thread at a time.  The
+ * request loop (qtx_rgf_submit) runs on a thread of its own with its own
+ * streams and workspace; solve_batch and the request loop of one context may
+ * run at the same time.
+ *
+ * Environment (read at qtx_rgf_create): QTX_STREAMS (1..8, default 4) sets
+ * the number of streams over which a batch's lane classes are spread;
+ * QTX_GRAPHS=0 disables graph capture of repeated launch segments;
+ * QTX_TUNE=0 disables the tile autotuner; QTX_TUNE_CACHE names its cache
+ * file; QTX_GEMM_CFG, QTX_BATCH_CLASS and QTX_SERVE_CLASS override the tile
+ * and the grouping of lanes into classes (for experiments).  Results do not
+ * depend on any of them.
  */
 #ifndef QTX_RGF_H
 #define QTX_RGF_H
@@ -101,7 +112,9 @@ typedef struct {
   const double* energies; /* host, [N_E] real energies (G-type; W ignores)   */
 
   /* G-type inputs.  H: energy independent, Hermitian; H.lower NULL means
-   * lower = upper^dagger.  S: energy independent overlap; S.diag NULL means
+   * lower = upper^dagger (the library may read either coupling block
+   * through the adjoint of the other, so a non-Hermitian H is not
+   * supported).  S: energy independent overlap; S.diag NULL means
    * S = I (then S.upper/S.lower must be NULL); S.upper/lower NULL = zero.
    * sigma_r: retarded self-energy (scattering + OBC), per energy; upper and
    * lower NULL = zero blocks.  sigma_l / sigma_g: Sigma^< / Sigma^>, per
