@@ -66,6 +66,11 @@ def parse():
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--cpu-energies", type=int, default=2,
                     help="energies in the CPU-oracle sample (0 = skip)")
+    ap.add_argument("--bt-sigma", action="store_true",
+                    help="plain/mixed: self-energies with block-tridiagonal parts (general "
+                         "path, F_BT flop model); use --energies 96 to fit HBM")
+    ap.add_argument("--per-b", action="store_true",
+                    help="uneven: also time the merged batch of each block size alone")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without per-launch HIP events")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -85,7 +90,16 @@ def parse():
     return ap.parse_args()
 
 
-def build_inputs(n, b, n_e, seed):
+def build_inputs(n, b, n_e, seed, bt_sigma=False):
+    """H on the host generator; self-energies expanded on the device.
+
+    Returns (problem dict, H triple, [(diag, upper, lower)] for Sigma^R,
+    Sigma^<, Sigma^>).  With bt_sigma the broadening gets an energy-independent
+    Hermitian block-tridiagonal part K (diagonal and coupling entries
+    CN(0, 0.005/b), drawn on the device from the seed):  Gamma -> Gamma + K,
+    Sigma^R = -i Gamma/2, Sigma^< = i f Gamma, Sigma^> = -i (1-f) Gamma, so
+    Sigma^> - Sigma^< = Sigma^R - Sigma^A still holds block by block.
+    """
     import torch
     from paper_2508_19138_amd import synth
     p = synth.g_problem(seed, n, b, n_e=n_e, expand=False)
@@ -95,7 +109,23 @@ def build_inputs(n, b, n_e, seed):
     sig = []
     for sc in p["sigma_scalars"]:
         s = torch.from_numpy(np.ascontiguousarray(sc)).to(dev)       # [n_e, n]
-        sig.append(s[:, :, None, None] * eye)                         # [n_e, n, b, b]
+        sig.append([s[:, :, None, None] * eye, None, None])           # [n_e, n, b, b]
+    if bt_sigma:
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(seed + 1)
+        X = _cn_dev(gen, (n, b, b), 0.005 / b)
+        Kd = 0.5 * (X + X.conj().transpose(1, 2))
+        del X
+        Ku = _cn_dev(gen, (n - 1, b, b), 0.005 / b)
+        E = p["energies"]
+        f = torch.from_numpy(synth.fermi(E)).to(dev)[:, None, None, None]
+        fb = torch.from_numpy(synth.one_minus_fermi(E)).to(dev)[:, None, None, None]
+        one = torch.ones_like(f)
+        for k, coef in ((0, -0.5j * one), (1, 1j * f), (2, -1j * fb)):
+            sig[k][0] += coef * Kd[None]
+            sig[k][1] = (coef * Ku[None]).contiguous()
+        sig[0][2] = (-0.5j * one * Ku.conj().transpose(1, 2)[None]).contiguous()
+        del Kd, Ku
     return p, H, sig
 
 
@@ -150,7 +180,7 @@ def run_plain(args, mixed=False):
     from paper_2508_19138_amd import qtx_rgf as Q
     n, b, n_e = args.n_blocks, args.block_size, args.energies
 
-    p, H, (sr, sl, sg) = build_inputs(n, b, n_e, args.seed)
+    p, H, (sr, sl, sg) = build_inputs(n, b, n_e, args.seed, args.bt_sigma)
     E = np.ascontiguousarray(p["energies"])
     mk = lambda: (torch.empty((n_e, n, b, b), dtype=torch.complex128, device="cuda:0"),
                   torch.empty((n_e, n - 1, b, b), dtype=torch.complex128, device="cuda:0"),
@@ -160,8 +190,8 @@ def run_plain(args, mixed=False):
 
     ctx = Q.Context(0, profile=not args.no_profile)
     prec = Q.QTX_MIXED if mixed else Q.QTX_FP64
-    prob = Q.make_g_problem(E, H, (sr, None, None), (sl, None, None),
-                            (sg, None, None), XR, XL, XG, precision=prec)
+    prob = Q.make_g_problem(E, H, tuple(sr), tuple(sl), tuple(sg), XR, XL, XG,
+                            precision=prec)
     for _ in range(args.warmup):
         ctx.solve_batch([prob])
         assert prob.status == 0, prob.status
@@ -176,7 +206,7 @@ def run_plain(args, mixed=False):
 
     ms_step = 1000.0 * dt / args.steps
     eps = n_e * args.steps / dt
-    flops_e = Q.flops_per_energy(Q.QTX_KIND_G, n, b, 2, False)
+    flops_e = Q.flops_per_energy(Q.QTX_KIND_G, n, b, 2, args.bt_sigma)
     tflops = flops_e * n_e * args.steps / dt / 1e12
     roof, kt = None, None
     if not args.no_profile:
@@ -193,7 +223,9 @@ def run_plain(args, mixed=False):
             kt["fp32_cgemm_tflops"] = _tf(ctx.kernel_stats("cgemm"))
     ctx.close()
     errors = None
-    if mixed:
+    if mixed and args.bt_sigma:
+        errors = "not computed for --bt-sigma (see the parity tests)"
+    elif mixed:
         with Q.Context(0, budget_bytes=8 << 30) as ctx64:
             errors = mixed_errors(ctx64, p, E, H, (sr, sl, sg), (XR, XL, XG), args)
     if args.copy_calibration:
@@ -206,7 +238,7 @@ def run_plain(args, mixed=False):
         del x, y
 
     cpu = None
-    if args.cpu_energies > 0 and not mixed:
+    if args.cpu_energies > 0 and not mixed and not args.bt_sigma:
         cpu = cpu_baseline(p, args.cpu_energies)
 
     out = {
@@ -216,9 +248,10 @@ def run_plain(args, mixed=False):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c64-mfma/f64" if mixed else "f64", "data": "synthetic",
         "config": {"workload": "%s batched RGF (G-type): complex128 block-tridiagonal, "
-                               "%d blocks of %dx%d, %d energies on [-2,2], block-diagonal Sigma, "
+                               "%d blocks of %dx%d, %d energies on [-2,2], %s Sigma, "
                                "outputs G^R/G^</G^> diag+upper+lower"
-                               % ("mixed-precision" if mixed else "plain FP64", n, b, b, n_e),
+                               % ("mixed-precision" if mixed else "plain FP64", n, b, b, n_e,
+                                  "block-tridiagonal" if args.bt_sigma else "block-diagonal"),
                    "n_blocks": n, "block_size": b, "n_energies": n_e, "seed": args.seed},
         "tflops": round(tflops, 3),
         "pct_fp64_mfma_peak": round(100.0 * tflops / FP64_MFMA_PEAK_TFLOPS, 2),
@@ -239,11 +272,11 @@ def _tf(st):
 
 
 def _rel_blocks(x, y):
-    """max over blocks of ||x - y||_F / ||y||_F (blocks on the last two axes)."""
+    """Per-block ||x - y||_F / ||y||_F (blocks on the last two axes), flat."""
     import torch
     d = torch.linalg.matrix_norm(x - y)
     r = torch.linalg.matrix_norm(y)
-    return float((d / torch.clamp(r, min=1e-300)).max())
+    return (d / torch.clamp(r, min=1e-300)).reshape(-1).cpu()
 
 
 def mixed_errors(ctx, p, E, H, sig, Xmix, args):
@@ -258,22 +291,24 @@ def mixed_errors(ctx, p, E, H, sig, Xmix, args):
     sr, sl, sg = sig
     names = ("G^R", "G^<", "G^>")
     parts = ("diag", "upper", "lower")
-    vs_fp64 = {}
+    per = {}
     ch = 8                                    # FP64 reference in energy chunks
     for e0 in range(0, n_e, ch):
         e1 = min(n_e, e0 + ch)
         X64 = tuple(tuple(torch.empty_like(t[e0:e1]) for t in T) for T in Xmix)
         Ec = np.ascontiguousarray(E[e0:e1])
-        prob = Q.make_g_problem(Ec, H, (sr[e0:e1], None, None), (sl[e0:e1], None, None),
-                                (sg[e0:e1], None, None), *X64)
+        prob = Q.make_g_problem(Ec, H, (sr[0][e0:e1], None, None), (sl[0][e0:e1], None, None),
+                                (sg[0][e0:e1], None, None), *X64)
         ctx.solve_batch([prob])
         torch.cuda.synchronize()
         for nm, A, B in zip(names, Xmix, X64):
             for pt, a, bb in zip(parts, A, B):
                 k = "%s %s" % (nm, pt)
-                vs_fp64[k] = max(vs_fp64.get(k, 0.0), _rel_blocks(a[e0:e1], bb))
+                per.setdefault(k, []).append(_rel_blocks(a[e0:e1], bb))
         del X64
-    vs_oracle = {}
+    vs_fp64 = {k: {"max": float(torch.cat(v).max()), "median": float(torch.cat(v).median())}
+               for k, v in per.items()}
+    per = {}
     idx = [0, n_e // 2]
     srs, sls, sgs = p["sigma_scalars"]
     z = np.zeros((n - 1, b, b), np.complex128)
@@ -284,9 +319,10 @@ def mixed_errors(ctx, p, E, H, sig, Xmix, args):
         for nm, ref, mix in zip(names, [XR] + list(XS), Xmix):
             for pt, r, m in zip(parts, ref, mix):
                 key = "%s %s" % (nm, pt)
-                err = _rel_blocks(m[e].cpu(), torch.from_numpy(np.asarray(r)))
-                vs_oracle[key] = max(vs_oracle.get(key, 0.0), err)
-    return {"metric": "max over blocks of ||X_mixed - X_ref||_F / ||X_ref||_F",
+                per.setdefault(key, []).append(_rel_blocks(m[e].cpu(), torch.from_numpy(np.asarray(r))))
+    vs_oracle = {k: {"max": float(torch.cat(v).max()), "median": float(torch.cat(v).median())}
+                 for k, v in per.items()}
+    return {"metric": "per-block ||X_mixed - X_ref||_F / ||X_ref||_F: max and median over blocks",
             "vs_fp64_library_all_energies": vs_fp64,
             "vs_cpu_oracle": vs_oracle, "oracle_energy_indices": idx}
 
@@ -372,12 +408,7 @@ def _uneven_problem(spec):
     return keep
 
 
-def run_uneven(args):
-    import torch
-    from paper_2508_19138_amd import qtx_rgf as Q
-    from paper_2508_19138_amd import synth
-    specs = synth.uneven_specs(args.seed, args.solves)
-    cap = int(args.wave_gib * 2 ** 30)
+def _waves(specs, cap):
     waves, cur, used = [], [], 0
     for sp in specs:
         by = _solve_bytes(sp)
@@ -388,10 +419,26 @@ def run_uneven(args):
         used += by
     if cur:
         waves.append(cur)
-    flops = {id(sp): Q.flops_per_energy(Q.QTX_KIND_G if sp["kind"] == "G" else Q.QTX_KIND_W,
-                                        sp["n"], sp["b"], 2, sp["kind"] == "W", False)
-             for sp in specs}
+    return waves
+
+
+def _spec_flops(Q, sp):
+    return Q.flops_per_energy(Q.QTX_KIND_G if sp["kind"] == "G" else Q.QTX_KIND_W,
+                              sp["n"], sp["b"], 2, sp["kind"] == "W", False)
+
+
+def run_uneven(args):
+    import torch
+    from paper_2508_19138_amd import qtx_rgf as Q
+    from paper_2508_19138_amd import synth
+    specs = synth.uneven_specs(args.seed, args.solves)
+    cap = int(args.wave_gib * 2 ** 30)
+    waves = _waves(specs, cap)
+    flops = {id(sp): _spec_flops(Q, sp) for sp in specs}
     ws = int(args.ws_gib * 2 ** 30)
+    # every wave is a different batch: no launch segment repeats, so graph
+    # capture (done on a segment's second sight) would only add its cost
+    os.environ["QTX_GRAPHS"] = "0"
     ctx = Q.Context(0, budget_bytes=ws, profile=False)
     # warm-up: tile tuning for every block size and both kinds, then the
     # first wave once (workspace growth) -- untimed
@@ -422,6 +469,26 @@ def run_uneven(args):
               % (wi + 1, len(waves), len(wave), t_merged, t_loop), file=sys.stderr, flush=True)
         del probs
         torch.cuda.empty_cache()
+    per_b = None
+    if args.per_b:
+        per_b = {}
+        for b in sorted({sp["b"] for sp in specs}):
+            sub = [sp for sp in specs if sp["b"] == b]
+            tb, fb = 0.0, 0.0
+            for wave in _waves(sub, cap):
+                probs = [_uneven_problem(sp) for sp in wave]
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                assert ctx.solve_batch([k["prob"] for k in probs]) == Q.QTX_OK
+                torch.cuda.synchronize()
+                tb += time.perf_counter() - t0
+                fb += sum(_spec_flops(Q, sp) for sp in wave)
+                del probs
+                torch.cuda.empty_cache()
+            per_b[str(b)] = {"solves": len(sub), "s": round(tb, 3),
+                             "tflops": round(fb / tb / 1e12, 3),
+                             "pct_fp64_mfma_peak": round(100 * fb / tb / 1e12 / FP64_MFMA_PEAK_TFLOPS, 2)}
+            print("b=%d alone: %s" % (b, per_b[str(b)]), file=sys.stderr, flush=True)
     ctx.close()
     n_sol = len(specs)
     out = {
@@ -442,6 +509,7 @@ def run_uneven(args):
             "tflops": round(tf_total / t_loop / 1e12, 3)},
         "speedup_merged_vs_loop": None if args.skip_loop else round(t_loop / t_merged, 3),
         "total_canonical_tflop": round(tf_total / 1e12, 3),
+        "merged_per_block_size": per_b,
     }
     print(json.dumps(out), flush=True)
 
@@ -577,7 +645,10 @@ def run_serve(args):
     for rate in rates:
         reqs = _serve_trace(args, rate)
         n_e_tot = sum(r["ne"] for r in reqs)
-        row = {"rate_per_s": rate, "requests": len(reqs), "energy_points": n_e_tot}
+        req_flops = np.mean([Q.flops_per_energy(Q.QTX_KIND_G, r["n"], r["b"], 2, False) * r["ne"]
+                             for r in reqs])
+        row = {"rate_per_s": rate, "requests": len(reqs), "energy_points": n_e_tot,
+               "mean_request_tflop": round(req_flops / 1e12, 4)}
         for name, ctx, served in (("served", ctx_s, True), ("per_solve_loop", ctx_l, False)):
             lat, span = _serve_run(ctx, inputs, reqs, cap, served)
             row[name] = _lat_summary(lat, n_e_tot, span)
@@ -585,9 +656,17 @@ def run_serve(args):
             torch.cuda.synchronize()
         row["throughput_ratio_served_vs_loop"] = round(
             row["served"]["energy_points_per_s"] / row["per_solve_loop"]["energy_points_per_s"], 3)
+        row["served"]["tflops"] = round(
+            row["requests"] * req_flops / row["served"]["span_s"] / 1e12, 3)
         results.append(row)
     ctx_s.close()
     ctx_l.close()
+    # offered load: arrival rate x mean request work over the largest served
+    # throughput measured (the loop's capacity)
+    cap_tf = max(r["served"]["tflops"] for r in results)
+    for r in results:
+        r["offered_load_vs_served_capacity"] = round(
+            r["rate_per_s"] * r["mean_request_tflop"] / cap_tf, 3)
     top = results[-1]
     out = {
         "mode": "serve",
