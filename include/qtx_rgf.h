@@ -52,6 +52,8 @@
  *
  * Environment (read at qtx_rgf_create): QTX_STREAMS (1..8, default 4) sets
  * the number of streams over which a batch's lane classes are spread;
+ * QTX_SPLIT (1..8, default 2) the number of streams a problem of 64 or more
+ * energies is split over;
  * QTX_GRAPHS=0 disables graph capture of repeated launch segments;
  * QTX_TUNE=0 disables the tile autotuner; QTX_TUNE_CACHE names its cache
  * file; QTX_GEMM_CFG, QTX_BATCH_CLASS and QTX_SERVE_CLASS override the tile

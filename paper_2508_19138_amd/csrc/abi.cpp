@@ -25,6 +25,7 @@ using namespace qtx;
 namespace {
 
 constexpr size_t kArenaLimit = 32u << 20;    // descriptor bytes per segment
+constexpr int kSplitMinEnergies = 64;          // energies before a problem is split
 
 size_t budget_now(qtx_rgf_ctx* c) {
   if (c->budget) return c->budget;
@@ -130,7 +131,7 @@ qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
 
   // lanes: the largest energy chunk whose workspace fits the budget
   const size_t budget = budget_now(c);
-  struct Pend { int prob, e0, ec; size_t bytes; };
+  struct Pend { int prob, e0, ec; size_t bytes; int part; };
   std::vector<Pend> pending;
   size_t total = 0, largest = 0;
   for (int i = 0; i < np; ++i) {
@@ -145,10 +146,16 @@ qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
       const int mid = (lo + hi + 1) / 2;
       if (lane_bytes(q, mid) <= budget) lo = mid; else hi = mid - 1;
     }
-    for (int e0 = 0; e0 < q.ne; e0 += lo) {
+    // a problem with many energies runs as `split` lanes on different
+    // streams (one class each): while one lane is in its latency-bound
+    // inverse, the other's products use the chip
+    const int split = q.ne >= kSplitMinEnergies ? c->split : 1;
+    if (split > 1) lo = std::min(lo, (q.ne + split - 1) / split);
+    int chunk = 0;
+    for (int e0 = 0; e0 < q.ne; e0 += lo, ++chunk) {
       const int ec = std::min(lo, q.ne - e0);
       const size_t by = lane_bytes(q, ec);
-      pending.push_back(Pend{i, e0, ec, by});
+      pending.push_back(Pend{i, e0, ec, by, split > 1 ? chunk % split : 0});
       total += (by + 255) & ~size_t(255);
       largest = std::max(largest, by);
     }
@@ -180,7 +187,7 @@ qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
       // lanes of one class (operation structure and block size) start
       // together and share one stream in lockstep; classes spread over the
       // pool's streams and overlap one another's latency-bound inverses
-      const uint64_t cls = lane_class(plans[pd.prob], p, c->batch_size_key);
+      const uint64_t cls = lane_class(plans[pd.prob], p, c->batch_size_key) * 8 + pd.part;
       const int xi = P.place(cls);
       build_lane(*L, p, plans[pd.prob], c->ws + off, pd.e0, pd.ec, d_E + e_off[pd.prob],
                  d_info + e_off[pd.prob], c->tuner, P.stream(xi));
@@ -276,6 +283,8 @@ qtx_status qtx_rgf_create(qtx_rgf_ctx** out, int device, uint64_t budget, void* 
     }
     c->own_stream = true;
   }
+  const char* sp = std::getenv("QTX_SPLIT");
+  if (sp) c->split = std::max(1, std::min(8, std::atoi(sp)));
   const char* bk = std::getenv("QTX_BATCH_CLASS");
   if (bk) c->batch_size_key = std::atoi(bk);
   const char* ns = std::getenv("QTX_STREAMS");
