@@ -52,7 +52,7 @@
  *
  * Environment (read at qtx_rgf_create): QTX_STREAMS (1..8, default 4) sets
  * the number of streams over which a batch's lane classes are spread;
- * QTX_SPLIT (1..8, default 2) the number of streams a problem of 64 or more
+ * QTX_SPLIT (1..8, default 1) the number of streams a problem of 64 or more
  * energies is split over;
  * QTX_GRAPHS=0 disables graph capture of repeated launch segments;
  * QTX_TUNE=0 disables the tile autotuner; QTX_TUNE_CACHE names its cache

@@ -146,9 +146,9 @@ qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
       const int mid = (lo + hi + 1) / 2;
       if (lane_bytes(q, mid) <= budget) lo = mid; else hi = mid - 1;
     }
-    // a problem with many energies runs as `split` lanes on different
-    // streams (one class each): while one lane is in its latency-bound
-    // inverse, the other's products use the chip
+    // optionally a problem with many energies runs as `split` lanes on
+    // different streams (one class each): while one lane is in its
+    // latency-bound inverse, the other's products use the chip
     const int split = q.ne >= kSplitMinEnergies ? c->split : 1;
     if (split > 1) lo = std::min(lo, (q.ne + split - 1) / split);
     int chunk = 0;

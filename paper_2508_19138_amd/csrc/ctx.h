@@ -30,7 +30,7 @@ struct qtx_rgf_ctx {
   qtx::Tuner tuner;
   bool graphs = true;
   int batch_size_key = 2;                // lane classes of a batch (lane_class)
-  int split = 2;                         // energy chunks per large problem, one stream each
+  int split = 1;                         // energy chunks per large problem, one stream each
   bool busy = false;
   std::unique_ptr<qtx::Server> server;   // request loop (qtx_rgf_submit)
   // defined with the request loop, where Server is complete
