@@ -191,3 +191,49 @@ def test_close_drains_outstanding_requests():
     ctx.close()                                   # without polling
     for j, r in zip(jobs, ref):
         _equal(j.results(), r, j.spec)
+
+
+def test_served_mixed_precision_and_wr_equal_alone():
+    """Requests with options: FP32 matrix-core products, and a W-type
+    request that also asks for W^R diagonal blocks."""
+    n, b, ne = 5, 48, 3
+    pg = synth.g_problem(41, n, b, n_e=ne)
+    pw = synth.w_problem(42, n, b, synth.energy_grid(ne))
+
+    def make():
+        E = np.ascontiguousarray(pg["energies"])
+        g_in = ((G.dev(pg["H"][0]), G.dev(pg["H"][1]), None),
+                (G.dev(pg["sigma_r"][0]), None, None),
+                (G.dev(pg["sigma_l"][0]), None, None),
+                (G.dev(pg["sigma_g"][0]), None, None))
+        g_out = (G.outputs(ne, n, b), G.outputs(ne, n, b), G.outputs(ne, n, b))
+        w_in = ((G.dev(pw["V"][0]), G.dev(pw["V"][1]), None),
+                tuple(G.dev(t) for t in pw["P_r"]),
+                (G.dev(pw["P_l"][0]), None, None),
+                (G.dev(pw["P_g"][0]), None, None))
+        w_out = (G.outputs(ne, n, b), G.outputs(ne, n, b), G.outputs(ne, n, b))
+        wr = G.empty((ne, n, b, b))
+        probs = [Q.make_g_problem(E, *g_in, *g_out, precision=Q.QTX_MIXED),
+                 Q.make_w_problem(*w_in, *w_out, WR_diag=wr)]
+        torch.cuda.synchronize()
+        return probs, (E, g_in, w_in), [g_out, w_out, wr]
+
+    def host(outs):
+        torch.cuda.synchronize()
+        g_out, w_out, wr = outs
+        return [G.host(T) for T in g_out + w_out] + [wr.cpu().numpy()]
+
+    with Q.Context(0) as ctx:
+        probs, keep, outs = make()
+        for pr in probs:
+            assert ctx.solve_batch([pr]) == Q.QTX_OK
+        ref = host(outs)
+        probs, keep2, outs2 = make()
+        tickets = [ctx.submit(pr) for pr in probs]
+        done = _drain(ctx, len(tickets))
+        assert all(done[t]["status"] == Q.QTX_OK for t in tickets)
+        got = host(outs2)
+    for a, r in zip(got[:-1], ref[:-1]):
+        for x, y in zip(a, r):
+            assert np.array_equal(x, y)
+    assert np.array_equal(got[-1], ref[-1])
