@@ -149,7 +149,12 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
     }
   }
 
-  int first_bad = 0;   // meaningful in thread 0 only
+  // Rows past b hold zeros and count as used, so they are never pivot
+  // candidates and their elimination leaves them zero: no bounds tests in
+  // the column loop.  Values read back from LDS are uniform across the
+  // workgroup, so the failure bookkeeping branches uniformly.
+  int first_bad = 0;
+  int pv_reg[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     if (c >= nbe) continue;      // uniform across the workgroup
@@ -160,7 +165,7 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int r = t + q * kInvThreads;
-      if (r < b && !u[q]) {
+      if (!u[q]) {
         const double v = a[q][c].x * a[q][c].x + a[q][c].y * a[q][c].y;
         if (!(v <= 1.7976931348623157e308)) bad = 1;     // NaN or Inf
         else key = fmax(key, pivot_key(v, r));
@@ -197,38 +202,44 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
     double2 prow[NB];
 #pragma unroll
     for (int cc = 0; cc < NB; ++cc) prow[cc] = rowS[par][bw][cc];
-    if (t == 0 && first_bad == 0) {
+    if (first_bad == 0) {
       const int code = code0 > 0 ? code0 : 1 + k0 + c;
       const double pv = prow[c].x * prow[c].x + prow[c].y * prow[c].y;
       if (anybad || bk < 0.0) first_bad = -code;
       else if (pv <= 0.0) first_bad = code;
     }
+    pv_reg[c] = p;
 #pragma unroll
-    for (int q = 0; q < R; ++q)
-      if (t + q * kInvThreads == p) {
-        u[q] = 1;
-        pc[q] = c;
-      }
-    if (t == 0) pivs[c] = p;
+    for (int q = 0; q < R; ++q) {
+      const bool isp = (t + q * kInvThreads == p);
+      u[q] |= isp;
+      pc[q] = isp ? c : pc[q];
+    }
     // ---- eliminate column k0 + c from every row ---------------------
+    // every row as a non-pivot row, then the pivot row is replaced by the
+    // scaled pivot row (its own update is discarded)
     const double2 inv = crecip_scaled(prow[c]);
     double2 ps[NB];
 #pragma unroll
     for (int cc = 0; cc < NB; ++cc) ps[cc] = (cc == c) ? inv : cmul(prow[cc], inv);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int r = t + q * kInvThreads;
-      if (r >= b) continue;
-      if (r == p) {
+      const double2 f = a[q][c];
+      a[q][c] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int cc = 0; cc < NB; ++cc) a[q][cc] = csub(a[q][cc], cmul(f, ps[cc]));
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (t + q * kInvThreads == p) {
 #pragma unroll
         for (int cc = 0; cc < NB; ++cc) a[q][cc] = ps[cc];
-      } else {
-        const double2 f = a[q][c];
-        a[q][c] = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc) a[q][cc] = csub(a[q][cc], cmul(f, ps[cc]));
       }
-    }
+  }
+  if (t == 0) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c < nbe) pivs[c] = pv_reg[c];
   }
   __syncthreads();                 // pivs[] complete before the write-back
 
