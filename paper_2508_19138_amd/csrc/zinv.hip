@@ -224,10 +224,15 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
     for (int cc = 0; cc < NB; ++cc) ps[cc] = (cc == c) ? inv : cmul(prow[cc], inv);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const double2 f = a[q][c];
-      a[q][c] = make_double2(0.0, 0.0);
+      // a -= f * ps as four fused multiply-adds per element; column c
+      // becomes -f * inv
+      const double fx = a[q][c].x, fy = a[q][c].y;
 #pragma unroll
-      for (int cc = 0; cc < NB; ++cc) a[q][cc] = csub(a[q][cc], cmul(f, ps[cc]));
+      for (int cc = 0; cc < NB; ++cc) {
+        const double2 z = (cc == c) ? make_double2(0.0, 0.0) : a[q][cc];
+        a[q][cc].x = fma(-fx, ps[cc].x, fma(fy, ps[cc].y, z.x));
+        a[q][cc].y = fma(-fx, ps[cc].y, fma(-fy, ps[cc].x, z.y));
+      }
     }
 #pragma unroll
     for (int q = 0; q < R; ++q)
