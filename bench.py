@@ -577,6 +577,7 @@ def _serve_run(ctx, inputs, reqs, cap, served):
     import torch
     R = len(reqs)
     lat = [None] * R
+    diag = {"client_wait": [], "lib_queue": [], "lib_latency": []}
     queue, nxt, used, done = [], 0, 0, 0
     live = {}
     t0 = time.perf_counter()
@@ -591,6 +592,7 @@ def _serve_run(ctx, inputs, reqs, cap, served):
                 i = queue.pop(0)
                 k = inputs.make(reqs[i])
                 torch.cuda.current_stream().synchronize()     # inputs written
+                diag["client_wait"].append(time.perf_counter() - t0 - reqs[i]["t"])
                 live[ctx.submit(k["prob"])] = (i, k)
                 used += _req_bytes(reqs[i])
             wait = 1 if (nxt < R or queue) else 50
@@ -600,6 +602,8 @@ def _serve_run(ctx, inputs, reqs, cap, served):
                 i, k = live.pop(c["ticket"])
                 assert c["status"] == 0, c
                 lat[i] = (tn - t0) - reqs[i]["t"]
+                diag["lib_queue"].append(c["queue_s"])
+                diag["lib_latency"].append(c["latency_s"])
                 used -= _req_bytes(reqs[i])
                 done += 1
                 last = tn
@@ -619,7 +623,7 @@ def _serve_run(ctx, inputs, reqs, cap, served):
             done += 1
             last = tn
             del k
-    return lat, last - t0
+    return lat, last - t0, diag
 
 
 def run_serve(args):
@@ -651,8 +655,15 @@ def run_serve(args):
         row = {"rate_per_s": rate, "requests": len(reqs), "energy_points": n_e_tot,
                "mean_request_tflop": round(req_flops / 1e12, 4)}
         for name, ctx, served in (("served", ctx_s, True), ("per_solve_loop", ctx_l, False)):
-            lat, span = _serve_run(ctx, inputs, reqs, cap, served)
+            lat, span, diag = _serve_run(ctx, inputs, reqs, cap, served)
             row[name] = _lat_summary(lat, n_e_tot, span)
+            if served:
+                # where the time goes: arrival -> submit in the client (input
+                # set-up, memory admission), submit -> first lane admitted and
+                # submit -> complete inside the library
+                row[name]["p50_p99_s"] = {
+                    k: [round(float(np.percentile(v, 50)), 4), round(float(np.percentile(v, 99)), 4)]
+                    for k, v in diag.items() if v}
             print("rate %g %s: %s" % (rate, name, row[name]), file=sys.stderr, flush=True)
             torch.cuda.synchronize()
         row["throughput_ratio_served_vs_loop"] = round(
