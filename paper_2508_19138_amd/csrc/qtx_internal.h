@@ -44,12 +44,14 @@ struct GemmDesc {
 };
 
 // Tile configurations of the product kernel (see zgemm.hip); the extra
-// value kGemmInvUpdate selects the general tile under its own kernel symbol
-// for the inverse's rank-kPanel updates (FP64, N x N only).
+// values kGemmInvUpdate / kGemmInvUpdateS select the general / the small
+// tile under their own kernel symbols for the inverse's update products
+// (FP64, N x N only).
 constexpr int kGemmConfigs = 3;
 constexpr int kGemmInvUpdate = 7;
-int gemm_tile_m(int cfg);   // kGemmInvUpdate maps to configuration 0
-int gemm_tile_n(int cfg);
+constexpr int kGemmInvUpdateS = 8;
+int gemm_tile_m(int cfg);   // kGemmInvUpdate maps to configuration 0,
+int gemm_tile_n(int cfg);   // kGemmInvUpdateS to configuration 2
 inline int gemm_tiles(int cfg, int M, int N) {
   return ((M + gemm_tile_m(cfg) - 1) / gemm_tile_m(cfg)) *
          ((N + gemm_tile_n(cfg) - 1) / gemm_tile_n(cfg));
