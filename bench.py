@@ -83,7 +83,7 @@ def parse():
                     help="uneven: device memory for the inputs/outputs of one wave")
     ap.add_argument("--requests", type=int, default=1000, help="serve: requests per rate")
     ap.add_argument("--rates", default="50,100,200,400", help="serve: arrivals per second")
-    ap.add_argument("--pool-gib", type=float, default=96.0,
+    ap.add_argument("--pool-gib", type=float, default=150.0,
                     help="serve: device memory for requests admitted by the client")
     ap.add_argument("--ws-gib", type=float, default=64.0,
                     help="uneven/serve: library workspace budget")
