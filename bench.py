@@ -79,6 +79,10 @@ def parse():
     ap.add_argument("--solves", type=int, default=512, help="uneven: solve count")
     ap.add_argument("--skip-loop", action="store_true",
                     help="uneven: time the merged batches only")
+    ap.add_argument("--repeat", type=int, default=1,
+                    help="uneven: solve each wave this many times and time the last "
+                         "(repeated batches replay captured graphs, as in a "
+                         "self-consistent loop that re-solves the same shapes)")
     ap.add_argument("--wave-gib", type=float, default=140.0,
                     help="uneven: device memory for the inputs/outputs of one wave")
     ap.add_argument("--requests", type=int, default=1000, help="serve: requests per rate")
@@ -437,9 +441,10 @@ def run_uneven(args):
     waves = _waves(specs, cap)
     flops = {id(sp): _spec_flops(Q, sp) for sp in specs}
     ws = int(args.ws_gib * 2 ** 30)
-    # every wave is a different batch: no launch segment repeats, so graph
-    # capture (done on a segment's second sight) would only add its cost
-    os.environ["QTX_GRAPHS"] = "0"
+    # without --repeat every wave is a different batch: no launch segment
+    # repeats, so graph capture (done on a segment's second sight) would only
+    # add its cost
+    os.environ["QTX_GRAPHS"] = "1" if args.repeat > 1 else "0"
     ctx = Q.Context(0, budget_bytes=ws, profile=False)
     # warm-up: tile tuning for every block size and both kinds, then the
     # first wave once (workspace growth) -- untimed
@@ -451,7 +456,10 @@ def run_uneven(args):
     for wi, wave in enumerate(waves):
         probs = [_uneven_problem(sp) for sp in wave]
         torch.cuda.synchronize()
-        if wi == 0:
+        if wi == 0 and args.repeat == 1:
+            ctx.solve_batch([k["prob"] for k in probs])
+            torch.cuda.synchronize()
+        for _ in range(args.repeat - 1):          # untimed: first sight, capture
             ctx.solve_batch([k["prob"] for k in probs])
             torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -501,7 +509,8 @@ def run_uneven(args):
                                "RGF solves, b from {64,128,256,384,512,768}, n from 8..128, "
                                "half G-type half W-type (W with W^< W^> outputs), merged "
                                "batches in %d memory waves" % (n_sol, len(waves)),
-                   "solves": n_sol, "waves": len(waves), "seed": args.seed},
+                   "solves": n_sol, "waves": len(waves), "seed": args.seed,
+                   "timed_solve_of_each_wave": args.repeat},
         "merged": {"s": round(t_merged, 3), "energy_points_per_s": round(n_sol / t_merged, 3),
                    "tflops": round(tf_total / t_merged / 1e12, 3),
                    "pct_fp64_mfma_peak": round(100 * tf_total / t_merged / 1e12 / FP64_MFMA_PEAK_TFLOPS, 2)},
