@@ -245,22 +245,10 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
     int maxb = 0;
     for (auto& v : all) maxb = std::max(maxb, v.b);
     const int R = (maxb + kInvThreads - 1) / kInvThreads;
-    // update products take the small tile when the general one would not
-    // cover the chip twice (few or small matrices); results do not depend
-    // on the tile
-    auto ucfg = [&](long long tiles0) {
-      return tiles0 < 2 * 256 ? kGemmInvUpdateS : kGemmInvUpdate;
-    };
+
     bool first = true;
     for (int K0 = 0; K0 < maxb; K0 += kSuper) {
       for (int k0 = K0; k0 < std::min(K0 + kSuper, maxb); k0 += kPanel) {
-        long long sub_tiles0 = 0;
-        for (const InvDesc& v : all) {
-          const int hi = std::min(v.b, K0 + kSuper);
-          if (v.b > k0 && hi - K0 > std::min(kPanel, v.b - k0))
-            sub_tiles0 += (long long)gemm_tiles(0, v.b, hi - K0) * v.batch;
-        }
-        const int scfg = ucfg(sub_tiles0);
         std::vector<InvDesc> d;
         std::vector<int> pre(1, 0);
         std::vector<GemmDesc> gd;
@@ -283,7 +271,7 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
             g.alpha = zc{1.0, 0.0};
             g.beta = zc{1.0, 0.0};
             g.batch = v.batch; g.batch2 = 1;
-            g.tiles = gemm_tiles(scfg, g.M, g.N);
+            g.tiles = gemm_tiles(kGemmInvUpdate, g.M, g.N);
             gd.push_back(g);
             gpre.push_back(gpre.back() + g.tiles * g.batch);
             gby += 16.0 * 2.0 * g.M * (double)g.N * g.batch;
@@ -293,14 +281,10 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
                                   (int)d.size(), pre.back(), kClassInv, (first ? fl : 0.0), by});
         first = false;
         if (!gd.empty())
-          recs_.push_back(LaunchRec{LaunchRec::Gemm, 'N', 'N', false, scfg, k0, put(gd),
+          recs_.push_back(LaunchRec{LaunchRec::Gemm, 'N', 'N', false, kGemmInvUpdate, k0, put(gd),
                                     put_prefix(gpre), (int)gd.size(), gpre.back(), kClassInv, 0.0, gby});
       }
       // gather + rank-kSuper update for matrices larger than one super-panel
-      long long big_tiles0 = 0;
-      for (const InvDesc& v : all)
-        if (v.b > K0 && v.b > kSuper) big_tiles0 += (long long)gemm_tiles(0, v.b, v.b) * v.batch;
-      const int bcfg = ucfg(big_tiles0);
       std::vector<InvDesc> d;
       std::vector<int> pre(1, 0);
       std::vector<GemmDesc> gd;
@@ -320,7 +304,7 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
         g.alpha = zc{1.0, 0.0};
         g.beta = zc{1.0, 0.0};
         g.batch = v.batch; g.batch2 = 1;
-        g.tiles = gemm_tiles(bcfg, g.M, g.N);
+        g.tiles = gemm_tiles(kGemmInvUpdate, g.M, g.N);
         gd.push_back(g);
         gpre.push_back(gpre.back() + g.tiles * g.batch);
         gby += 16.0 * 2.0 * g.M * (double)g.N * g.batch;
@@ -328,7 +312,7 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
       if (!d.empty()) {
         recs_.push_back(LaunchRec{LaunchRec::Gather, 'N', 'N', false, 0, K0, put(d), put_prefix(pre),
                                   (int)d.size(), pre.back(), kClassInv, 0.0, by});
-        recs_.push_back(LaunchRec{LaunchRec::Gemm, 'N', 'N', false, bcfg, K0, put(gd),
+        recs_.push_back(LaunchRec{LaunchRec::Gemm, 'N', 'N', false, kGemmInvUpdate, K0, put(gd),
                                   put_prefix(gpre), (int)gd.size(), gpre.back(), kClassInv, 0.0, gby});
       }
     }

@@ -44,14 +44,13 @@ struct GemmDesc {
 };
 
 // Tile configurations of the product kernel (see zgemm.hip); the extra
-// values kGemmInvUpdate / kGemmInvUpdateS select the general / the small
-// tile under their own kernel symbols for the inverse's update products
-// (FP64, N x N only).
+// value kGemmInvUpdate selects the small tile under its own kernel symbol
+// for the inverse's update products (FP64, N x N only; measured faster than
+// the larger tiles for these thin or short products at any batch size).
 constexpr int kGemmConfigs = 3;
 constexpr int kGemmInvUpdate = 7;
-constexpr int kGemmInvUpdateS = 8;
-int gemm_tile_m(int cfg);   // kGemmInvUpdate maps to configuration 0,
-int gemm_tile_n(int cfg);   // kGemmInvUpdateS to configuration 2
+int gemm_tile_m(int cfg);   // kGemmInvUpdate maps to configuration 2
+int gemm_tile_n(int cfg);
 inline int gemm_tiles(int cfg, int M, int N) {
   return ((M + gemm_tile_m(cfg) - 1) / gemm_tile_m(cfg)) *
          ((N + gemm_tile_n(cfg) - 1) / gemm_tile_n(cfg));

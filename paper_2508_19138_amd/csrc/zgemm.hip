@@ -283,22 +283,17 @@ hipError_t launch_prec(int cfg, char opa, char opb, const FlatLaunch& l, hipStre
 }  // namespace
 
 int gemm_tile_m(int cfg) {
-  return cfg == 1 ? Cfg1::BM : (cfg == 2 || cfg == kGemmInvUpdateS) ? Cfg2::BM : Cfg0::BM;
+  return cfg == 1 ? Cfg1::BM : (cfg == 2 || cfg == kGemmInvUpdate) ? Cfg2::BM : Cfg0::BM;
 }
 int gemm_tile_n(int cfg) {
-  return cfg == 1 ? Cfg1::BN : (cfg == 2 || cfg == kGemmInvUpdateS) ? Cfg2::BN : Cfg0::BN;
+  return cfg == 1 ? Cfg1::BN : (cfg == 2 || cfg == kGemmInvUpdate) ? Cfg2::BN : Cfg0::BN;
 }
-// the inverse's update products use the general tile
+// the inverse's update products use the small tile
 
 hipError_t launch_gemm(int cfg, bool fp32, char opa, char opb, const FlatLaunch& l,
                        hipStream_t s) {
   if (l.total <= 0 || l.nd <= 0) return hipSuccess;
   if (cfg == kGemmInvUpdate) {
-    hipLaunchKernelGGL((zgemm_kernel<MathF64, Cfg0, 0, 0, 1>), dim3(l.total), dim3(Cfg0::kThreads),
-                       0, s, l);
-    return hipGetLastError();
-  }
-  if (cfg == kGemmInvUpdateS) {
     hipLaunchKernelGGL((zgemm_kernel<MathF64, Cfg2, 0, 0, 1>), dim3(l.total), dim3(Cfg2::kThreads),
                        0, s, l);
     return hipGetLastError();
