@@ -63,6 +63,7 @@ struct Cfg {
 typedef Cfg<64, 64, 16, 2, 2> Cfg0;     // general
 typedef Cfg<128, 64, 8, 2, 2> Cfg1;    // large blocks: 64 x 32 per wave
 typedef Cfg<32, 32, 16, 2, 2> Cfg2;     // small blocks
+typedef Cfg2 CfgU;                      // the inverse's update products
 
 __device__ __forceinline__ int xcd_remap(int w, int G) {
   constexpr int kXcd = 8;
@@ -283,10 +284,10 @@ hipError_t launch_prec(int cfg, char opa, char opb, const FlatLaunch& l, hipStre
 }  // namespace
 
 int gemm_tile_m(int cfg) {
-  return cfg == 1 ? Cfg1::BM : (cfg == 2 || cfg == kGemmInvUpdate) ? Cfg2::BM : Cfg0::BM;
+  return cfg == kGemmInvUpdate ? CfgU::BM : cfg == 1 ? Cfg1::BM : cfg == 2 ? Cfg2::BM : Cfg0::BM;
 }
 int gemm_tile_n(int cfg) {
-  return cfg == 1 ? Cfg1::BN : (cfg == 2 || cfg == kGemmInvUpdate) ? Cfg2::BN : Cfg0::BN;
+  return cfg == kGemmInvUpdate ? CfgU::BN : cfg == 1 ? Cfg1::BN : cfg == 2 ? Cfg2::BN : Cfg0::BN;
 }
 // the inverse's update products use the small tile
 
@@ -294,7 +295,7 @@ hipError_t launch_gemm(int cfg, bool fp32, char opa, char opb, const FlatLaunch&
                        hipStream_t s) {
   if (l.total <= 0 || l.nd <= 0) return hipSuccess;
   if (cfg == kGemmInvUpdate) {
-    hipLaunchKernelGGL((zgemm_kernel<MathF64, Cfg2, 0, 0, 1>), dim3(l.total), dim3(Cfg2::kThreads),
+    hipLaunchKernelGGL((zgemm_kernel<MathF64, CfgU, 0, 0, 1>), dim3(l.total), dim3(CfgU::kThreads),
                        0, s, l);
     return hipGetLastError();
   }

@@ -10,7 +10,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libqtx_rgf.so")
+# QTX_RGF_LIB selects another build of the library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("QTX_RGF_LIB") or os.path.join(_HERE, "libqtx_rgf.so")
 
 QTX_OK = 0
 QTX_ERR_INVALID_ARG = 1
