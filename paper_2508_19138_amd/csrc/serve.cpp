@@ -46,7 +46,6 @@ class Server {
   ~Server();
   qtx_status submit(const qtx_rgf_problem& p, uint64_t* ticket);
   qtx_status poll(qtx_rgf_completion* out, int cap, int* n, int* pending, int wait_ms);
-  bool failed() const { return failed_; }
 
  private:
   struct Fin {
@@ -58,6 +57,7 @@ class Server {
   void retire(bool block);
   void complete(Request* r);
   void fail_all(int st);
+  void free_resources();
   hipEvent_t get_event();
 
   qtx_rgf_ctx* c_;
@@ -88,35 +88,55 @@ class Server {
   bool by_b_ = true;
 };
 
+#define SCHK(expr)                                     \
+  do {                                                 \
+    if ((expr) != hipSuccess) throw Fail{QTX_ERR_HIP}; \
+  } while (0)
+
 namespace {
 constexpr size_t kAuxCap = 64u << 20;        // energies + status words
 constexpr int kRoundsPerSegment = 64;
 constexpr size_t kSegArena = 8u << 20;
 constexpr int kServeStreams = 4;
-
-#define SCHK(expr)                               \
-  do {                                           \
-    if ((expr) != hipSuccess) throw Fail{QTX_ERR_HIP}; \
-  } while (0)
 }  // namespace
 
 Server::Server(qtx_rgf_ctx* c, size_t ws_budget) : c_(c) {
-  SCHK(hipSetDevice(c->device));
-  SCHK(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
-  SCHK(hipStreamCreateWithFlags(&s_read_, hipStreamNonBlocking));
-  pool_.reset(new Pool(s_, kServeStreams));
-  const char* cp = std::getenv("QTX_SERVE_CLASS");
-  by_b_ = !(cp && std::string(cp) == "shape");
-  ws_cap_ = ws_budget;
-  if (hipMalloc((void**)&ws_, ws_cap_) != hipSuccess) {
-    (void)hipGetLastError();
-    throw Fail{QTX_ERR_NOMEM};
+  try {
+    SCHK(hipSetDevice(c->device));
+    SCHK(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+    SCHK(hipStreamCreateWithFlags(&s_read_, hipStreamNonBlocking));
+    pool_.reset(new Pool(s_, kServeStreams));
+    const char* cp = std::getenv("QTX_SERVE_CLASS");
+    by_b_ = !(cp && std::string(cp) == "shape");
+    ws_cap_ = ws_budget;
+    if (hipMalloc((void**)&ws_, ws_cap_) != hipSuccess) {
+      (void)hipGetLastError();
+      ws_ = nullptr;
+      throw Fail{QTX_ERR_NOMEM};
+    }
+    aux_cap_ = kAuxCap;
+    SCHK(hipMalloc((void**)&aux_, aux_cap_));
+    wsr_.reset(new Regions(ws_cap_));
+    auxr_.reset(new Regions(aux_cap_));
+    th_ = std::thread([this] { loop(); });
+  } catch (...) {
+    free_resources();              // the destructor does not run for a failed constructor
+    throw;
   }
-  aux_cap_ = kAuxCap;
-  SCHK(hipMalloc((void**)&aux_, aux_cap_));
-  wsr_.reset(new Regions(ws_cap_));
-  auxr_.reset(new Regions(aux_cap_));
-  th_ = std::thread([this] { loop(); });
+}
+
+void Server::free_resources() {
+  pool_.reset();
+  for (auto e : ev_pool_) (void)hipEventDestroy(e);
+  ev_pool_.clear();
+  for (auto& f : fin_) (void)hipEventDestroy(f.ev);
+  fin_.clear();
+  if (ws_) (void)hipFree(ws_);
+  if (aux_) (void)hipFree(aux_);
+  if (s_) (void)hipStreamDestroy(s_);
+  if (s_read_) (void)hipStreamDestroy(s_read_);
+  ws_ = aux_ = nullptr;
+  s_ = s_read_ = nullptr;
 }
 
 Server::~Server() {
@@ -126,13 +146,7 @@ Server::~Server() {
   }
   cv_in_.notify_all();
   if (th_.joinable()) th_.join();
-  pool_.reset();
-  for (auto e : ev_pool_) (void)hipEventDestroy(e);
-  for (auto& f : fin_) (void)hipEventDestroy(f.ev);
-  if (ws_) (void)hipFree(ws_);
-  if (aux_) (void)hipFree(aux_);
-  if (s_) (void)hipStreamDestroy(s_);
-  if (s_read_) (void)hipStreamDestroy(s_read_);
+  free_resources();
 }
 
 qtx_status Server::submit(const qtx_rgf_problem& p, uint64_t* ticket) {
