@@ -549,30 +549,38 @@ void Executor::wait_slot() {
 Pool::Pool(hipStream_t main, int n) {
   n = std::max(1, n);
   x_.resize(n);
-  for (int i = 0; i < n; ++i) {
-    X& x = x_[i];
-    if (i == 0) {
-      x.s = main;
-    } else {
-      XCHK(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
-      x.own = true;
+  try {
+    for (int i = 0; i < n; ++i) {
+      X& x = x_[i];
+      if (i == 0) {
+        x.s = main;
+      } else {
+        XCHK(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
+        x.own = true;
+      }
+      x.exe.reset(new Executor(x.s));
+      XCHK(hipEventCreateWithFlags(&x.rel, hipEventDisableTiming));
+      XCHK(hipEventCreateWithFlags(&x.ev, hipEventDisableTiming));
+      x.waited.assign(n, 0);
     }
-    x.exe.reset(new Executor(x.s));
-    XCHK(hipEventCreateWithFlags(&x.rel, hipEventDisableTiming));
-    XCHK(hipEventCreateWithFlags(&x.ev, hipEventDisableTiming));
-    x.waited.assign(n, 0);
+  } catch (...) {
+    destroy();                     // the destructor does not run for a failed constructor
+    throw;
   }
 }
 
-Pool::~Pool() {
+void Pool::destroy() {
   for (X& x : x_) {
     if (x.s) (void)hipStreamSynchronize(x.s);
     x.exe.reset();
     if (x.rel) (void)hipEventDestroy(x.rel);
     if (x.ev) (void)hipEventDestroy(x.ev);
-    if (x.own) (void)hipStreamDestroy(x.s);
+    if (x.own && x.s) (void)hipStreamDestroy(x.s);
+    x = X();
   }
 }
+
+Pool::~Pool() { destroy(); }
 
 int Pool::place(uint64_t cls) {
   auto it = cls_x_.find(cls);

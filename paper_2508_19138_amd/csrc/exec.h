@@ -177,6 +177,7 @@ class Pool {
   void release();     // graphs and arenas of every executor
 
  private:
+  void destroy();
   struct X {
     std::unique_ptr<Executor> exe;
     hipStream_t s = nullptr;
