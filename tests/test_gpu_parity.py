@@ -105,7 +105,7 @@ def _adversarial(b, kind, rng):
     raise ValueError(kind)
 
 
-@pytest.mark.parametrize("b", [1, 5, 16, 17, 32, 64, 100, 257, 512, 768])
+@pytest.mark.parametrize("b", [1, 5, 16, 17, 32, 64, 100, 257, 512, 768, 1000, 1024])
 @pytest.mark.parametrize("kind", ["random", "zero_lead", "perm_identity", "graded"])
 def test_zinv_matches_numpy(ctx, b, kind):
     gh = _gh()
@@ -160,7 +160,7 @@ def test_config1_plain_fp64(ctx):
     assert worst < TOL, worst
 
 
-@pytest.mark.parametrize("n,b", [(1, 24), (2, 17), (5, 40), (3, 100), (4, 130)])
+@pytest.mark.parametrize("n,b", [(1, 24), (2, 17), (5, 40), (3, 100), (4, 130), (6, 1)])
 def test_ragged_shapes_bt_sigma(ctx, n, b):
     """Block sizes off the tile grid and self-energies with off-diagonal
     blocks (the y_i / Y_i terms)."""
@@ -359,3 +359,22 @@ def test_mixed_precision_error_vs_fp64_oracle(ctx):
     print("mixed-precision max block rel err:", worst)
     assert max(worst.values()) < 1e-3
     assert max(worst.values()) > 1e-9          # the FP32 path really ran
+
+
+def test_maximum_block_size_solve(ctx):
+    """The largest supported block size (1024, four rows per thread in the
+    panel kernel), G-type with off-diagonal self-energy blocks."""
+    gh = _gh()
+    n, b = 2, 1024
+    p = synth.g_problem(91, n, b, n_e=1, bt_sigma=True)
+    prob, XR, XL, XG = gh.solve_g(ctx, p, h_lower=False)
+    assert prob.status == 0
+    OR, (OL, OG) = _oracle_g(p, 0)
+    assert triple_err(_sel(XR, 0), OR) < TOL
+    assert triple_err(_sel(XL, 0), OL) < TOL
+    assert triple_err(_sel(XG, 0), OG) < TOL
+
+
+def test_empty_batch(ctx):
+    assert ctx.solve_batch([]) == Q.QTX_OK
+
