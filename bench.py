@@ -616,6 +616,8 @@ def _serve_run(ctx, inputs, reqs, cap, served):
                 used -= _req_bytes(reqs[i])
                 done += 1
                 last = tn
+                if done % 1000 == 0:
+                    print("  served %d/%d" % (done, R), file=sys.stderr, flush=True)
         else:
             if not queue:
                 dt = reqs[nxt]["t"] - (time.perf_counter() - t0)
@@ -632,6 +634,8 @@ def _serve_run(ctx, inputs, reqs, cap, served):
             done += 1
             last = tn
             del k
+            if done % 1000 == 0:
+                print("  per-solve loop %d/%d" % (done, R), file=sys.stderr, flush=True)
     return lat, last - t0, diag
 
 
