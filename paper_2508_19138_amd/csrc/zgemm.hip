@@ -207,6 +207,25 @@ void zgemm_kernel(FlatLaunch L) {
       accI[i][j] = Acc{0, 0, 0, 0};
     }
 
+  // the inverse's update products (K = 16 or 64) read C before the k loop,
+  // so that its latency overlaps the operand loads and the products
+  constexpr bool kPreC = (TAG == 1);
+  double2 cpre[kPreC ? T::kTM : 1][kPreC ? T::kTN : 1][4];
+  if (kPreC) {
+    const double2* __restrict__ Cp = g.C ? (const double2*)g.C + e * g.sC + i2 * g.tC : nullptr;
+    const int lr = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < T::kTM; ++i)
+#pragma unroll
+      for (int j = 0; j < T::kTN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gm = m0 + wm * T::kWM + i * 16 + P::row(r, lq);
+          const int gn = n0 + wn * T::kWN + j * 16 + lr;
+          cpre[i][j][r] = (Cp && gm < M && gn < N) ? Cp[(long long)gm * g.ldc + gn]
+                                                   : make_double2(0.0, 0.0);
+        }
+  }
   const int nk = (K + BK - 1) / BK;
   load_tiles(0);
   store_tiles(0);
@@ -255,7 +274,7 @@ void zgemm_kernel(FlatLaunch L) {
         const int gn = n0 + wn * T::kWN + j * 16 + lrow;
         if (gm < M && gn < N) {
           double2 v = cscale(alpha, make_double2((double)accR[i][j][r], (double)accI[i][j][r]));
-          if (useC) v = cadd(v, cscale(beta, C[(long long)gm * ldc + gn]));
+          if (useC) v = cadd(v, cscale(beta, kPreC ? cpre[i][j][r] : C[(long long)gm * ldc + gn]));
           D[(long long)gm * ldd + gn] = v;
         }
       }
