@@ -539,13 +539,62 @@ def _serve_trace(args, rate):
     return reqs
 
 
+class _Arena:
+    """The client's request memory: one device allocation made up front and
+    carved first-fit into per-request regions (in complex128 elements), so
+    that admitting a request calls no allocator.  A caching allocator that
+    runs short of memory frees its cached blocks, and each free waits for
+    the whole device, i.e. for the library's queued work."""
+
+    ALIGN = 16                                  # elements (256 bytes)
+
+    def __init__(self, gib):
+        import torch
+        self.n = int(gib * 2 ** 30) // 16 // self.ALIGN * self.ALIGN
+        self.buf = torch.empty(self.n, dtype=torch.complex128, device="cuda:0")
+        self.free = [(0, self.n)]               # sorted (offset, length)
+
+    def _round(self, n):
+        return (n + self.ALIGN - 1) // self.ALIGN * self.ALIGN
+
+    def alloc(self, n):
+        n = self._round(n)
+        for k, (o, l) in enumerate(self.free):
+            if l >= n:
+                if l == n:
+                    del self.free[k]
+                else:
+                    self.free[k] = (o + n, l - n)
+                return o
+        return None
+
+    def release(self, o, n):
+        import bisect
+        n = self._round(n)
+        k = bisect.bisect(self.free, (o, 0))
+        self.free.insert(k, (o, n))
+        if k + 1 < len(self.free) and o + n == self.free[k + 1][0]:
+            self.free[k] = (o, n + self.free[k + 1][1])
+            del self.free[k + 1]
+        if k > 0 and self.free[k - 1][0] + self.free[k - 1][1] == o:
+            self.free[k - 1] = (self.free[k - 1][0], self.free[k - 1][1] + self.free[k][1])
+            del self.free[k]
+
+
+def _req_elems(r):
+    """complex128 elements of one request's self-energies and outputs."""
+    bb, n, ne = r["b"] * r["b"], r["n"], r["ne"]
+    return bb * ne * (3 * n + 3 * (n + 2 * (n - 1)))
+
+
 class _ServeInputs:
     """Shared read-only H per block size (prefix views per block count);
-    per-request self-energies and outputs are made when the client admits
-    the request."""
+    per-request self-energies and outputs are views of a region of the
+    client's arena, filled when the client admits the request."""
 
-    def __init__(self, seed):
+    def __init__(self, seed, arena):
         import torch
+        self.arena = arena
         self.H = {}
         for b in (128, 192, 256):
             gen = torch.Generator(device="cuda:0")
@@ -553,21 +602,40 @@ class _ServeInputs:
             self.H[b] = _herm_bt_dev(gen, 64, b)
 
     def make(self, r):
+        """The request's problem, or None while the arena has no room."""
+        import torch
         from paper_2508_19138_amd import qtx_rgf as Q
         from paper_2508_19138_amd import synth
         n, b, ne = r["n"], r["b"], r["ne"]
+        size = _req_elems(r)
+        off = self.arena.alloc(size)
+        if off is None:
+            return None
+        buf = self.arena.buf
+        pos = [off]
+
+        def take(k):
+            t = buf[pos[0]:pos[0] + ne * k * b * b].view(ne, k, b, b)
+            pos[0] += ne * k * b * b
+            return t
+
         E = np.ascontiguousarray(np.linspace(r["e0"], r["e0"] + 1.0, ne))
-        sr, sl, sg = synth.g_sigma_scalars(E, n)
+        sig = []
+        for scal in synth.g_sigma_scalars(E, n):
+            t = take(n)
+            t.zero_()
+            sc = torch.from_numpy(np.ascontiguousarray(scal)).to("cuda:0")
+            t.diagonal(dim1=-2, dim2=-1).copy_(sc[..., None].expand(ne, n, b))
+            sig.append(t)
+        outs = tuple((take(n), take(n - 1), take(n - 1)) for _ in range(3))
         Hd, Hu = self.H[b]
-        ins = ((Hd[:n], Hu[:n - 1], None), (_eye_dev(sr, b), None, None),
-               (_eye_dev(sl, b), None, None), (_eye_dev(sg, b), None, None))
-        outs = (_outs_dev(ne, n, b), _outs_dev(ne, n, b), _outs_dev(ne, n, b))
-        return {"E": E, "ins": ins, "outs": outs,
+        ins = ((Hd[:n], Hu[:n - 1], None), (sig[0], None, None),
+               (sig[1], None, None), (sig[2], None, None))
+        return {"E": E, "ins": ins, "outs": outs, "off": off, "size": size,
                 "prob": Q.make_g_problem(E, *ins, *outs)}
 
-
-def _req_bytes(r):
-    return 16 * r["b"] * r["b"] * r["ne"] * r["n"] * 12
+    def release(self, k):
+        self.arena.release(k["off"], k["size"])
 
 
 def _lat_summary(lat, n_e_tot, t_span):
@@ -579,15 +647,16 @@ def _lat_summary(lat, n_e_tot, t_span):
             "mean_latency_s": round(float(lat.mean()), 4), "span_s": round(t_span, 3)}
 
 
-def _serve_run(ctx, inputs, reqs, cap, served):
+def _serve_run(ctx, inputs, reqs, served):
     """Replay the arrival trace; returns (latencies, span).  served: submit
-    to the request loop; otherwise solve each request alone, in arrival
+    to the request loop, admitting requests in arrival order while the
+    client's arena has room; otherwise solve each request alone, in arrival
     order, as soon as the previous one is done."""
     import torch
     R = len(reqs)
     lat = [None] * R
     diag = {"client_wait": [], "lib_queue": [], "lib_latency": []}
-    queue, nxt, used, done = [], 0, 0, 0
+    queue, nxt, done = [], 0, 0
     live = {}
     t0 = time.perf_counter()
     last = t0
@@ -597,13 +666,15 @@ def _serve_run(ctx, inputs, reqs, cap, served):
             queue.append(nxt)
             nxt += 1
         if served:
-            while queue and (used + _req_bytes(reqs[queue[0]]) <= cap or not live):
+            while queue:
+                k = inputs.make(reqs[queue[0]])
+                if k is None:
+                    assert live, "request larger than the client arena"
+                    break
                 i = queue.pop(0)
-                k = inputs.make(reqs[i])
                 torch.cuda.current_stream().synchronize()     # inputs written
                 diag["client_wait"].append(time.perf_counter() - t0 - reqs[i]["t"])
                 live[ctx.submit(k["prob"])] = (i, k)
-                used += _req_bytes(reqs[i])
             wait = 1 if (nxt < R or queue) else 50
             cs, _ = ctx.poll(cap=64, wait_ms=wait)
             tn = time.perf_counter()
@@ -613,7 +684,7 @@ def _serve_run(ctx, inputs, reqs, cap, served):
                 lat[i] = (tn - t0) - reqs[i]["t"]
                 diag["lib_queue"].append(c["queue_s"])
                 diag["lib_latency"].append(c["latency_s"])
-                used -= _req_bytes(reqs[i])
+                inputs.release(k)
                 done += 1
                 last = tn
                 if done % 1000 == 0:
@@ -631,9 +702,9 @@ def _serve_run(ctx, inputs, reqs, cap, served):
             assert k["prob"].status == 0
             tn = time.perf_counter()
             lat[i] = (tn - t0) - reqs[i]["t"]
+            inputs.release(k)
             done += 1
             last = tn
-            del k
             if done % 1000 == 0:
                 print("  per-solve loop %d/%d" % (done, R), file=sys.stderr, flush=True)
     return lat, last - t0, diag
@@ -644,8 +715,7 @@ def run_serve(args):
     from paper_2508_19138_amd import qtx_rgf as Q
     rates = [float(x) for x in args.rates.split(",") if x]
     ws = int(args.ws_gib * 2 ** 30)
-    cap = int(args.pool_gib * 2 ** 30)
-    inputs = _ServeInputs(args.seed)
+    inputs = _ServeInputs(args.seed, _Arena(args.pool_gib))
     results = []
     ctx_s = Q.Context(0, budget_bytes=ws)
     ctx_l = Q.Context(0, budget_bytes=ws)
@@ -660,6 +730,7 @@ def run_serve(args):
             cs, _ = ctx_s.poll(cap=4, wait_ms=100)
             if any(c["ticket"] == t for c in cs):
                 break
+        inputs.release(k)
     for rate in rates:
         reqs = _serve_trace(args, rate)
         n_e_tot = sum(r["ne"] for r in reqs)
@@ -668,7 +739,7 @@ def run_serve(args):
         row = {"rate_per_s": rate, "requests": len(reqs), "energy_points": n_e_tot,
                "mean_request_tflop": round(req_flops / 1e12, 4)}
         for name, ctx, served in (("served", ctx_s, True), ("per_solve_loop", ctx_l, False)):
-            lat, span, diag = _serve_run(ctx, inputs, reqs, cap, served)
+            lat, span, diag = _serve_run(ctx, inputs, reqs, served)
             row[name] = _lat_summary(lat, n_e_tot, span)
             if served:
                 # where the time goes: arrival -> submit in the client (input
@@ -701,9 +772,9 @@ def run_serve(args):
         "data": "synthetic",
         "config": {"workload": "serving stream: Poisson arrivals, %d G-type requests per rate, "
                                "each n in 8..64 blocks of b in {128,192,256}, 1..16 energies "
-                               "in a window of width 1 in [-2,2]; client admits requests into "
-                               "%.0f GiB of device memory in arrival order; latency = arrival "
-                               "to observed completion" % (args.requests, args.pool_gib),
+                               "in a window of width 1 in [-2,2]; client admits requests in "
+                               "arrival order into a %.0f GiB device arena allocated up front; "
+                               "latency = arrival to observed completion" % (args.requests, args.pool_gib),
                    "rates_per_s": rates, "seed": args.seed},
         "rates": results,
     }
