@@ -330,6 +330,7 @@ qtx_status qtx_rgf_solve_batch(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int32_t n
     HIPCHK(c, hipSetDevice(c->device));
     return solve(c, probs, np);
   } catch (const Fail& f) {
+    if (c->err.empty()) c->err = f.what;
     try { c->pool->sync_and_collect(c->stats); } catch (...) {}
     return (qtx_status)f.st;
   } catch (...) {
@@ -409,6 +410,7 @@ qtx_status gemm_abi(bool fp32, qtx_rgf_ctx* c, char opa, char opb, int32_t m, in
     return QTX_ERR_INVALID_ARG;
   if (m == 0 || n == 0 || batch == 0) return QTX_OK;
   BusyGuard g(c);
+  c->err.clear();
   try {
     HIPCHK(c, hipSetDevice(c->device));
     Lane L;
@@ -434,6 +436,7 @@ qtx_status gemm_abi(bool fp32, qtx_rgf_ctx* c, char opa, char opb, int32_t m, in
     run_lanes_to_end(c, lp);
     c->pool->exe(0).sync_and_collect(c->stats);
   } catch (const Fail& f) {
+    if (c->err.empty()) c->err = f.what;
     return (qtx_status)f.st;
   }
   return QTX_OK;
@@ -466,6 +469,7 @@ qtx_status qtx_rgf_zinv(qtx_rgf_ctx* c, int32_t b, void* A, void* X, int32_t* in
   if (c->busy) return QTX_ERR_BUSY;
   if (batch == 0) return QTX_OK;
   BusyGuard g(c);
+  c->err.clear();
   void* work = nullptr;
   try {
     HIPCHK(c, hipSetDevice(c->device));
@@ -497,6 +501,7 @@ qtx_status qtx_rgf_zinv(qtx_rgf_ctx* c, int32_t b, void* A, void* X, int32_t* in
     c->pool->exe(0).sync_and_collect(c->stats);
     HIPCHK(c, hipFree(work));
   } catch (const Fail& f) {
+    if (c->err.empty()) c->err = f.what;
     if (work) (void)hipFree(work);
     return (qtx_status)f.st;
   }

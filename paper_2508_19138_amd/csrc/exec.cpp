@@ -22,7 +22,9 @@ namespace qtx {
 #define XCHK(expr)                                  \
   do {                                              \
     hipError_t e_ = (expr);                         \
-    if (e_ != hipSuccess) throw Fail{5};            \
+    if (e_ != hipSuccess)                           \
+      throw Fail{5, std::string(#expr) + ": " +     \
+                        hipGetErrorString(e_)};     \
   } while (0)
 
 // ------------------------------------------------------------------ tuner --

@@ -58,6 +58,7 @@ struct Lane {
 // Thrown for HIP failures; carries the status for the ABI.
 struct Fail {
   int st;
+  std::string what = {};     // the failing call, when one is known
 };
 
 class Tuner {

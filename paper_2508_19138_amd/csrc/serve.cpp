@@ -88,9 +88,12 @@ class Server {
   bool by_b_ = true;
 };
 
-#define SCHK(expr)                                     \
-  do {                                                 \
-    if ((expr) != hipSuccess) throw Fail{QTX_ERR_HIP}; \
+#define SCHK(expr)                                                   \
+  do {                                                               \
+    hipError_t e_ = (expr);                                          \
+    if (e_ != hipSuccess)                                            \
+      throw Fail{QTX_ERR_HIP, std::string(#expr) + ": " +            \
+                                  hipGetErrorString(e_)};            \
   } while (0)
 
 namespace {
@@ -410,7 +413,7 @@ qtx_status qtx_rgf_submit(qtx_rgf_ctx* c, const qtx_rgf_problem* p, uint64_t* ti
     }
     return c->server->submit(*p, ticket);
   } catch (const Fail& f) {
-    c->err = "request loop could not start";
+    c->err = "request loop could not start" + (f.what.empty() ? std::string() : ": " + f.what);
     return (qtx_status)f.st;
   }
 }
