@@ -1,0 +1,84 @@
+"""Retarded open-boundary surface function of a lead (Sec. "Retarded OBC").
+
+TEST INFRASTRUCTURE ONLY (see the package header): nothing on the product
+path may import, call or link this module.
+
+A semi-infinite lead attached to a device contact gives the surface matrix
+x^R, the solution of Eq. (retarded-recursion)
+
+    x = (m - n x n')^{-1},
+
+where m, n and n' are b x b blocks of M - B^R_scatt for the contact: the
+lead's on-site block and its two couplings (n couples a layer to the next
+one into the lead, n' back).  The contact's non-zero block of B^R_OBC is
+n x n' (same section).
+
+* ``obc_fixed_point`` - Eq. (naive), x_{i+1} = (m - n x_i n')^{-1}, for a
+  fixed number of iterations from a given start.  Starting from the previous
+  self-consistent iteration's x is the memoized mode of Sec. "OBC
+  Memoization", where a fixed iteration count keeps all energies in step.
+  Returns x_N, the boundary block n x_N n' and the relative size of the last
+  update, ||x_N - x_{N-1}||_F / ||x_N||_F.
+* ``obc_sancho_rubio`` - the decimation method the paper cites for fewer
+  iterations (Lopez Sancho et al., 1985), written for M blocks.  Layers of
+  the lead obey  n' X_{j-1} + m X_j + n X_{j+1} = delta_j;  eliminating every
+  other layer with g = m_bulk^{-1} leaves a lead of half the layers with
+      n_new  = -n g n,      n'_new = -n' g n',
+      m_bulk_new = m_bulk - n g n' - n' g n,
+      m_surf_new = m_surf - n g n'          (the surface has no layer -1).
+  The couplings shrink geometrically; once they vanish, x = m_surf^{-1}.
+
+All arithmetic is complex128 on the host; inverses are LAPACK via NumPy.
+Parity pins: tests/test_oracle_obc.py.
+"""
+
+import numpy as np
+
+
+def _fro(a):
+    return float(np.sqrt(np.sum(np.abs(a) ** 2)))
+
+
+def obc_fixed_point(m, n, np_, x0, n_iter):
+    """Eq. (naive) for a fixed number of iterations.
+
+    m, n, np_: [b, b] complex blocks (m, n, n'); x0: start [b, b] (zeros for
+    a cold start).  Returns (x_N, n x_N n', ||x_N - x_{N-1}||_F / ||x_N||_F).
+    """
+    if n_iter < 1:
+        raise ValueError("n_iter must be >= 1")
+    x = np.array(x0, dtype=np.complex128)
+    prev = x
+    for _ in range(n_iter):
+        prev = x
+        x = np.linalg.inv(m - n @ x @ np_)
+    upd = _fro(x - prev) / max(_fro(x), np.finfo(float).tiny)
+    return x, n @ x @ np_, upd
+
+
+def obc_sancho_rubio(m, n, np_, max_iter=100, tol=1e-15):
+    """Decimation until ||n_k||_F + ||n'_k||_F <= tol (||n||_F + ||n'||_F).
+
+    Returns (x, n x n', steps taken).  Raises if it does not converge in
+    max_iter steps.
+    """
+    a = np.array(n, dtype=np.complex128)
+    c = np.array(np_, dtype=np.complex128)
+    ms = np.array(m, dtype=np.complex128)
+    mb = np.array(m, dtype=np.complex128)
+    scale = _fro(a) + _fro(c)
+    if scale == 0.0:
+        x = np.linalg.inv(ms)
+        return x, n @ x @ np_, 0
+    for k in range(1, max_iter + 1):
+        g = np.linalg.inv(mb)
+        agc = a @ g @ c
+        cga = c @ g @ a
+        ms = ms - agc
+        mb = mb - agc - cga
+        a = -(a @ g @ a)
+        c = -(c @ g @ c)
+        if _fro(a) + _fro(c) <= tol * scale:
+            x = np.linalg.inv(ms)
+            return x, n @ x @ np_, k
+    raise RuntimeError("Sancho-Rubio decimation did not converge in %d steps" % max_iter)

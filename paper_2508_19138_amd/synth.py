@@ -215,3 +215,24 @@ def uneven_specs(seed, count=512, block_sizes=UNEVEN_BLOCK_SIZES,
     seeds = rng.integers(0, 2 ** 31 - 1, size=count)
     return [{"kind": str(k), "b": int(b), "n": int(n), "E": float(e),
              "seed": int(s)} for k, b, n, e, s in zip(kinds, bs, ns, es, seeds)]
+
+
+def lead_blocks(seed, b, energies, eta=0.05):
+    """Contact blocks of a semi-infinite lead, one set per energy.
+
+    The lead repeats one layer: on-site H00 = (X + X^dagger)/2, X complex
+    N(0, 1/b), and coupling H01 complex N(0, 0.25/b) to the next layer (same
+    draw order as a Hermitian block-tridiagonal matrix with n = 1 plus one
+    upper block).  With S = I and a retarded broadening eta:
+        m(E) = (E + i eta) I - H00,   n = -H01,   n' = -H01^dagger.
+    Returns m [N_E, b, b], n [b, b], n' [b, b] (n, n' shared by all energies).
+    """
+    rng = np.random.default_rng(seed)
+    X = cn(rng, (b, b), 1.0 / b)
+    h00 = 0.5 * (X + X.conj().T)
+    h01 = cn(rng, (b, b), 0.25 / b)
+    E = np.asarray(energies, dtype=np.float64)
+    eye = np.eye(b, dtype=np.complex128)
+    m = (E[:, None, None] + 1j * eta) * eye[None] - h00[None]
+    return np.ascontiguousarray(m), np.ascontiguousarray(-h01), \
+        np.ascontiguousarray(-h01.conj().T)

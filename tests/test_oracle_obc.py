@@ -1,0 +1,131 @@
+"""Pins of the lead surface-function oracle (Sec. "Retarded OBC").
+
+The oracle's two solvers of Eq. (retarded-recursion) are checked against
+results fixed independently of either iteration:
+
+* the uniform chain with coupling t*I: in the eigenbasis of the on-site
+  block the lead splits into scalar chains whose surface function is
+  lambda_k / t, lambda_k the root of lambda + 1/lambda = (z - eps_k)/t with
+  |lambda_k| < 1 (z = E + i eta); at real E outside the band the boundary
+  block t^2 x must equal the chain module's lead self-energy;
+* brute force: the surface block of the dense inverse of a long finite
+  lead (L identical layers), which differs from x by O(|lambda|^(2L));
+* the defining equation itself, retardation (Im x <= 0 for a Hermitian
+  lead) and the fixed point's invariance when started at the solution.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import chain_lead_self_energy, obc_fixed_point, obc_sancho_rubio
+from paper_2508_19138_amd import synth
+
+
+def _chain_surface(z, h0, t):
+    """U diag(lambda_k / t) U^dagger with |lambda_k| < 1 (decaying root)."""
+    eps, U = np.linalg.eigh(h0)
+    w = (z - eps) / t
+    r = np.sqrt(w.astype(np.complex128) ** 2 - 4.0)
+    l1, l2 = (w + r) / 2.0, (w - r) / 2.0
+    lam = np.where(np.abs(l1) < 1.0, l1, l2)
+    return (U * (lam / t)) @ U.conj().T
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _finite_lead_surface(m, n, np_, L):
+    """Block (0, 0) of the inverse of the L-layer lead (dense, brute force)."""
+    b = m.shape[0]
+    A = np.zeros((L * b, L * b), np.complex128)
+    for j in range(L):
+        A[j * b:(j + 1) * b, j * b:(j + 1) * b] = m
+        if j + 1 < L:
+            A[j * b:(j + 1) * b, (j + 1) * b:(j + 2) * b] = n
+            A[(j + 1) * b:(j + 2) * b, j * b:(j + 1) * b] = np_
+    return np.linalg.inv(A)[:b, :b]
+
+
+@pytest.mark.parametrize("b,t,E,eta", [(1, 1.0, 0.3, 0.05), (4, 0.7, -0.5, 0.1),
+                                       (6, 1.3, 1.1, 0.02)])
+def test_chain_surface_function_closed_form(b, t, E, eta):
+    rng = np.random.default_rng(7 + b)
+    X = synth.cn(rng, (b, b), 1.0 / b)
+    h0 = 0.5 * (X + X.conj().T)
+    z = E + 1j * eta
+    m = z * np.eye(b) - h0
+    n = -t * np.eye(b, dtype=np.complex128)
+    exact = _chain_surface(z, h0, t)
+    xs, sig, steps = obc_sancho_rubio(m, n, n)
+    assert _rel(xs, exact) < 1e-12, steps
+    assert _rel(sig, t * t * exact) < 1e-12
+    # Eq. (naive) contracts by about |lambda|^2 per iteration
+    xf, sigf, upd = obc_fixed_point(m, n, n, np.zeros((b, b), np.complex128), 4000)
+    assert _rel(xf, exact) < 1e-10
+    assert upd < 1e-12
+
+
+@pytest.mark.parametrize("E", [-3.1, 2.7])
+def test_boundary_block_matches_chain_self_energy_outside_band(E):
+    b, t = 5, 1.0
+    rng = np.random.default_rng(11)
+    X = synth.cn(rng, (b, b), 0.2 / b)
+    h0 = 0.5 * (X + X.conj().T)
+    m = E * np.eye(b) - h0
+    n = -t * np.eye(b, dtype=np.complex128)
+    _, sig, _ = obc_sancho_rubio(m, n, n)
+    assert _rel(sig, chain_lead_self_energy(E, h0, t)) < 1e-12
+
+
+@pytest.mark.parametrize("b,E,eta", [(3, 0.2, 0.3), (8, -0.7, 0.25)])
+def test_general_lead_matches_dense_finite_lead(b, E, eta):
+    m, n, np_ = synth.lead_blocks(5 + b, b, [E], eta=eta)
+    m = m[0]
+    xs, _, _ = obc_sancho_rubio(m, n, np_)
+    x_dense = _finite_lead_surface(m, n, np_, 120)
+    assert _rel(xs, x_dense) < 1e-11
+    xf, _, _ = obc_fixed_point(m, n, np_, np.zeros((b, b), np.complex128), 400)
+    assert _rel(xf, x_dense) < 1e-11
+
+
+def test_non_hermitian_couplings_solve_the_defining_equation():
+    rng = np.random.default_rng(3)
+    b = 6
+    m = (0.4 + 0.3j) * np.eye(b) + synth.cn(rng, (b, b), 0.1 / b)
+    n = synth.cn(rng, (b, b), 0.2 / b)
+    np_ = synth.cn(rng, (b, b), 0.2 / b)          # not n^dagger
+    xs, sig, _ = obc_sancho_rubio(m, n, np_)
+    assert _rel(xs, np.linalg.inv(m - n @ xs @ np_)) < 1e-13
+    assert _rel(sig, n @ xs @ np_) < 1e-15
+    xf, _, _ = obc_fixed_point(m, n, np_, np.zeros((b, b), np.complex128), 200)
+    assert _rel(xf, xs) < 1e-12
+
+
+def test_retarded_surface_function_has_nonpositive_imaginary_part():
+    m, n, np_ = synth.lead_blocks(21, 10, [-0.4, 0.0, 0.9], eta=0.05)
+    for e in range(3):
+        xs, _, _ = obc_sancho_rubio(m[e], n, np_)
+        im = (xs - xs.conj().T) / 2j
+        assert np.linalg.eigvalsh(im).max() < 1e-12
+
+
+def test_memoized_start_is_a_fixed_point():
+    m, n, np_ = synth.lead_blocks(4, 12, [0.5], eta=0.05)
+    xs, sig_s, _ = obc_sancho_rubio(m[0], n, np_)
+    x3, sig3, upd = obc_fixed_point(m[0], n, np_, xs, 3)
+    assert _rel(x3, xs) < 1e-12
+    assert _rel(sig3, sig_s) < 1e-12
+    assert upd < 1e-12
+
+
+def test_fixed_point_first_iteration_and_update_definition():
+    m, n, np_ = synth.lead_blocks(9, 4, [0.1], eta=0.2)
+    x0 = np.zeros((4, 4), np.complex128)
+    x1, sig1, upd1 = obc_fixed_point(m[0], n, np_, x0, 1)
+    assert np.allclose(x1, np.linalg.inv(m[0]), rtol=0, atol=1e-15)
+    assert upd1 == pytest.approx(1.0, abs=1e-15)        # ||x1 - 0|| / ||x1||
+    x2, _, upd2 = obc_fixed_point(m[0], n, np_, x0, 2)
+    assert upd2 == pytest.approx(np.linalg.norm(x2 - x1) / np.linalg.norm(x2), rel=1e-12)
+    with pytest.raises(ValueError):
+        obc_fixed_point(m[0], n, np_, x0, 0)
