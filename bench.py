@@ -57,7 +57,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--mode", default="plain",
-                    choices=["plain", "mixed", "uneven", "serve", "gemm"])
+                    choices=["plain", "mixed", "uneven", "serve", "gemm", "obc"])
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-blocks", type=int, default=32)
@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--bt-sigma", action="store_true",
                     help="plain/mixed: self-energies with block-tridiagonal parts (general "
                          "path, F_BT flop model); use --energies 96 to fit HBM")
+    ap.add_argument("--obc-iters", type=int, default=20,
+                    help="obc: fixed-point iterations per call (memoized mode)")
     ap.add_argument("--per-b", action="store_true",
                     help="uneven: also time the merged batch of each block size alone")
     ap.add_argument("--no-profile", action="store_true",
@@ -797,6 +799,79 @@ PAPER_CONTEXT = {
 }
 
 
+def run_obc(args):
+    """Lead surface function (retarded OBC) in the memoized mode: every call
+    runs a fixed number of fixed-point iterations over all energies, starting
+    from the previous call's result, and returns x, n x n' and the update."""
+    import torch
+    from paper_2508_19138_amd import qtx_rgf as Q
+    from paper_2508_19138_amd import synth
+    b, ne, it = args.block_size, args.energies, args.obc_iters
+    E = synth.energy_grid(ne)
+    m, n, np_ = synth.lead_blocks(args.seed, b, E, eta=0.05)
+    dev = lambda a: torch.from_numpy(a).to("cuda:0")
+    dm, dn, dnp = dev(m), dev(n), dev(np_)
+    x = torch.zeros((ne, b, b), dtype=torch.complex128, device="cuda:0")
+    sig = torch.empty_like(x)
+    upd = torch.empty(ne, dtype=torch.float64, device="cuda:0")
+    info = torch.zeros(ne, dtype=torch.int32, device="cuda:0")
+    flops_call = ne * (3 * it + 2) * 8.0 * b ** 3
+    with Q.Context(0, profile=not args.no_profile) as ctx:
+        torch.cuda.synchronize()
+        for _ in range(max(1, args.warmup)):        # also brings x near the solution
+            ctx.obc_fixed_point(b, ne, dm, b * b, dn, 0, dnp, 0, x, sig, upd, info, it)
+        torch.cuda.synchronize()
+        ctx.reset_stats()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.obc_fixed_point(b, ne, dm, b * b, dn, 0, dnp, 0, x, sig, upd, info, it)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        roof = None if args.no_profile else _gemm_roofline(
+            ctx, "zgemm", FP64_MFMA_PEAK_TFLOPS,
+            "zgemm_kernel (complex FP64, 4 real MFMA per complex product)")
+        if roof is not None:
+            roof["traffic"] = None           # no counter run of this workload
+        kt = None if args.no_profile else {
+            k: round(ctx.kernel_stats(k)["ms"] / args.steps, 2)
+            for k in ("zgemm", "inverse", "elementwise")}
+    assert int(info.max().item()) == 0 and int(info.min().item()) == 0
+    upd_h = upd.cpu().numpy()
+    cpu = None
+    if args.cpu_energies > 0:
+        from oracle import obc_fixed_point
+        # about 10 s of host work: evenly spaced energies, both ends included
+        k = min(ne, max(args.cpu_energies, 48))
+        idx = [int(i) for i in np.linspace(0, ne - 1, k).round()]
+        x0 = np.zeros((b, b), np.complex128)
+        t1 = time.perf_counter()
+        for e in idx:
+            obc_fixed_point(m[e], n, np_, x0, it)
+        dc = time.perf_counter() - t1
+        cpu = {"value": len(idx) / dc, "unit": "energy-points/s",
+               "cores": os.cpu_count() or 1, "kind": "oracle",
+               "sample": "%d of the %d energies (evenly spaced, both ends), %d iterations "
+                         "each, NumPy/OpenBLAS, %.1f s" % (len(idx), ne, it, dc)}
+    out = {
+        "mode": "obc",
+        "metric": "lead surface functions/s (energy-points/s) + % FP64 MFMA peak",
+        "value": round(ne / dt, 3), "unit": "energy-points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "retarded OBC surface function x = (m - n x n')^-1 by %d "
+                               "fixed-point iterations per call (memoized start), b=%d, "
+                               "%d energies on [-2,2], eta 0.05, shared couplings"
+                               % (it, b, ne), "block_size": b, "n_energies": ne,
+                   "iterations": it, "seed": args.seed},
+        "tflops": round(flops_call / dt / 1e12, 3),
+        "pct_fp64_mfma_peak": round(100 * flops_call / dt / 1e12 / FP64_MFMA_PEAK_TFLOPS, 2),
+        "flops_per_call": flops_call,
+        "last_update_max": float(upd_h.max()), "last_update_median": float(np.median(upd_h)),
+        "roofline": roof, "kernel_time_ms_per_call": kt, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_gemm(args):
     """Product kernel alone; HIP-event time per launch and algorithmic bytes."""
     import torch
@@ -849,6 +924,8 @@ def main():
         run_uneven(args)
     elif args.mode == "gemm":
         run_gemm(args)
+    elif args.mode == "obc":
+        run_obc(args)
     else:
         run_serve(args)
 

@@ -271,6 +271,44 @@ qtx_status qtx_rgf_cgemm(qtx_rgf_ctx* ctx, char opa, char opb, int32_t m,
 qtx_status qtx_rgf_zinv(qtx_rgf_ctx* ctx, int32_t b, void* A, void* X,
                         int32_t* info, int32_t batch);
 
+/* Retarded open-boundary surface function of a lead (Sec. "Retarded OBC"):
+ * the solution x of Eq. (retarded-recursion), x = (m - n x n')^{-1}, by
+ * n_iter iterations of Eq. (naive),
+ *     x_{i+1} = (m - n x_i n')^{-1},
+ * for every energy of a batch at once.  The start is whatever x holds on
+ * entry: zeros for a cold start, or the previous self-consistent
+ * iteration's x (the memoized mode of Sec. "OBC Memoization", where a fixed
+ * iteration count keeps the energies in step).
+ *
+ *   m, n, n_prime  row-major b x b complex128 device blocks (m, n, n'); the
+ *                  block of energy e starts at base + e * s_* elements, and a
+ *                  stride of 0 shares one block among all energies
+ *                  (otherwise s_* >= b*b).  m is typically (E + i eta) S_00 -
+ *                  H_00 - Sigma^R_scatt,00, n and n' the contact couplings.
+ *   x              [batch][b][b] device, contiguous: start on entry, x_N on
+ *                  return.
+ *   sigma          [batch][b][b] device or NULL: the boundary block
+ *                  n x_N n' that enters B^R_OBC.
+ *   update         device double[batch] or NULL: ||x_N - x_{N-1}||_F /
+ *                  ||x_N||_F per energy (the caller's convergence test;
+ *                  infinite if x_N is zero).
+ *   info           device int32[batch]: 0, or +k / -k for the first
+ *                  iteration k (1-based) whose inverse met an exactly zero /
+ *                  a non-finite pivot; that energy's outputs are then
+ *                  meaningless and the others are unaffected.
+ * 1 <= b <= 1024, batch >= 0, n_iter >= 1.  Inputs must be complete on the
+ * device before the call; the call returns when the results are written.
+ * Scratch of 3 * batch * b*b complex128 plus the inverse's panel buffers is
+ * allocated and freed per call (QTX_ERR_NOMEM if that fails).  Errors:
+ * QTX_ERR_INVALID_ARG (bad sizes, strides or NULL), QTX_ERR_BUSY,
+ * QTX_ERR_HIP. */
+qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* ctx, int32_t b, int32_t batch,
+                                   const void* m, int64_t s_m, const void* n,
+                                   int64_t s_n, const void* n_prime,
+                                   int64_t s_np, void* x, void* sigma,
+                                   double* update, int32_t* info,
+                                   int32_t n_iter);
+
 #ifdef __cplusplus
 }
 #endif

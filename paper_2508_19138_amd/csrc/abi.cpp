@@ -508,4 +508,108 @@ qtx_status qtx_rgf_zinv(qtx_rgf_ctx* c, int32_t b, void* A, void* X, int32_t* in
   return QTX_OK;
 }
 
+// Eq. (naive) for all energies at once: one lane holding the n_iter
+// iterations (two products and one inverse each) and the boundary block, so
+// the whole chain runs as merged launches with no host round trip.
+qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t batch, const void* m,
+                                   int64_t s_m, const void* n, int64_t s_n, const void* n_prime,
+                                   int64_t s_np, void* x, void* sigma, double* update,
+                                   int32_t* info, int32_t n_iter) {
+  if (!c || b < 1 || b > 1024 || batch < 0 || n_iter < 1 || !m || !n || !n_prime || !x || !info)
+    return QTX_ERR_INVALID_ARG;
+  const long long bb = (long long)b * b;
+  auto bad_stride = [bb](int64_t st) { return st != 0 && st < bb; };
+  if (bad_stride(s_m) || bad_stride(s_n) || bad_stride(s_np)) return QTX_ERR_INVALID_ARG;
+  if (c->busy) return QTX_ERR_BUSY;
+  if (batch == 0) return QTX_OK;
+  BusyGuard g(c);
+  c->err.clear();
+  char* work = nullptr;
+  try {
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t blk = (size_t)batch * bb * 16;
+    const size_t pan = (size_t)batch * b * kPanel * 16;
+    const size_t span = (size_t)batch * b * kSuper * 16;
+    const size_t ints = (size_t)batch * b * 4;
+    if (hipMalloc((void**)&work, 3 * blk + 2 * pan + 2 * span + 2 * ints + 4096) != hipSuccess) {
+      (void)hipGetLastError();
+      work = nullptr;
+      c->err = "scratch allocation of the fixed-point iteration failed";
+      return QTX_ERR_NOMEM;
+    }
+    void* T = work;
+    void* W = work + blk;
+    void* xb = work + 2 * blk;
+    char* iw = work + 3 * blk;
+    const int cfg = c->tuner.cfg(b, b, b, false, c->stream);
+    Lane L;
+    // D = alpha A B + beta C over the batch (strides in elements)
+    auto gemm = [&](const void* A, long long sA, const void* B, long long sB, const void* C,
+                    long long sC, void* D, double alpha, double beta) {
+      GemmDesc d{};
+      d.A = A; d.sA = sA; d.lda = b;
+      d.B = B; d.sB = sB; d.ldb = b;
+      d.C = C; d.sC = sC; d.ldc = b;
+      d.D = D; d.sD = bb; d.ldd = b;
+      d.alpha = zc{alpha, 0.0};
+      d.beta = C ? zc{beta, 0.0} : zc{0.0, 0.0};
+      d.M = b; d.N = b; d.K = b;
+      d.batch = batch; d.batch2 = 1;
+      L.gd.push_back(d);
+      Op o;
+      o.k = OpK::Gemm;
+      o.opa = 'N'; o.opb = 'N'; o.fp32 = false;
+      o.cfg = cfg;
+      o.first = (int)L.gd.size() - 1; o.count = 1;
+      o.flops = 8.0 * (double)bb * b * batch;
+      o.bytes = 16.0 * 4.0 * (double)bb * batch;
+      L.ops.push_back(o);
+    };
+    void* cur = x;
+    void* nxt = xb;
+    for (int it = 0; it < n_iter; ++it) {
+      gemm(cur, bb, n_prime, s_np, nullptr, 0, T, 1.0, 0.0);          // T = x_i n'
+      gemm(n, s_n, T, bb, m, s_m, W, -1.0, 1.0);                      // W = m - n T
+      InvDesc d{};                                                    // x_{i+1} = W^{-1}
+      d.S = W; d.sS = bb;
+      d.X = nxt; d.sX = bb;
+      d.panel = iw;
+      d.brow = iw + pan;
+      d.spanel = iw + 2 * pan;
+      d.sbrow = iw + 2 * pan + span;
+      d.perm = (int*)(iw + 2 * pan + 2 * span);
+      d.used = (int*)(iw + 2 * pan + 2 * span + ints);
+      d.info = info; d.code = it + 1; d.reset_info = it == 0 ? 1 : 0;
+      d.b = b; d.batch = batch;
+      L.id.push_back(d);
+      Op o;
+      o.k = OpK::Inv;
+      o.first = (int)L.id.size() - 1; o.count = 1;
+      o.flops = 8.0 * (double)bb * b * batch;
+      L.ops.push_back(o);
+      std::swap(cur, nxt);
+    }
+    // cur = x_N, nxt = x_{N-1}
+    if (sigma) {
+      gemm(cur, bb, n_prime, s_np, nullptr, 0, T, 1.0, 0.0);
+      gemm(n, s_n, T, bb, nullptr, 0, sigma, 1.0, 0.0);
+    }
+    std::vector<Lane*> lp{&L};
+    run_lanes_to_end(c, lp);
+    const hipStream_t st = c->pool->exe(0).stream();
+    if (update) HIPCHK(c, launch_update_norm(cur, nxt, update, bb, batch, st));
+    if (cur != x) HIPCHK(c, hipMemcpyAsync(x, cur, blk, hipMemcpyDeviceToDevice, st));
+    c->pool->exe(0).sync_and_collect(c->stats);
+    HIPCHK(c, hipFree(work));
+  } catch (const Fail& f) {
+    if (c->err.empty()) c->err = f.what;
+    if (work) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(work);
+    }
+    return (qtx_status)f.st;
+  }
+  return QTX_OK;
+}
+
 }  // extern "C"

@@ -127,7 +127,46 @@ void transcomb_kernel(FlatLaunch L) {
   }
 }
 
+// Relative size of the last fixed-point update of every matrix: one
+// workgroup per matrix sums |x - prev|^2 and |x|^2 over its elements
+// (strided by the workgroup, then a tree in LDS).
+__global__ __launch_bounds__(256)
+void update_norm_kernel(const double2* __restrict__ x, const double2* __restrict__ prev,
+                        double* __restrict__ out, long long bb) {
+  const long long e = blockIdx.x;
+  const double2* a = x + e * bb;
+  const double2* p = prev + e * bb;
+  double sd = 0.0, sx = 0.0;
+  for (long long i = threadIdx.x; i < bb; i += 256) {
+    const double2 u = a[i], v = p[i];
+    const double dx = u.x - v.x, dy = u.y - v.y;
+    sd += dx * dx + dy * dy;
+    sx += u.x * u.x + u.y * u.y;
+  }
+  __shared__ double rd[256], rx[256];
+  const int t = threadIdx.x;
+  rd[t] = sd;
+  rx[t] = sx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      rd[t] += rd[t + h];
+      rx[t] += rx[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) out[e] = rx[0] > 0.0 ? sqrt(rd[0]) / sqrt(rx[0]) : (rd[0] > 0.0 ? HUGE_VAL : 0.0);
+}
+
 }  // namespace
+
+hipError_t launch_update_norm(const void* x, const void* prev, double* out, long long bb,
+                              int batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(update_norm_kernel, dim3(batch), dim3(256), 0, s, (const double2*)x,
+                     (const double2*)prev, out, bb);
+  return hipGetLastError();
+}
 
 hipError_t launch_lincomb(const FlatLaunch& l, hipStream_t s) {
   if (l.total <= 0) return hipSuccess;

@@ -135,6 +135,10 @@ struct TransDesc {
 constexpr int kTransTile = 32;
 hipError_t launch_lincomb(const FlatLaunch& l, hipStream_t s);
 hipError_t launch_transcomb(const FlatLaunch& l, hipStream_t s);
+// out[e] = ||x_e - prev_e||_F / ||x_e||_F for `batch` contiguous matrices of
+// bb complex elements each (one workgroup per matrix).
+hipError_t launch_update_norm(const void* x, const void* prev, double* out, long long bb,
+                              int batch, hipStream_t s);
 
 // workgroups per matrix of the elementwise kernels
 __host__ __device__ inline int lincomb_chunks(int b) { return (int)(((long long)b * b + kLinChunk - 1) / kLinChunk); }

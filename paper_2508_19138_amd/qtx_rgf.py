@@ -117,6 +117,12 @@ def lib():
     L.qtx_rgf_zinv.argtypes = [c_ctx, ctypes.c_int32, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
     L.qtx_rgf_zinv.restype = ctypes.c_int
+    L.qtx_rgf_obc_fixed_point.argtypes = [
+        c_ctx, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_int32]
+    L.qtx_rgf_obc_fixed_point.restype = ctypes.c_int
     L.qtx_rgf_submit.argtypes = [c_ctx, ctypes.POINTER(Problem),
                                  ctypes.POINTER(ctypes.c_uint64)]
     L.qtx_rgf_submit.restype = ctypes.c_int
@@ -133,7 +139,8 @@ def exported_symbols():
             "qtx_rgf_status_string", "qtx_rgf_last_error",
             "qtx_rgf_flops_per_energy", "qtx_rgf_kernel_stats",
             "qtx_rgf_reset_stats", "qtx_rgf_zgemm", "qtx_rgf_cgemm",
-            "qtx_rgf_zinv", "qtx_rgf_submit", "qtx_rgf_poll"]
+            "qtx_rgf_zinv", "qtx_rgf_submit", "qtx_rgf_poll",
+            "qtx_rgf_obc_fixed_point"]
 
 
 def status_string(st):
@@ -255,6 +262,15 @@ class Context:
     def zinv(self, b, A, X, info, batch):
         st = lib().qtx_rgf_zinv(self._h, b, _ptr(A), _ptr(X), _ptr(info), batch)
         return self._check(st, "qtx_rgf_zinv")
+
+    def obc_fixed_point(self, b, batch, m, s_m, n, s_n, n_prime, s_np, x, sigma,
+                        update, info, n_iter):
+        """n_iter iterations of x <- (m - n x n')^{-1}; see the C header.
+        Strides in complex elements between energies (0 = shared block)."""
+        st = lib().qtx_rgf_obc_fixed_point(self._h, b, batch, _ptr(m), s_m, _ptr(n), s_n,
+                                           _ptr(n_prime), s_np, _ptr(x), _ptr(sigma),
+                                           _ptr(update), _ptr(info), n_iter)
+        return self._check(st, "qtx_rgf_obc_fixed_point")
 
 
 def make_g_problem(energies_host, H, sigma_r, sigma_l, sigma_g, XR, XL=None,
