@@ -70,7 +70,10 @@ def parse():
                     help="plain/mixed: self-energies with block-tridiagonal parts (general "
                          "path, F_BT flop model); use --energies 96 to fit HBM")
     ap.add_argument("--obc-iters", type=int, default=20,
-                    help="obc: fixed-point iterations per call (memoized mode)")
+                    help="obc: fixed-point iterations (or decimation steps) per call")
+    ap.add_argument("--obc-method", default="fixed", choices=["fixed", "sancho"],
+                    help="obc: memoized fixed-point iterations, or Sancho-Rubio decimation "
+                         "from scratch")
     ap.add_argument("--per-b", action="store_true",
                     help="uneven: also time the merged batch of each block size alone")
     ap.add_argument("--no-profile", action="store_true",
@@ -815,16 +818,27 @@ def run_obc(args):
     sig = torch.empty_like(x)
     upd = torch.empty(ne, dtype=torch.float64, device="cuda:0")
     info = torch.zeros(ne, dtype=torch.int32, device="cuda:0")
-    flops_call = ne * (3 * it + 2) * 8.0 * b ** 3
+    sancho = args.obc_method == "sancho"
+    # fixed point: two products and one inverse per iteration; decimation:
+    # six products and one inverse per step and one final inverse; both end
+    # with the two products of n x n' (an inverse counts as 8 b^3)
+    flops_call = ne * ((7 * it + 3) if sancho else (3 * it + 2)) * 8.0 * b ** 3
+
+    def run(ctx):
+        if sancho:
+            ctx.obc_sancho_rubio(b, ne, dm, b * b, dn, 0, dnp, 0, x, sig, upd, info, it)
+        else:
+            ctx.obc_fixed_point(b, ne, dm, b * b, dn, 0, dnp, 0, x, sig, upd, info, it)
+
     with Q.Context(0, profile=not args.no_profile) as ctx:
         torch.cuda.synchronize()
         for _ in range(max(1, args.warmup)):        # also brings x near the solution
-            ctx.obc_fixed_point(b, ne, dm, b * b, dn, 0, dnp, 0, x, sig, upd, info, it)
+            run(ctx)
         torch.cuda.synchronize()
         ctx.reset_stats()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            ctx.obc_fixed_point(b, ne, dm, b * b, dn, 0, dnp, 0, x, sig, upd, info, it)
+            run(ctx)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         roof = None if args.no_profile else _gemm_roofline(
@@ -839,14 +853,17 @@ def run_obc(args):
     upd_h = upd.cpu().numpy()
     cpu = None
     if args.cpu_energies > 0:
-        from oracle import obc_fixed_point
+        from oracle import obc_fixed_point, obc_sancho_rubio_steps
         # about 10 s of host work: evenly spaced energies, both ends included
-        k = min(ne, max(args.cpu_energies, 48))
+        k = min(ne, max(args.cpu_energies, 20 if sancho else 48))
         idx = [int(i) for i in np.linspace(0, ne - 1, k).round()]
         x0 = np.zeros((b, b), np.complex128)
         t1 = time.perf_counter()
         for e in idx:
-            obc_fixed_point(m[e], n, np_, x0, it)
+            if sancho:
+                obc_sancho_rubio_steps(m[e], n, np_, it)
+            else:
+                obc_fixed_point(m[e], n, np_, x0, it)
         dc = time.perf_counter() - t1
         cpu = {"value": len(idx) / dc, "unit": "energy-points/s",
                "cores": os.cpu_count() or 1, "kind": "oracle",
@@ -859,14 +876,18 @@ def run_obc(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
         "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "retarded OBC surface function x = (m - n x n')^-1 by %d "
-                               "fixed-point iterations per call (memoized start), b=%d, "
-                               "%d energies on [-2,2], eta 0.05, shared couplings"
-                               % (it, b, ne), "block_size": b, "n_energies": ne,
+                               "%s per call, b=%d, %d energies on [-2,2], eta 0.05, "
+                               "shared couplings"
+                               % (it, "Sancho-Rubio decimation steps (from scratch)" if sancho
+                                  else "fixed-point iterations (memoized start)", b, ne),
+                   "block_size": b, "n_energies": ne, "method": args.obc_method,
                    "iterations": it, "seed": args.seed},
         "tflops": round(flops_call / dt / 1e12, 3),
         "pct_fp64_mfma_peak": round(100 * flops_call / dt / 1e12 / FP64_MFMA_PEAK_TFLOPS, 2),
         "flops_per_call": flops_call,
-        "last_update_max": float(upd_h.max()), "last_update_median": float(np.median(upd_h)),
+        ("remaining_coupling_max" if sancho else "last_update_max"): float(upd_h.max()),
+        ("remaining_coupling_median" if sancho else "last_update_median"):
+            float(np.median(upd_h)),
         "roofline": roof, "kernel_time_ms_per_call": kt, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

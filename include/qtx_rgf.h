@@ -309,6 +309,33 @@ qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* ctx, int32_t b, int32_t batch,
                                    double* update, int32_t* info,
                                    int32_t n_iter);
 
+/* The same surface function by Sancho-Rubio decimation, the faster iterative
+ * method the paper cites in Sec. "Retarded OBC" (Lopez Sancho et al., 1985):
+ * n_steps steps for every energy, each eliminating every other layer of the
+ * lead,
+ *     g = m_b^{-1},  m_s -= n g n',  m_b -= n g n' + n' g n,
+ *     n <- -n g n,   n' <- -n' g n',
+ * starting from m_s = m_b = m; then x = m_s^{-1}.  The represented lead
+ * length doubles per step, so the couplings shrink geometrically.
+ *   m, n, n_prime, s_*  as for qtx_rgf_obc_fixed_point.
+ *   x          [batch][b][b] device, contiguous: output only.
+ *   sigma      [batch][b][b] device or NULL: n x n'.
+ *   coupling   device double[batch] or NULL: the remaining coupling
+ *              (||n_N||_F + ||n'_N||_F) / (||n||_F + ||n'||_F), the caller's
+ *              convergence test.
+ *   info       device int32[batch]: 0, or +k / -k for the first inverse that
+ *              met an exactly zero / non-finite pivot: k = step (1-based),
+ *              n_steps + 1 for the final inverse of m_s.
+ * 1 <= b <= 1024, batch >= 0, n_steps >= 1.  Scratch of 11 * batch * b*b
+ * complex128 plus the inverse's panel buffers is allocated and freed per
+ * call.  Errors as for qtx_rgf_obc_fixed_point. */
+qtx_status qtx_rgf_obc_sancho_rubio(qtx_rgf_ctx* ctx, int32_t b, int32_t batch,
+                                    const void* m, int64_t s_m, const void* n,
+                                    int64_t s_n, const void* n_prime,
+                                    int64_t s_np, void* x, void* sigma,
+                                    double* coupling, int32_t* info,
+                                    int32_t n_steps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,11 +32,12 @@ from .assembly import assemble_g, assemble_w, w_retarded_diag
 from .chain import chain_closed_form, chain_lead_self_energy
 from .tridiag import tridiag_inverse_selected
 from .flops import rgf_flops, w_assembly_flops
-from .obc import obc_fixed_point, obc_sancho_rubio
+from .obc import obc_fixed_point, obc_sancho_rubio, obc_sancho_rubio_steps
 
 __all__ = [
     "rgf_selected", "rgf_selected_batch", "dense_from_bt", "dense_selected",
     "assemble_g", "assemble_w", "w_retarded_diag", "chain_closed_form",
     "chain_lead_self_energy", "tridiag_inverse_selected", "rgf_flops",
     "w_assembly_flops", "obc_fixed_point", "obc_sancho_rubio",
+    "obc_sancho_rubio_steps",
 ]

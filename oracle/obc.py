@@ -56,21 +56,21 @@ def obc_fixed_point(m, n, np_, x0, n_iter):
     return x, n @ x @ np_, upd
 
 
-def obc_sancho_rubio(m, n, np_, max_iter=100, tol=1e-15):
-    """Decimation until ||n_k||_F + ||n'_k||_F <= tol (||n||_F + ||n'||_F).
-
-    Returns (x, n x n', steps taken).  Raises if it does not converge in
-    max_iter steps.
-    """
+def _decimate(m, n, np_, steps, tol):
+    """Decimation steps; stops after `steps` (if given) or once the remaining
+    coupling ||n_k||_F + ||n'_k||_F is at most tol times its start."""
     a = np.array(n, dtype=np.complex128)
     c = np.array(np_, dtype=np.complex128)
     ms = np.array(m, dtype=np.complex128)
     mb = np.array(m, dtype=np.complex128)
     scale = _fro(a) + _fro(c)
-    if scale == 0.0:
-        x = np.linalg.inv(ms)
-        return x, n @ x @ np_, 0
-    for k in range(1, max_iter + 1):
+    k = 0
+    while True:
+        rest = (_fro(a) + _fro(c)) / scale if scale > 0.0 else 0.0
+        if steps is not None and k == steps:
+            break
+        if steps is None and rest <= tol:
+            break
         g = np.linalg.inv(mb)
         agc = a @ g @ c
         cga = c @ g @ a
@@ -78,7 +78,30 @@ def obc_sancho_rubio(m, n, np_, max_iter=100, tol=1e-15):
         mb = mb - agc - cga
         a = -(a @ g @ a)
         c = -(c @ g @ c)
-        if _fro(a) + _fro(c) <= tol * scale:
-            x = np.linalg.inv(ms)
-            return x, n @ x @ np_, k
-    raise RuntimeError("Sancho-Rubio decimation did not converge in %d steps" % max_iter)
+        k += 1
+        if steps is None and k > 10000:
+            raise RuntimeError("Sancho-Rubio decimation did not converge")
+    x = np.linalg.inv(ms)
+    return x, n @ x @ np_, k, rest
+
+
+def obc_sancho_rubio(m, n, np_, max_iter=100, tol=1e-15):
+    """Decimation until ||n_k||_F + ||n'_k||_F <= tol (||n||_F + ||n'||_F).
+
+    Returns (x, n x n', steps taken).  Raises if it does not converge in
+    max_iter steps.
+    """
+    x, sig, k, rest = _decimate(m, n, np_, None, tol)
+    if k > max_iter:
+        raise RuntimeError("Sancho-Rubio decimation did not converge in %d steps" % max_iter)
+    return x, sig, k
+
+
+def obc_sancho_rubio_steps(m, n, np_, steps):
+    """Exactly `steps` decimation steps (the fixed count a batched solver
+    runs for every energy).  Returns (x, n x n', remaining coupling
+    (||n_N||_F + ||n'_N||_F) / (||n||_F + ||n'||_F))."""
+    if steps < 1:
+        raise ValueError("steps must be >= 1")
+    x, sig, _, rest = _decimate(m, n, np_, steps, 0.0)
+    return x, sig, rest

@@ -508,6 +508,103 @@ qtx_status qtx_rgf_zinv(qtx_rgf_ctx* c, int32_t b, void* A, void* X, int32_t* in
   return QTX_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One lane of batched b x b complex128 operations for the lead solvers; all
+// energies advance together in merged launches, in the order pushed.
+struct LeadLane {
+  Lane L;
+  int b, batch, cfg;
+  long long bb;
+  char* iw;                    // inverse work buffers for `batch` matrices
+  size_t pan, span, ints;
+
+  LeadLane(qtx_rgf_ctx* c, int b_, int batch_, char* inv_work)
+      : b(b_), batch(batch_), bb((long long)b_ * b_), iw(inv_work) {
+    cfg = c->tuner.cfg(b, b, b, false, c->stream);
+    pan = (size_t)batch * b * kPanel * 16;
+    span = (size_t)batch * b * kSuper * 16;
+    ints = (size_t)batch * b * 4;
+  }
+  static size_t inv_work(int b, int batch) {
+    return (size_t)batch * b * (2 * kPanel + 2 * kSuper) * 16 + (size_t)batch * b * 8 + 4096;
+  }
+  // D = alpha A B + beta C (strides in elements between energies)
+  void gemm(const void* A, long long sA, const void* B, long long sB, const void* C,
+            long long sC, void* D, double alpha, double beta) {
+    GemmDesc d{};
+    d.A = A; d.sA = sA; d.lda = b;
+    d.B = B; d.sB = sB; d.ldb = b;
+    d.C = C; d.sC = sC; d.ldc = b;
+    d.D = D; d.sD = bb; d.ldd = b;
+    d.alpha = zc{alpha, 0.0};
+    d.beta = C ? zc{beta, 0.0} : zc{0.0, 0.0};
+    d.M = b; d.N = b; d.K = b;
+    d.batch = batch; d.batch2 = 1;
+    L.gd.push_back(d);
+    Op o;
+    o.k = OpK::Gemm;
+    o.opa = 'N'; o.opb = 'N'; o.fp32 = false;
+    o.cfg = cfg;
+    o.first = (int)L.gd.size() - 1; o.count = 1;
+    o.flops = 8.0 * (double)bb * b * batch;
+    o.bytes = 16.0 * (C ? 4.0 : 3.0) * (double)bb * batch;
+    L.ops.push_back(o);
+  }
+  // X = S^{-1} (S is overwritten); info keeps the first failure's code
+  void inv(void* S, void* X, int* info, int code, bool reset_info) {
+    InvDesc d{};
+    d.S = S; d.sS = bb;
+    d.X = X; d.sX = bb;
+    d.panel = iw;
+    d.brow = iw + pan;
+    d.spanel = iw + 2 * pan;
+    d.sbrow = iw + 2 * pan + span;
+    d.perm = (int*)(iw + 2 * pan + 2 * span);
+    d.used = (int*)(iw + 2 * pan + 2 * span + ints);
+    d.info = info; d.code = code; d.reset_info = reset_info ? 1 : 0;
+    d.b = b; d.batch = batch;
+    L.id.push_back(d);
+    Op o;
+    o.k = OpK::Inv;
+    o.first = (int)L.id.size() - 1; o.count = 1;
+    o.flops = 8.0 * (double)bb * b * batch;
+    L.ops.push_back(o);
+  }
+  // D = c0 S0 + c1 S1 (S1 may be null)
+  void lin(const void* s0, long long ss0, double c0, const void* s1, long long ss1, double c1,
+           void* D) {
+    LinCombDesc a{};
+    a.src[0] = s0; a.sSrc[0] = ss0; a.c[0] = zc{c0, 0.0};
+    a.src[1] = s1; a.sSrc[1] = ss1; a.c[1] = zc{c1, 0.0};
+    a.D = D; a.sD = bb;
+    a.b = b; a.batch = batch;
+    L.ld.push_back(a);
+    Op o;
+    o.k = OpK::Lin;
+    o.first = (int)L.ld.size() - 1; o.count = 1;
+    o.bytes = 16.0 * (double)bb * batch * (2 + (s1 != nullptr));
+    L.ops.push_back(o);
+  }
+};
+
+qtx_status lead_args_ok(int32_t b, int32_t batch, const void* m, int64_t s_m, const void* n,
+                        int64_t s_n, const void* n_prime, int64_t s_np, const void* x,
+                        const int32_t* info, int32_t count) {
+  if (b < 1 || b > 1024 || batch < 0 || count < 1 || !m || !n || !n_prime || !x || !info)
+    return QTX_ERR_INVALID_ARG;
+  const long long bb = (long long)b * b;
+  auto bad_stride = [bb](int64_t st) { return st != 0 && st < bb; };
+  if (bad_stride(s_m) || bad_stride(s_n) || bad_stride(s_np)) return QTX_ERR_INVALID_ARG;
+  return QTX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 // Eq. (naive) for all energies at once: one lane holding the n_iter
 // iterations (two products and one inverse each) and the boundary block, so
 // the whole chain runs as merged launches with no host round trip.
@@ -515,11 +612,9 @@ qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t batch, con
                                    int64_t s_m, const void* n, int64_t s_n, const void* n_prime,
                                    int64_t s_np, void* x, void* sigma, double* update,
                                    int32_t* info, int32_t n_iter) {
-  if (!c || b < 1 || b > 1024 || batch < 0 || n_iter < 1 || !m || !n || !n_prime || !x || !info)
-    return QTX_ERR_INVALID_ARG;
-  const long long bb = (long long)b * b;
-  auto bad_stride = [bb](int64_t st) { return st != 0 && st < bb; };
-  if (bad_stride(s_m) || bad_stride(s_n) || bad_stride(s_np)) return QTX_ERR_INVALID_ARG;
+  if (!c) return QTX_ERR_INVALID_ARG;
+  const qtx_status ok = lead_args_ok(b, batch, m, s_m, n, s_n, n_prime, s_np, x, info, n_iter);
+  if (ok != QTX_OK) return ok;
   if (c->busy) return QTX_ERR_BUSY;
   if (batch == 0) return QTX_OK;
   BusyGuard g(c);
@@ -527,11 +622,9 @@ qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t batch, con
   char* work = nullptr;
   try {
     HIPCHK(c, hipSetDevice(c->device));
+    const long long bb = (long long)b * b;
     const size_t blk = (size_t)batch * bb * 16;
-    const size_t pan = (size_t)batch * b * kPanel * 16;
-    const size_t span = (size_t)batch * b * kSuper * 16;
-    const size_t ints = (size_t)batch * b * 4;
-    if (hipMalloc((void**)&work, 3 * blk + 2 * pan + 2 * span + 2 * ints + 4096) != hipSuccess) {
+    if (hipMalloc((void**)&work, 3 * blk + LeadLane::inv_work(b, batch)) != hipSuccess) {
       (void)hipGetLastError();
       work = nullptr;
       c->err = "scratch allocation of the fixed-point iteration failed";
@@ -540,65 +633,105 @@ qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t batch, con
     void* T = work;
     void* W = work + blk;
     void* xb = work + 2 * blk;
-    char* iw = work + 3 * blk;
-    const int cfg = c->tuner.cfg(b, b, b, false, c->stream);
-    Lane L;
-    // D = alpha A B + beta C over the batch (strides in elements)
-    auto gemm = [&](const void* A, long long sA, const void* B, long long sB, const void* C,
-                    long long sC, void* D, double alpha, double beta) {
-      GemmDesc d{};
-      d.A = A; d.sA = sA; d.lda = b;
-      d.B = B; d.sB = sB; d.ldb = b;
-      d.C = C; d.sC = sC; d.ldc = b;
-      d.D = D; d.sD = bb; d.ldd = b;
-      d.alpha = zc{alpha, 0.0};
-      d.beta = C ? zc{beta, 0.0} : zc{0.0, 0.0};
-      d.M = b; d.N = b; d.K = b;
-      d.batch = batch; d.batch2 = 1;
-      L.gd.push_back(d);
-      Op o;
-      o.k = OpK::Gemm;
-      o.opa = 'N'; o.opb = 'N'; o.fp32 = false;
-      o.cfg = cfg;
-      o.first = (int)L.gd.size() - 1; o.count = 1;
-      o.flops = 8.0 * (double)bb * b * batch;
-      o.bytes = 16.0 * 4.0 * (double)bb * batch;
-      L.ops.push_back(o);
-    };
+    LeadLane q(c, b, batch, work + 3 * blk);
     void* cur = x;
     void* nxt = xb;
     for (int it = 0; it < n_iter; ++it) {
-      gemm(cur, bb, n_prime, s_np, nullptr, 0, T, 1.0, 0.0);          // T = x_i n'
-      gemm(n, s_n, T, bb, m, s_m, W, -1.0, 1.0);                      // W = m - n T
-      InvDesc d{};                                                    // x_{i+1} = W^{-1}
-      d.S = W; d.sS = bb;
-      d.X = nxt; d.sX = bb;
-      d.panel = iw;
-      d.brow = iw + pan;
-      d.spanel = iw + 2 * pan;
-      d.sbrow = iw + 2 * pan + span;
-      d.perm = (int*)(iw + 2 * pan + 2 * span);
-      d.used = (int*)(iw + 2 * pan + 2 * span + ints);
-      d.info = info; d.code = it + 1; d.reset_info = it == 0 ? 1 : 0;
-      d.b = b; d.batch = batch;
-      L.id.push_back(d);
-      Op o;
-      o.k = OpK::Inv;
-      o.first = (int)L.id.size() - 1; o.count = 1;
-      o.flops = 8.0 * (double)bb * b * batch;
-      L.ops.push_back(o);
+      q.gemm(cur, bb, n_prime, s_np, nullptr, 0, T, 1.0, 0.0);       // T = x_i n'
+      q.gemm(n, s_n, T, bb, m, s_m, W, -1.0, 1.0);                   // W = m - n T
+      q.inv(W, nxt, info, it + 1, it == 0);                          // x_{i+1} = W^{-1}
       std::swap(cur, nxt);
     }
     // cur = x_N, nxt = x_{N-1}
     if (sigma) {
-      gemm(cur, bb, n_prime, s_np, nullptr, 0, T, 1.0, 0.0);
-      gemm(n, s_n, T, bb, nullptr, 0, sigma, 1.0, 0.0);
+      q.gemm(cur, bb, n_prime, s_np, nullptr, 0, T, 1.0, 0.0);
+      q.gemm(n, s_n, T, bb, nullptr, 0, sigma, 1.0, 0.0);
     }
-    std::vector<Lane*> lp{&L};
+    std::vector<Lane*> lp{&q.L};
     run_lanes_to_end(c, lp);
     const hipStream_t st = c->pool->exe(0).stream();
     if (update) HIPCHK(c, launch_update_norm(cur, nxt, update, bb, batch, st));
     if (cur != x) HIPCHK(c, hipMemcpyAsync(x, cur, blk, hipMemcpyDeviceToDevice, st));
+    c->pool->exe(0).sync_and_collect(c->stats);
+    HIPCHK(c, hipFree(work));
+  } catch (const Fail& f) {
+    if (c->err.empty()) c->err = f.what;
+    if (work) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(work);
+    }
+    return (qtx_status)f.st;
+  }
+  return QTX_OK;
+}
+
+// Sancho-Rubio decimation for all energies at once: each step copies the
+// bulk block (the inverse overwrites its input), inverts it, forms
+// n g n' once and folds it into both the surface and the bulk blocks, and
+// squares the couplings; then x = m_surf^{-1} and n x n'.
+qtx_status qtx_rgf_obc_sancho_rubio(qtx_rgf_ctx* c, int32_t b, int32_t batch, const void* m,
+                                    int64_t s_m, const void* n, int64_t s_n,
+                                    const void* n_prime, int64_t s_np, void* x, void* sigma,
+                                    double* coupling, int32_t* info, int32_t n_steps) {
+  if (!c) return QTX_ERR_INVALID_ARG;
+  const qtx_status ok = lead_args_ok(b, batch, m, s_m, n, s_n, n_prime, s_np, x, info, n_steps);
+  if (ok != QTX_OK) return ok;
+  if (c->busy) return QTX_ERR_BUSY;
+  if (batch == 0) return QTX_OK;
+  BusyGuard g(c);
+  c->err.clear();
+  char* work = nullptr;
+  try {
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long bb = (long long)b * b;
+    const size_t blk = (size_t)batch * bb * 16;
+    constexpr int kBlocks = 11;
+    if (hipMalloc((void**)&work, kBlocks * blk + LeadLane::inv_work(b, batch)) != hipSuccess) {
+      (void)hipGetLastError();
+      work = nullptr;
+      c->err = "scratch allocation of the decimation failed";
+      return QTX_ERR_NOMEM;
+    }
+    char* w = work;
+    void* ms = w;            void* mb = w + blk;       void* W = w + 2 * blk;
+    void* gi = w + 3 * blk;  void* ga = w + 4 * blk;   void* gc = w + 5 * blk;
+    void* T = w + 6 * blk;
+    void* a2[2] = {w + 7 * blk, w + 8 * blk};
+    void* c2[2] = {w + 9 * blk, w + 10 * blk};
+    LeadLane q(c, b, batch, work + kBlocks * blk);
+    const void* a = n;         long long sa = s_n;
+    const void* cp = n_prime;  long long sc = s_np;
+    const void* msrc = m;      long long sms = s_m;    // surface block so far
+    const void* mbsrc = m;     long long smb = s_m;    // bulk block so far
+    for (int k = 0; k < n_steps; ++k) {
+      q.lin(mbsrc, smb, 1.0, nullptr, 0, 0.0, W);                  // W = m_bulk
+      q.inv(W, gi, info, k + 1, k == 0);                           // g = m_bulk^{-1}
+      q.gemm(gi, bb, a, sa, nullptr, 0, ga, 1.0, 0.0);             // g n
+      q.gemm(gi, bb, cp, sc, nullptr, 0, gc, 1.0, 0.0);            // g n'
+      q.gemm(a, sa, gc, bb, nullptr, 0, T, 1.0, 0.0);              // T = n g n'
+      q.lin(msrc, sms, 1.0, T, bb, -1.0, ms);                      // m_surf -= T
+      q.lin(mbsrc, smb, 1.0, T, bb, -1.0, mb);                     // m_bulk -= T
+      q.gemm(cp, sc, ga, bb, mb, bb, mb, -1.0, 1.0);               // m_bulk -= n' g n
+      void* an = a2[k & 1];
+      void* cn = c2[k & 1];
+      q.gemm(a, sa, ga, bb, nullptr, 0, an, -1.0, 0.0);            // n <- -n g n
+      q.gemm(cp, sc, gc, bb, nullptr, 0, cn, -1.0, 0.0);           // n' <- -n' g n'
+      a = an; sa = bb;
+      cp = cn; sc = bb;
+      msrc = ms; sms = bb;
+      mbsrc = mb; smb = bb;
+    }
+    q.lin(ms, bb, 1.0, nullptr, 0, 0.0, W);
+    q.inv(W, x, info, n_steps + 1, false);                         // x = m_surf^{-1}
+    if (sigma) {
+      q.gemm(x, bb, n_prime, s_np, nullptr, 0, T, 1.0, 0.0);
+      q.gemm(n, s_n, T, bb, nullptr, 0, sigma, 1.0, 0.0);
+    }
+    std::vector<Lane*> lp{&q.L};
+    run_lanes_to_end(c, lp);
+    const hipStream_t st = c->pool->exe(0).stream();
+    if (coupling)
+      HIPCHK(c, launch_coupling_norm(a, cp, n, s_n, n_prime, s_np, coupling, bb, batch, st));
     c->pool->exe(0).sync_and_collect(c->stats);
     HIPCHK(c, hipFree(work));
   } catch (const Fail& f) {

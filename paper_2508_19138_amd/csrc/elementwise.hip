@@ -158,7 +158,53 @@ void update_norm_kernel(const double2* __restrict__ x, const double2* __restrict
   if (t == 0) out[e] = rx[0] > 0.0 ? sqrt(rd[0]) / sqrt(rx[0]) : (rd[0] > 0.0 ? HUGE_VAL : 0.0);
 }
 
+// Remaining coupling of the decimation per matrix:
+// (||a_e||_F + ||c_e||_F) / (||a0_e||_F + ||c0_e||_F), where a0/c0 may be one
+// block shared by all matrices (stride 0).
+__global__ __launch_bounds__(256)
+void coupling_norm_kernel(const double2* __restrict__ a, const double2* __restrict__ c,
+                          const double2* __restrict__ a0, long long sa0,
+                          const double2* __restrict__ c0, long long sc0,
+                          double* __restrict__ out, long long bb) {
+  const long long e = blockIdx.x;
+  const double2* src[4] = {a + e * bb, c + e * bb, a0 + e * sa0, c0 + e * sc0};
+  __shared__ double red[4][256];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double s = 0.0;
+    for (long long i = t; i < bb; i += 256) {
+      const double2 u = src[k][i];
+      s += u.x * u.x + u.y * u.y;
+    }
+    red[k][t] = s;
+  }
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[k][t] += red[k][t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double num = sqrt(red[0][0]) + sqrt(red[1][0]);
+    const double den = sqrt(red[2][0]) + sqrt(red[3][0]);
+    out[e] = den > 0.0 ? num / den : 0.0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_coupling_norm(const void* a, const void* c, const void* a0, long long sa0,
+                                const void* c0, long long sc0, double* out, long long bb,
+                                int batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(coupling_norm_kernel, dim3(batch), dim3(256), 0, s, (const double2*)a,
+                     (const double2*)c, (const double2*)a0, sa0, (const double2*)c0, sc0, out,
+                     bb);
+  return hipGetLastError();
+}
 
 hipError_t launch_update_norm(const void* x, const void* prev, double* out, long long bb,
                               int batch, hipStream_t s) {

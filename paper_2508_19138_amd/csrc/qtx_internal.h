@@ -139,6 +139,11 @@ hipError_t launch_transcomb(const FlatLaunch& l, hipStream_t s);
 // bb complex elements each (one workgroup per matrix).
 hipError_t launch_update_norm(const void* x, const void* prev, double* out, long long bb,
                               int batch, hipStream_t s);
+// out[e] = (||a_e||_F + ||c_e||_F) / (||a0_e||_F + ||c0_e||_F); a0, c0 at strides
+// sa0, sc0 (0 = one shared block).
+hipError_t launch_coupling_norm(const void* a, const void* c, const void* a0, long long sa0,
+                                const void* c0, long long sc0, double* out, long long bb,
+                                int batch, hipStream_t s);
 
 // workgroups per matrix of the elementwise kernels
 __host__ __device__ inline int lincomb_chunks(int b) { return (int)(((long long)b * b + kLinChunk - 1) / kLinChunk); }

@@ -123,6 +123,8 @@ def lib():
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_int32]
     L.qtx_rgf_obc_fixed_point.restype = ctypes.c_int
+    L.qtx_rgf_obc_sancho_rubio.argtypes = L.qtx_rgf_obc_fixed_point.argtypes
+    L.qtx_rgf_obc_sancho_rubio.restype = ctypes.c_int
     L.qtx_rgf_submit.argtypes = [c_ctx, ctypes.POINTER(Problem),
                                  ctypes.POINTER(ctypes.c_uint64)]
     L.qtx_rgf_submit.restype = ctypes.c_int
@@ -140,7 +142,7 @@ def exported_symbols():
             "qtx_rgf_flops_per_energy", "qtx_rgf_kernel_stats",
             "qtx_rgf_reset_stats", "qtx_rgf_zgemm", "qtx_rgf_cgemm",
             "qtx_rgf_zinv", "qtx_rgf_submit", "qtx_rgf_poll",
-            "qtx_rgf_obc_fixed_point"]
+            "qtx_rgf_obc_fixed_point", "qtx_rgf_obc_sancho_rubio"]
 
 
 def status_string(st):
@@ -271,6 +273,14 @@ class Context:
                                            _ptr(n_prime), s_np, _ptr(x), _ptr(sigma),
                                            _ptr(update), _ptr(info), n_iter)
         return self._check(st, "qtx_rgf_obc_fixed_point")
+
+    def obc_sancho_rubio(self, b, batch, m, s_m, n, s_n, n_prime, s_np, x, sigma,
+                         coupling, info, n_steps):
+        """n_steps decimation steps, then x = m_surf^{-1}; see the C header."""
+        st = lib().qtx_rgf_obc_sancho_rubio(self._h, b, batch, _ptr(m), s_m, _ptr(n), s_n,
+                                            _ptr(n_prime), s_np, _ptr(x), _ptr(sigma),
+                                            _ptr(coupling), _ptr(info), n_steps)
+        return self._check(st, "qtx_rgf_obc_sancho_rubio")
 
 
 def make_g_problem(energies_host, H, sigma_r, sigma_l, sigma_g, XR, XL=None,

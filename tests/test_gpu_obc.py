@@ -182,3 +182,107 @@ def test_full_size_sampled_energies(ctx):
         assert float(block_rel_err(x[e][None], rx[None])[0]) < TOL
         assert float(block_rel_err(sig[e][None], rs[None])[0]) < TOL
         assert abs(upd[e] - ru) <= 1e-8 * ru + 1e-12
+
+
+# ----------------------------------------------------- Sancho-Rubio decimation
+
+def _run_sr(ctx, m, n, np_, steps, shared=True):
+    ne, b = m.shape[0], m.shape[1]
+    dm, dn, dnp = G.dev(m), G.dev(n), G.dev(np_)
+    x = G.empty((ne, b, b))
+    sig = G.empty((ne, b, b))
+    cpl = torch.empty(ne, dtype=torch.float64, device=G.DEV)
+    info = torch.full((ne,), 77, dtype=torch.int32, device=G.DEV)
+    s_n = 0 if shared else b * b
+    torch.cuda.synchronize()
+    ctx.obc_sancho_rubio(b, ne, dm, b * b, dn, s_n, dnp, s_n, x, sig, cpl, info, steps)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), sig.cpu().numpy(), cpl.cpu().numpy(), info.cpu().numpy()
+
+
+def _check_sr(m, n, np_, steps, got, shared=True, skip=()):
+    from oracle import obc_sancho_rubio_steps
+    x, sig, cpl, info = got
+    for e in range(m.shape[0]):
+        if e in skip:
+            continue
+        ne_ = n if shared else n[e]
+        np_e = np_ if shared else np_[e]
+        rx, rs, rc = obc_sancho_rubio_steps(m[e], ne_, np_e, steps)
+        assert info[e] == 0, (e, info[e])
+        assert float(block_rel_err(x[e][None], rx[None])[0]) < TOL, e
+        assert float(block_rel_err(sig[e][None], rs[None])[0]) < TOL, e
+        assert abs(cpl[e] - rc) <= 1e-8 * rc + 1e-14, (e, cpl[e], rc)
+
+
+@pytest.mark.parametrize("b,ne,steps", [(32, 4, 6), (100, 3, 5), (1, 5, 8),
+                                        (65, 2, 4), (256, 2, 3)])
+def test_decimation_matches_oracle(ctx, b, ne, steps):
+    E = np.linspace(-1.5, 1.5, ne)
+    m, n, np_ = synth.lead_blocks(300 + b, b, E, eta=0.05)
+    got = _run_sr(ctx, m, n, np_, steps)
+    _check_sr(m, n, np_, steps, got)
+
+
+def test_decimation_per_energy_non_hermitian_couplings(ctx):
+    rng = np.random.default_rng(31)
+    b, ne = 40, 3
+    m = np.stack([(0.3 + 0.4j) * np.eye(b) + synth.cn(rng, (b, b), 0.1 / b)
+                  for _ in range(ne)])
+    n = synth.cn(rng, (ne, b, b), 0.2 / b)
+    np_ = synth.cn(rng, (ne, b, b), 0.2 / b)
+    got = _run_sr(ctx, m, n, np_, 5, shared=False)
+    _check_sr(m, n, np_, 5, got, shared=False)
+
+
+def test_decimation_converges_to_the_fixed_point_solution(ctx):
+    """Enough steps give the converged surface function: it agrees with the
+    oracle's converged decimation and solves the defining equation."""
+    b, ne = 24, 3
+    E = np.array([-1.2, 0.0, 0.8])
+    m, n, np_ = synth.lead_blocks(17, b, E, eta=0.05)
+    x, sig, cpl, info = _run_sr(ctx, m, n, np_, 40)
+    for e in range(ne):
+        xs, _, _ = obc_sancho_rubio(m[e], n, np_)
+        assert info[e] == 0 and cpl[e] < 1e-14
+        assert float(block_rel_err(x[e][None], xs[None])[0]) < TOL
+        r = np.linalg.inv(m[e] - n @ x[e] @ np_)
+        assert np.linalg.norm(x[e] - r) / np.linalg.norm(r) < 1e-12
+
+
+def test_decimation_singular_energy_is_flagged_and_isolated(ctx):
+    b, ne = 24, 3
+    E = np.array([-0.5, 0.0, 0.5])
+    m, n, np_ = synth.lead_blocks(8, b, E, eta=0.05)
+    m[1] = 0.0                                   # m_bulk = 0 at the first step
+    got = _run_sr(ctx, m, n, np_, 4)
+    assert got[3][1] == 1
+    _check_sr(m, n, np_, 4, got, skip=(1,))
+
+
+def test_decimation_invalid_arguments(ctx):
+    b = 8
+    m = G.empty((1, b, b))
+    x = G.empty((1, b, b))
+    info = torch.zeros(1, dtype=torch.int32, device=G.DEV)
+    for args in [(b, 1, m, 0, m, 0, m, 0, x, None, None, info, 0),
+                 (b, 1, m, 0, m, 3, m, 0, x, None, None, info, 1),
+                 (b, -1, m, 0, m, 0, m, 0, x, None, None, info, 1),
+                 (b, 1, m, 0, m, 0, m, 0, None, None, None, info, 1)]:
+        with pytest.raises(Q.QtxError) as ei:
+            ctx.obc_sancho_rubio(*args)
+        assert ei.value.status == Q.QTX_ERR_INVALID_ARG
+
+
+def test_decimation_full_size_sampled_energies(ctx):
+    b, ne, steps = 512, 16, 5
+    E = np.linspace(-2.0, 2.0, ne)
+    m, n, np_ = synth.lead_blocks(2025, b, E, eta=0.05)
+    x, sig, cpl, info = _run_sr(ctx, m, n, np_, steps)
+    assert np.all(info == 0) and np.all(np.isfinite(cpl))
+    from oracle import obc_sancho_rubio_steps
+    for e in (0, ne // 2):
+        rx, rs, rc = obc_sancho_rubio_steps(m[e], n, np_, steps)
+        assert float(block_rel_err(x[e][None], rx[None])[0]) < TOL
+        assert float(block_rel_err(sig[e][None], rs[None])[0]) < TOL
+        assert abs(cpl[e] - rc) <= 1e-8 * rc + 1e-14

@@ -129,3 +129,20 @@ def test_fixed_point_first_iteration_and_update_definition():
     assert upd2 == pytest.approx(np.linalg.norm(x2 - x1) / np.linalg.norm(x2), rel=1e-12)
     with pytest.raises(ValueError):
         obc_fixed_point(m[0], n, np_, x0, 0)
+
+
+def test_fixed_step_decimation_agrees_with_converged_run():
+    from oracle import obc_sancho_rubio_steps
+    m, n, np_ = synth.lead_blocks(14, 10, [0.3], eta=0.05)
+    xs, sig_s, k = obc_sancho_rubio(m[0], n, np_)
+    x, sig, rest = obc_sancho_rubio_steps(m[0], n, np_, k + 3)
+    assert _rel(x, xs) < 1e-13 and _rel(sig, sig_s) < 1e-13 and rest < 1e-15
+    # one step: m_surf = m - n m^-1 n'
+    x1, _, rest1 = obc_sancho_rubio_steps(m[0], n, np_, 1)
+    g = np.linalg.inv(m[0])
+    assert _rel(x1, np.linalg.inv(m[0] - n @ g @ np_)) < 1e-13
+    a1, c1 = -(n @ g @ n), -(np_ @ g @ np_)
+    assert rest1 == pytest.approx((np.linalg.norm(a1) + np.linalg.norm(c1))
+                                  / (np.linalg.norm(n) + np.linalg.norm(np_)), rel=1e-12)
+    with pytest.raises(ValueError):
+        obc_sancho_rubio_steps(m[0], n, np_, 0)
