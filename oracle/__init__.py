@@ -20,7 +20,8 @@ paper (arXiv 2508.19138, "QuaTrEx"):
                  continuants (independent pin for block size 1).
 * ``obc``      - the lead surface function of Sec. "Retarded OBC": the
                  fixed-point iteration of Eq. (naive) and Sancho-Rubio
-                 decimation, and the boundary block n x n'.
+                 decimation, the boundary block n x n', and the
+                 lesser/greater blocks by fluctuation-dissipation.
 * ``flops``    - the canonical flop model used to price a solve.
 
 All arithmetic is complex128 (IEEE binary64), the paper's precision.
@@ -32,12 +33,13 @@ from .assembly import assemble_g, assemble_w, w_retarded_diag
 from .chain import chain_closed_form, chain_lead_self_energy
 from .tridiag import tridiag_inverse_selected
 from .flops import rgf_flops, w_assembly_flops
-from .obc import obc_fixed_point, obc_sancho_rubio, obc_sancho_rubio_steps
+from .obc import (obc_fixed_point, obc_sancho_rubio, obc_sancho_rubio_steps,
+                  obc_lesser_greater)
 
 __all__ = [
     "rgf_selected", "rgf_selected_batch", "dense_from_bt", "dense_selected",
     "assemble_g", "assemble_w", "w_retarded_diag", "chain_closed_form",
     "chain_lead_self_energy", "tridiag_inverse_selected", "rgf_flops",
     "w_assembly_flops", "obc_fixed_point", "obc_sancho_rubio",
-    "obc_sancho_rubio_steps",
+    "obc_sancho_rubio_steps", "obc_lesser_greater",
 ]

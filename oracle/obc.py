@@ -27,6 +27,8 @@ n x n' (same section).
       m_bulk_new = m_bulk - n g n' - n' g n,
       m_surf_new = m_surf - n g n'          (the surface has no layer -1).
   The couplings shrink geometrically; once they vanish, x = m_surf^{-1}.
+* ``obc_lesser_greater`` - Sec. "Lesser/Greater OBC" for electrons: the
+  lesser/greater blocks from the retarded one by fluctuation-dissipation.
 
 All arithmetic is complex128 on the host; inverses are LAPACK via NumPy.
 Parity pins: tests/test_oracle_obc.py.
@@ -105,3 +107,14 @@ def obc_sancho_rubio_steps(m, n, np_, steps):
         raise ValueError("steps must be >= 1")
     x, sig, _, rest = _decimate(m, n, np_, steps, 0.0)
     return x, sig, rest
+
+
+def obc_lesser_greater(sigma_r, f, one_minus_f):
+    """Lesser/greater boundary blocks of a contact in equilibrium (Sec.
+    "Lesser/Greater OBC"): by the fluctuation-dissipation theorem, with the
+    broadening Gamma = i (Sigma^R - Sigma^R^dagger) of the retarded block,
+        Sigma^< = i f Gamma,     Sigma^> = -i (1 - f) Gamma,
+    f the contact's occupation at this energy (1 - f passed separately so
+    that neither rounds to zero).  Returns (Sigma^<, Sigma^>)."""
+    gamma = 1j * (sigma_r - sigma_r.conj().T)
+    return 1j * f * gamma, -1j * one_minus_f * gamma

@@ -146,3 +146,62 @@ def test_fixed_step_decimation_agrees_with_converged_run():
                                   / (np.linalg.norm(n) + np.linalg.norm(np_)), rel=1e-12)
     with pytest.raises(ValueError):
         obc_sancho_rubio_steps(m[0], n, np_, 0)
+
+
+# ------------------------------------------------- lesser/greater boundary blocks
+
+def _chain_setup(b=5, t=1.0, seed=19):
+    rng = np.random.default_rng(seed)
+    X = synth.cn(rng, (b, b), 1.0 / b)
+    return 0.5 * (X + X.conj().T), t
+
+
+@pytest.mark.parametrize("E", [-0.9, 0.35])
+def test_lesser_greater_in_the_chain_eigenbasis(E):
+    """Each scalar channel k of the uniform chain has broadening
+    -2 Im(t lambda_k); the matrix form must agree with it channel by channel."""
+    from oracle import obc_lesser_greater
+    h0, t = _chain_setup()
+    sig = chain_lead_self_energy(E, h0, t)
+    f = float(synth.fermi(np.array([E]))[0])
+    omf = float(synth.one_minus_fermi(np.array([E]))[0])
+    sl, sg = obc_lesser_greater(sig, f, omf)
+    eps, U = np.linalg.eigh(h0)
+    d = np.diag(U.conj().T @ sig @ U)
+    gam = -2.0 * np.imag(d)
+    assert _rel(sl, (U * (1j * f * gam)) @ U.conj().T) < 1e-13
+    assert _rel(sg, (U * (-1j * omf * gam)) @ U.conj().T) < 1e-13
+    assert _rel(sg - sl, sig - sig.conj().T) < 1e-13
+    assert _rel(sl, -sl.conj().T) < 1e-15 and _rel(sg, -sg.conj().T) < 1e-15
+
+
+def test_equilibrium_device_with_lesser_boundary_blocks():
+    """A chain device closed by its exact leads, both at occupation f: the
+    lesser function from the (pinned) recursion equals the closed form and
+    the equilibrium relation G^< = -f (G^R - G^A)."""
+    from oracle import obc_lesser_greater, rgf_selected, chain_closed_form
+    h0, t = _chain_setup(b=4, seed=23)
+    n, E = 6, 0.2
+    b = h0.shape[0]
+    sig = chain_lead_self_energy(E, h0, t)
+    f = float(synth.fermi(np.array([E]))[0])
+    omf = float(synth.one_minus_fermi(np.array([E]))[0])
+    sl, sg = obc_lesser_greater(sig, f, omf)
+    I = np.eye(b)
+    d = np.stack([E * I - h0] * n)
+    d[0] -= sig
+    d[-1] -= sig
+    u = np.stack([-t * I] * (n - 1)).astype(np.complex128)
+    A = (d.astype(np.complex128), u, u.copy())
+    z = np.zeros((n - 1, b, b), np.complex128)
+    bl = np.zeros((n, b, b), np.complex128)
+    bl[0] = sl
+    bl[-1] = sl
+    XR, XS = rgf_selected(A, [(bl, z, z)])
+    XL = XS[0]
+    (CR, CL) = chain_closed_form(E, h0, t, n, f, f)
+    for k in range(3):
+        assert _rel(XR[k], CR[k]) < 1e-12
+        assert _rel(XL[k], CL[k]) < 1e-12
+    gl_eq = -f * (XR[0] - np.conj(np.swapaxes(XR[0], 1, 2)))
+    assert _rel(XL[0], gl_eq) < 1e-12
