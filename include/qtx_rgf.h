@@ -336,6 +336,25 @@ qtx_status qtx_rgf_obc_sancho_rubio(qtx_rgf_ctx* ctx, int32_t b, int32_t batch,
                                     double* coupling, int32_t* info,
                                     int32_t n_steps);
 
+/* Lesser/greater boundary blocks of a contact in equilibrium (Sec.
+ * "Lesser/Greater OBC", electrons): by the fluctuation-dissipation theorem,
+ * with Gamma = i (Sigma^R - Sigma^R^dagger),
+ *     Sigma^< = i f Gamma,     Sigma^> = -i (1 - f) Gamma.
+ *   sigma_r           device, block of energy e at sigma_r + e * s_sr
+ *                     (s_sr = 0 shares one block, else s_sr >= b*b): the
+ *                     retarded boundary block n x n'.
+ *   f, one_minus_f    HOST double[batch]: the contact's occupation at each
+ *                     energy and its complement, both evaluated by the
+ *                     caller (so that neither rounds to zero).
+ *   sigma_l, sigma_g  [batch][b][b] device outputs; either may be NULL, not
+ *                     both.  Outputs must not overlap sigma_r.
+ * 1 <= b <= 1024, batch >= 0; returns when written.  Errors:
+ * QTX_ERR_INVALID_ARG, QTX_ERR_BUSY, QTX_ERR_HIP. */
+qtx_status qtx_rgf_obc_lesser_greater(qtx_rgf_ctx* ctx, int32_t b, int32_t batch,
+                                      const void* sigma_r, int64_t s_sr,
+                                      const double* f, const double* one_minus_f,
+                                      void* sigma_l, void* sigma_g);
+
 #ifdef __cplusplus
 }
 #endif

@@ -745,4 +745,61 @@ qtx_status qtx_rgf_obc_sancho_rubio(qtx_rgf_ctx* c, int32_t b, int32_t batch, co
   return QTX_OK;
 }
 
+// D_e = z_e Sigma^R_e + g_e (Sigma^R_e)^dagger with per-energy coefficients:
+// one adjoint-combination descriptor per energy, merged into few launches.
+qtx_status qtx_rgf_obc_lesser_greater(qtx_rgf_ctx* c, int32_t b, int32_t batch,
+                                      const void* sigma_r, int64_t s_sr, const double* f,
+                                      const double* one_minus_f, void* sigma_l,
+                                      void* sigma_g) {
+  if (!c || b < 1 || b > 1024 || batch < 0 || !sigma_r || (!sigma_l && !sigma_g))
+    return QTX_ERR_INVALID_ARG;
+  if ((sigma_l && !f) || (sigma_g && !one_minus_f)) return QTX_ERR_INVALID_ARG;
+  const long long bb = (long long)b * b;
+  if (s_sr != 0 && s_sr < bb) return QTX_ERR_INVALID_ARG;
+  if (c->busy) return QTX_ERR_BUSY;
+  if (batch == 0) return QTX_OK;
+  BusyGuard g(c);
+  c->err.clear();
+  try {
+    HIPCHK(c, hipSetDevice(c->device));
+    Lane L;
+    constexpr int kPerOp = 1024;              // descriptors per merged launch
+    auto add = [&](void* out, const double* occ, double sign) {
+      if (!out) return;
+      for (int e0 = 0; e0 < batch; e0 += kPerOp) {
+        const int cnt = std::min(kPerOp, batch - e0);
+        Op o;
+        o.k = OpK::Trans;
+        o.first = (int)L.td.size();
+        o.count = cnt;
+        for (int e = e0; e < e0 + cnt; ++e) {
+          // Sigma^< = -f (S - S^dag), Sigma^> = (1 - f)(S - S^dag)
+          const double w = sign * occ[e];
+          TransDesc t{};
+          t.C = nullptr;
+          t.Z = (const double2*)sigma_r + (long long)e * s_sr;
+          t.D = (double2*)out + (long long)e * bb;
+          t.sC = 0; t.sZ = bb; t.sD = bb;
+          t.a = zc{0.0, 0.0};
+          t.z = zc{w, 0.0};
+          t.g = zc{-w, 0.0};
+          t.b = b; t.batch = 1;
+          L.td.push_back(t);
+        }
+        o.bytes = 32.0 * (double)bb * cnt;
+        L.ops.push_back(o);
+      }
+    };
+    add(sigma_l, f, -1.0);
+    add(sigma_g, one_minus_f, 1.0);
+    std::vector<Lane*> lp{&L};
+    run_lanes_to_end(c, lp);
+    c->pool->exe(0).sync_and_collect(c->stats);
+  } catch (const Fail& fl) {
+    if (c->err.empty()) c->err = fl.what;
+    return (qtx_status)fl.st;
+  }
+  return QTX_OK;
+}
+
 }  // extern "C"

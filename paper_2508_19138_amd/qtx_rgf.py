@@ -9,6 +9,8 @@ loudly if the library has not been built.
 import ctypes
 import os
 
+import numpy as np
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # QTX_RGF_LIB selects another build of the library (e.g. a tuning variant)
 LIB_PATH = os.environ.get("QTX_RGF_LIB") or os.path.join(_HERE, "libqtx_rgf.so")
@@ -125,6 +127,10 @@ def lib():
     L.qtx_rgf_obc_fixed_point.restype = ctypes.c_int
     L.qtx_rgf_obc_sancho_rubio.argtypes = L.qtx_rgf_obc_fixed_point.argtypes
     L.qtx_rgf_obc_sancho_rubio.restype = ctypes.c_int
+    L.qtx_rgf_obc_lesser_greater.argtypes = [
+        c_ctx, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.qtx_rgf_obc_lesser_greater.restype = ctypes.c_int
     L.qtx_rgf_submit.argtypes = [c_ctx, ctypes.POINTER(Problem),
                                  ctypes.POINTER(ctypes.c_uint64)]
     L.qtx_rgf_submit.restype = ctypes.c_int
@@ -142,7 +148,8 @@ def exported_symbols():
             "qtx_rgf_flops_per_energy", "qtx_rgf_kernel_stats",
             "qtx_rgf_reset_stats", "qtx_rgf_zgemm", "qtx_rgf_cgemm",
             "qtx_rgf_zinv", "qtx_rgf_submit", "qtx_rgf_poll",
-            "qtx_rgf_obc_fixed_point", "qtx_rgf_obc_sancho_rubio"]
+            "qtx_rgf_obc_fixed_point", "qtx_rgf_obc_sancho_rubio",
+            "qtx_rgf_obc_lesser_greater"]
 
 
 def status_string(st):
@@ -281,6 +288,16 @@ class Context:
                                             _ptr(n_prime), s_np, _ptr(x), _ptr(sigma),
                                             _ptr(coupling), _ptr(info), n_steps)
         return self._check(st, "qtx_rgf_obc_sancho_rubio")
+
+    def obc_lesser_greater(self, b, batch, sigma_r, s_sr, f, one_minus_f, sigma_l, sigma_g):
+        """Sigma^< = i f Gamma, Sigma^> = -i (1-f) Gamma; f, one_minus_f are host
+        float64 numpy arrays of length batch (kept alive by the caller)."""
+        fp = None if f is None else np.ascontiguousarray(f, dtype=np.float64)
+        gp = None if one_minus_f is None else np.ascontiguousarray(one_minus_f, dtype=np.float64)
+        dp = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+        st = lib().qtx_rgf_obc_lesser_greater(self._h, b, batch, _ptr(sigma_r), s_sr, dp(fp),
+                                              dp(gp), _ptr(sigma_l), _ptr(sigma_g))
+        return self._check(st, "qtx_rgf_obc_lesser_greater")
 
 
 def make_g_problem(energies_host, H, sigma_r, sigma_l, sigma_g, XR, XL=None,

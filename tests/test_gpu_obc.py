@@ -286,3 +286,85 @@ def test_decimation_full_size_sampled_energies(ctx):
         assert float(block_rel_err(x[e][None], rx[None])[0]) < TOL
         assert float(block_rel_err(sig[e][None], rs[None])[0]) < TOL
         assert abs(cpl[e] - rc) <= 1e-8 * rc + 1e-14
+
+
+# ------------------------------------------------- lesser/greater boundary blocks
+
+def _lg(ctx, sr, f, omf, shared=False, want=("L", "G")):
+    ne = len(f)
+    b = sr.shape[-1]
+    dsr = G.dev(sr)
+    sl = G.empty((ne, b, b)) if "L" in want else None
+    sg = G.empty((ne, b, b)) if "G" in want else None
+    torch.cuda.synchronize()
+    ctx.obc_lesser_greater(b, ne, dsr, 0 if shared else b * b, f, omf, sl, sg)
+    torch.cuda.synchronize()
+    return (None if sl is None else sl.cpu().numpy(), None if sg is None else sg.cpu().numpy())
+
+
+@pytest.mark.parametrize("b,ne", [(1, 5), (33, 4), (100, 3), (4, 1500)])
+def test_lesser_greater_matches_oracle(ctx, b, ne):
+    from oracle import obc_lesser_greater
+    rng = np.random.default_rng(40 + b)
+    sr = synth.cn(rng, (ne, b, b), 1.0 / b)
+    E = np.linspace(-1.0, 1.0, ne)
+    f, omf = synth.fermi(E), synth.one_minus_fermi(E)
+    sl, sg = _lg(ctx, sr, f, omf)
+    for e in range(ne):
+        rl, rg = obc_lesser_greater(sr[e], f[e], omf[e])
+        assert float(block_rel_err(sl[e][None], rl[None])[0]) < 1e-13, e
+        assert float(block_rel_err(sg[e][None], rg[None])[0]) < 1e-13, e
+
+
+def test_lesser_greater_shared_block_and_single_output(ctx):
+    from oracle import obc_lesser_greater
+    rng = np.random.default_rng(5)
+    b, ne = 20, 3
+    sr = synth.cn(rng, (1, b, b), 1.0 / b)
+    E = np.array([-0.3, 0.0, 0.3])
+    f, omf = synth.fermi(E), synth.one_minus_fermi(E)
+    sl, _ = _lg(ctx, sr, f, omf, shared=True, want=("L",))
+    _, sg = _lg(ctx, sr, f, omf, shared=True, want=("G",))
+    for e in range(ne):
+        rl, rg = obc_lesser_greater(sr[0], f[e], omf[e])
+        assert float(block_rel_err(sl[e][None], rl[None])[0]) < 1e-13
+        assert float(block_rel_err(sg[e][None], rg[None])[0]) < 1e-13
+
+
+def test_chain_boundary_blocks_end_to_end(ctx):
+    """Decimation, then fluctuation-dissipation, both on the device, for the
+    uniform chain: each scalar channel's broadening is -2 Im(t lambda_k)."""
+    b, t, E = 6, 1.0, np.array([-0.7, 0.25])
+    rng = np.random.default_rng(29)
+    X = synth.cn(rng, (b, b), 1.0 / b)
+    h0 = 0.5 * (X + X.conj().T)
+    eta = 1e-3
+    m = (E[:, None, None] + 1j * eta) * np.eye(b)[None] - h0[None]
+    n = -t * np.eye(b, dtype=np.complex128)
+    _, sig, cpl, info = _run_sr(ctx, m, n, n, 40)
+    assert np.all(info == 0)
+    f, omf = synth.fermi(E), synth.one_minus_fermi(E)
+    sl, sg = _lg(ctx, sig, f, omf)
+    eps, U = np.linalg.eigh(h0)
+    for e in range(2):
+        w = (E[e] + 1j * eta - eps) / t
+        r = np.sqrt(w ** 2 - 4.0)
+        lam = np.where(np.abs((w + r) / 2) < 1, (w + r) / 2, (w - r) / 2)
+        gam = -2.0 * np.imag(t * lam)
+        want_l = (U * (1j * f[e] * gam)) @ U.conj().T
+        want_g = (U * (-1j * omf[e] * gam)) @ U.conj().T
+        assert np.linalg.norm(sl[e] - want_l) / np.linalg.norm(want_l) < 1e-9
+        assert np.linalg.norm(sg[e] - want_g) / np.linalg.norm(want_g) < 1e-9
+
+
+def test_lesser_greater_invalid_arguments(ctx):
+    b = 4
+    s = G.empty((1, b, b))
+    f = np.array([0.5])
+    for args in [(b, 1, s, 0, f, f, None, None),
+                 (b, 1, s, 3, f, f, s, None),
+                 (b, 1, s, 0, None, f, s, None),
+                 (0, 1, s, 0, f, f, s, None)]:
+        with pytest.raises(Q.QtxError) as ei:
+            ctx.obc_lesser_greater(*args)
+        assert ei.value.status == Q.QTX_ERR_INVALID_ARG
