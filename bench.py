@@ -849,6 +849,18 @@ def run_obc(args):
         kt = None if args.no_profile else {
             k: round(ctx.kernel_stats(k)["ms"] / args.steps, 2)
             for k in ("zgemm", "inverse", "elementwise")}
+        # lesser/greater boundary blocks from n x n' (HBM-bound); algorithmic
+        # bytes: read the retarded block once, write the two outputs
+        f_h, omf_h = synth.fermi(E), synth.one_minus_fermi(E)
+        sl, sg = torch.empty_like(sig), torch.empty_like(sig)
+        ctx.obc_lesser_greater(b, ne, sig, b * b, f_h, omf_h, sl, sg)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.obc_lesser_greater(b, ne, sig, b * b, f_h, omf_h, sl, sg)
+        torch.cuda.synchronize()
+        lg_s = (time.perf_counter() - t2) / args.steps
+        lg_bytes = 3.0 * 16.0 * b * b * ne
     assert int(info.max().item()) == 0 and int(info.min().item()) == 0
     upd_h = upd.cpu().numpy()
     cpu = None
@@ -889,6 +901,11 @@ def run_obc(args):
         ("remaining_coupling_median" if sancho else "last_update_median"):
             float(np.median(upd_h)),
         "roofline": roof, "kernel_time_ms_per_call": kt, "cpu_baseline": cpu,
+        "lesser_greater": {"ms_per_call": round(lg_s * 1e3, 3),
+                           "algorithmic_bytes": lg_bytes,
+                           "GB_per_s": round(lg_bytes / lg_s / 1e9, 1),
+                           "note": "host-timed call incl. launch; Sigma^< and Sigma^> for all "
+                                   "energies"},
     }
     print(json.dumps(out), flush=True)
 
