@@ -18,6 +18,8 @@ paper (arXiv 2508.19138, "QuaTrEx"):
                  chain with exact lead self-energies (independent pin).
 * ``tridiag``  - closed-form inverse of a scalar tridiagonal matrix via
                  continuants (independent pin for block size 1).
+* ``observables`` - local density of states, charge density and current
+                 from the selected blocks (Sec. "Observables").
 * ``obc``      - the lead surface function of Sec. "Retarded OBC": the
                  fixed-point iteration of Eq. (naive) and Sancho-Rubio
                  decimation, the boundary block n x n', and the
@@ -35,11 +37,12 @@ from .tridiag import tridiag_inverse_selected
 from .flops import rgf_flops, w_assembly_flops
 from .obc import (obc_fixed_point, obc_sancho_rubio, obc_sancho_rubio_steps,
                   obc_lesser_greater)
+from .observables import observables
 
 __all__ = [
     "rgf_selected", "rgf_selected_batch", "dense_from_bt", "dense_selected",
     "assemble_g", "assemble_w", "w_retarded_diag", "chain_closed_form",
     "chain_lead_self_energy", "tridiag_inverse_selected", "rgf_flops",
     "w_assembly_flops", "obc_fixed_point", "obc_sancho_rubio",
-    "obc_sancho_rubio_steps", "obc_lesser_greater",
+    "obc_sancho_rubio_steps", "obc_lesser_greater", "observables",
 ]
