@@ -57,7 +57,8 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--mode", default="plain",
-                    choices=["plain", "mixed", "uneven", "serve", "gemm", "obc"])
+                    choices=["plain", "mixed", "uneven", "serve", "gemm", "obc",
+                             "observables"])
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-blocks", type=int, default=32)
@@ -910,6 +911,49 @@ def run_obc(args):
     print(json.dumps(out), flush=True)
 
 
+def run_observables(args):
+    """Density of states, density and current per block from G^</G^> of the
+    device-size shape (random contents: the reduction does not depend on
+    them).  HBM-bound: reports GB/s on algorithmic bytes."""
+    import torch
+    from paper_2508_19138_amd import qtx_rgf as Q
+    n, b, ne = args.n_blocks, args.block_size, min(args.energies, 64)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(args.seed)
+    mk = lambda *sh: torch.randn(sh, dtype=torch.complex128, device="cuda:0", generator=g)
+    gl_d, gg_d, gl_l, hu = mk(ne, n, b, b), mk(ne, n, b, b), mk(ne, n - 1, b, b), mk(n - 1, b, b)
+    dos = torch.empty((ne, n), dtype=torch.float64, device="cuda:0")
+    dens = torch.empty_like(dos)
+    cur = torch.empty((ne, n - 1), dtype=torch.float64, device="cuda:0")
+    with Q.Context(0) as ctx:
+        torch.cuda.synchronize()
+        for _ in range(max(1, args.warmup)):
+            ctx.observables(n, b, ne, gl_d, gg_d, gl_l, hu, dos, dens, cur)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.observables(n, b, ne, gl_d, gg_d, gl_l, hu, dos, dens, cur)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+    # per energy: the diagonals of G^<_ii and G^>_ii, every G^<_{i+1,i};
+    # per call: H_{i,i+1} read and its adjoint written once
+    by = ne * (2.0 * n * b * 16 + (n - 1) * b * b * 16.0) + 2.0 * (n - 1) * b * b * 16
+    out = {"mode": "observables",
+           "metric": "observables energy-points/s + HBM GB/s",
+           "value": round(ne / dt, 2), "unit": "energy-points/s", "n_gpus": 1,
+           "steps": args.steps, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "density of states, density (n blocks) and current (n-1 "
+                                  "interfaces) per energy from G^</G^> blocks, %d blocks of "
+                                  "%d, %d energies" % (n, b, ne), "n_blocks": n,
+                      "block_size": b, "n_energies": ne},
+           "roofline": {"bound": "hbm", "achieved": round(by / dt / 1e9, 1), "peak": 8000.0,
+                        "unit": "GB/s", "frac": round(by / dt / 1e9 / 8000.0, 4),
+                        "traffic": None, "algorithmic_bytes_per_call": by,
+                        "note": "host-timed call (adjoint of H, then one reduction launch)"}}
+    print(json.dumps(out), flush=True)
+
+
 def run_gemm(args):
     """Product kernel alone; HIP-event time per launch and algorithmic bytes."""
     import torch
@@ -964,6 +1008,8 @@ def main():
         run_gemm(args)
     elif args.mode == "obc":
         run_obc(args)
+    elif args.mode == "observables":
+        run_observables(args)
     else:
         run_serve(args)
 

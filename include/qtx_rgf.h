@@ -355,6 +355,32 @@ qtx_status qtx_rgf_obc_lesser_greater(qtx_rgf_ctx* ctx, int32_t b, int32_t batch
                                       const double* f, const double* one_minus_f,
                                       void* sigma_l, void* sigma_g);
 
+/* Observables from the selected blocks (Sec. "Observables": local density of
+ * states, charge density and current follow from the diagonal and first
+ * off-diagonal blocks of G^< and G^>).  Per energy e and block i, in units
+ * e = hbar = 1, one spin, per unit energy:
+ *     dos[e][i]     = Tr(i (G^>_ii - G^<_ii)) / (2 pi)
+ *     density[e][i] = Tr(-i G^<_ii) / (2 pi)
+ *     current[e][i] = 2 Re Tr(H_{i,i+1} G^<_{i+1,i}) / (2 pi),  i < n-1,
+ *                     through the interface between blocks i and i+1,
+ *                     positive from i to i+1.
+ *   XL_diag, XG_diag  [batch][n][b][b] device: diagonal blocks of G^<, G^>
+ *                     (the X^<, X^> outputs of a G-type solve).
+ *   XL_lower          [batch][n-1][b][b] device: G^<_{i+1,i}.
+ *   H_upper           [n-1][b][b] device: H_{i,i+1} (energy independent).
+ *   dos, density      device double[batch][n] or NULL; current device
+ *                     double[batch][n-1] or NULL (then XL_lower and H_upper
+ *                     may be NULL).  XG_diag may be NULL if dos is.
+ * Integration over energy is left to the caller.  1 <= b <= 1024, n >= 1,
+ * batch >= 0; returns when written.  Scratch of (n-1) b*b complex128 per
+ * call.  Errors: QTX_ERR_INVALID_ARG, QTX_ERR_NOMEM, QTX_ERR_BUSY,
+ * QTX_ERR_HIP. */
+qtx_status qtx_rgf_observables(qtx_rgf_ctx* ctx, int32_t n_blocks, int32_t b,
+                               int32_t batch, const void* XL_diag,
+                               const void* XG_diag, const void* XL_lower,
+                               const void* H_upper, double* dos,
+                               double* density, double* current);
+
 #ifdef __cplusplus
 }
 #endif

@@ -802,4 +802,66 @@ qtx_status qtx_rgf_obc_lesser_greater(qtx_rgf_ctx* c, int32_t b, int32_t batch,
   return QTX_OK;
 }
 
+// Observables: H_{i,i+1}^dagger for every interface once (adjoint kernel),
+// then one reduction launch over (energy, block or interface).
+qtx_status qtx_rgf_observables(qtx_rgf_ctx* c, int32_t n_blocks, int32_t b, int32_t batch,
+                               const void* XL_diag, const void* XG_diag, const void* XL_lower,
+                               const void* H_upper, double* dos, double* density,
+                               double* current) {
+  if (!c || b < 1 || b > 1024 || n_blocks < 1 || batch < 0 || !XL_diag) return QTX_ERR_INVALID_ARG;
+  if (dos && !XG_diag) return QTX_ERR_INVALID_ARG;
+  const bool want_cur = current && n_blocks > 1;
+  if (want_cur && (!XL_lower || !H_upper)) return QTX_ERR_INVALID_ARG;
+  if (!dos && !density && !current) return QTX_ERR_INVALID_ARG;
+  if (c->busy) return QTX_ERR_BUSY;
+  if (batch == 0) return QTX_OK;
+  BusyGuard g(c);
+  c->err.clear();
+  void* hd = nullptr;
+  try {
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long bb = (long long)b * b;
+    const hipStream_t st = c->pool->exe(0).stream();
+    if (want_cur) {
+      if (hipMalloc(&hd, (size_t)(n_blocks - 1) * bb * 16) != hipSuccess) {
+        (void)hipGetLastError();
+        hd = nullptr;
+        c->err = "scratch allocation of the adjoint couplings failed";
+        return QTX_ERR_NOMEM;
+      }
+      Lane L;
+      TransDesc t{};
+      t.C = nullptr;
+      t.Z = H_upper;
+      t.D = hd;
+      t.sC = 0; t.sZ = bb; t.sD = bb;
+      t.a = zc{0.0, 0.0};
+      t.z = zc{0.0, 0.0};
+      t.g = zc{1.0, 0.0};                      // D = Z^dagger
+      t.b = b; t.batch = n_blocks - 1;
+      L.td.push_back(t);
+      Op o;
+      o.k = OpK::Trans;
+      o.first = 0; o.count = 1;
+      o.bytes = 32.0 * (double)bb * (n_blocks - 1);
+      L.ops.push_back(o);
+      std::vector<Lane*> lp{&L};
+      run_lanes_to_end(c, lp);
+    }
+    HIPCHK(c, launch_observables(XL_diag, XG_diag, want_cur ? XL_lower : nullptr, hd, dos,
+                                 density, want_cur ? current : nullptr, n_blocks, b, batch,
+                                 st));
+    c->pool->exe(0).sync_and_collect(c->stats);
+    if (hd) HIPCHK(c, hipFree(hd));
+  } catch (const Fail& fl) {
+    if (c->err.empty()) c->err = fl.what;
+    if (hd) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(hd);
+    }
+    return (qtx_status)fl.st;
+  }
+  return QTX_OK;
+}
+
 }  // extern "C"

@@ -194,7 +194,75 @@ void coupling_norm_kernel(const double2* __restrict__ a, const double2* __restri
   }
 }
 
+// Observables per energy e: workgroups k < n take block k's traces
+// (density of states from i(G^> - G^<), density from -i G^<, diagonal
+// elements only), workgroups k >= n the current through interface
+// i = k - n, 2 Re Tr(H_{i,i+1} G^<_{i+1,i}) = 2 sum_q Re(G[q] conj(Hd[q]))
+// with Hd = H_{i,i+1}^dagger, so both blocks are read contiguously.
+__global__ __launch_bounds__(256)
+void observables_kernel(const double2* __restrict__ gl_d, const double2* __restrict__ gg_d,
+                        const double2* __restrict__ gl_l, const double2* __restrict__ hd,
+                        double* __restrict__ dos, double* __restrict__ dens,
+                        double* __restrict__ cur, int n, int b) {
+  const int per = 2 * n - 1;
+  const long long e = blockIdx.x / per;
+  const int k = blockIdx.x % per;
+  const long long bb = (long long)b * b;
+  const int t = threadIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  if (k < n) {
+    // gg_d is null when no density of states is asked for (uniform branch)
+    const double2* L = gl_d + (e * n + k) * bb;
+    const double2* Gg = gg_d ? gg_d + (e * n + k) * bb : nullptr;
+    for (int j = t; j < b; j += 256) {
+      const double2 l = L[(long long)j * (b + 1)];
+      const double2 g = Gg ? Gg[(long long)j * (b + 1)] : make_double2(0.0, 0.0);
+      s0 += l.y - g.y;          // Re(i (g - l))
+      s1 += l.y;                // Re(-i l)
+    }
+  } else if (cur) {             // gl_l and hd are null when no current is asked for
+    const int i = k - n;
+    const double2* G = gl_l + (e * (n - 1) + i) * bb;
+    const double2* H = hd + (long long)i * bb;
+    for (long long q = t; q < bb; q += 256) {
+      const double2 g = G[q], h = H[q];
+      s0 += g.x * h.x + g.y * h.y;
+    }
+  }
+  __shared__ double r0[256], r1[256];
+  r0[t] = s0;
+  r1[t] = s1;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      r0[t] += r0[t + h];
+      r1[t] += r1[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double inv2pi = 0.15915494309189533577;   // 1 / (2 pi)
+    if (k < n) {
+      if (dos) dos[e * n + k] = r0[0] * inv2pi;
+      if (dens) dens[e * n + k] = r1[0] * inv2pi;
+    } else if (cur) {
+      cur[e * (n - 1) + (k - n)] = 2.0 * r0[0] * inv2pi;
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_observables(const void* gl_d, const void* gg_d, const void* gl_l,
+                              const void* hd, double* dos, double* dens, double* cur, int n,
+                              int b, int batch, hipStream_t s) {
+  if (batch <= 0 || n <= 0) return hipSuccess;
+  const long long grid = (long long)batch * (2 * n - 1);
+  hipLaunchKernelGGL(observables_kernel, dim3((unsigned)grid), dim3(256), 0, s,
+                     (const double2*)gl_d, (const double2*)gg_d, (const double2*)gl_l,
+                     (const double2*)hd, dos, dens, cur, n, b);
+  return hipGetLastError();
+}
 
 hipError_t launch_coupling_norm(const void* a, const void* c, const void* a0, long long sa0,
                                 const void* c0, long long sc0, double* out, long long bb,

@@ -141,6 +141,12 @@ hipError_t launch_update_norm(const void* x, const void* prev, double* out, long
                               int batch, hipStream_t s);
 // out[e] = (||a_e||_F + ||c_e||_F) / (||a0_e||_F + ||c0_e||_F); a0, c0 at strides
 // sa0, sc0 (0 = one shared block).
+// Per energy: dos[n], density[n] from the diagonal blocks of G^< / G^>,
+// current[n-1] from the lower blocks of G^< and Hd = H_{i,i+1}^dagger
+// ([n-1][b][b], shared by all energies).  Null outputs are skipped.
+hipError_t launch_observables(const void* gl_d, const void* gg_d, const void* gl_l,
+                              const void* hd, double* dos, double* dens, double* cur, int n,
+                              int b, int batch, hipStream_t s);
 hipError_t launch_coupling_norm(const void* a, const void* c, const void* a0, long long sa0,
                                 const void* c0, long long sc0, double* out, long long bb,
                                 int batch, hipStream_t s);

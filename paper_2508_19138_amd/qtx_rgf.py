@@ -131,6 +131,11 @@ def lib():
         c_ctx, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     L.qtx_rgf_obc_lesser_greater.restype = ctypes.c_int
+    L.qtx_rgf_observables.argtypes = [
+        c_ctx, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_void_p]
+    L.qtx_rgf_observables.restype = ctypes.c_int
     L.qtx_rgf_submit.argtypes = [c_ctx, ctypes.POINTER(Problem),
                                  ctypes.POINTER(ctypes.c_uint64)]
     L.qtx_rgf_submit.restype = ctypes.c_int
@@ -149,7 +154,7 @@ def exported_symbols():
             "qtx_rgf_reset_stats", "qtx_rgf_zgemm", "qtx_rgf_cgemm",
             "qtx_rgf_zinv", "qtx_rgf_submit", "qtx_rgf_poll",
             "qtx_rgf_obc_fixed_point", "qtx_rgf_obc_sancho_rubio",
-            "qtx_rgf_obc_lesser_greater"]
+            "qtx_rgf_obc_lesser_greater", "qtx_rgf_observables"]
 
 
 def status_string(st):
@@ -298,6 +303,14 @@ class Context:
         st = lib().qtx_rgf_obc_lesser_greater(self._h, b, batch, _ptr(sigma_r), s_sr, dp(fp),
                                               dp(gp), _ptr(sigma_l), _ptr(sigma_g))
         return self._check(st, "qtx_rgf_obc_lesser_greater")
+
+    def observables(self, n, b, batch, XL_diag, XG_diag, XL_lower, H_upper, dos, density,
+                    current):
+        """Density of states, density and current per block; see the C header."""
+        st = lib().qtx_rgf_observables(self._h, n, b, batch, _ptr(XL_diag), _ptr(XG_diag),
+                                       _ptr(XL_lower), _ptr(H_upper), _ptr(dos),
+                                       _ptr(density), _ptr(current))
+        return self._check(st, "qtx_rgf_observables")
 
 
 def make_g_problem(energies_host, H, sigma_r, sigma_l, sigma_g, XR, XL=None,
