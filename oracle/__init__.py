@@ -36,7 +36,7 @@ from .chain import chain_closed_form, chain_lead_self_energy
 from .tridiag import tridiag_inverse_selected
 from .flops import rgf_flops, w_assembly_flops
 from .obc import (obc_fixed_point, obc_sancho_rubio, obc_sancho_rubio_steps,
-                  obc_lesser_greater)
+                  obc_lesser_greater, obc_lyapunov_fixed_point, obc_lyapunov_doubling)
 from .observables import observables
 
 __all__ = [
@@ -45,4 +45,5 @@ __all__ = [
     "chain_lead_self_energy", "tridiag_inverse_selected", "rgf_flops",
     "w_assembly_flops", "obc_fixed_point", "obc_sancho_rubio",
     "obc_sancho_rubio_steps", "obc_lesser_greater", "observables",
+    "obc_lyapunov_fixed_point", "obc_lyapunov_doubling",
 ]

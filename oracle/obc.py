@@ -29,6 +29,9 @@ n x n' (same section).
   The couplings shrink geometrically; once they vanish, x = m_surf^{-1}.
 * ``obc_lesser_greater`` - Sec. "Lesser/Greater OBC" for electrons: the
   lesser/greater blocks from the retarded one by fluctuation-dissipation.
+* ``obc_lyapunov_fixed_point``, ``obc_lyapunov_doubling`` - the same section
+  for the screened interaction: Eq. (lyapunov), w = q - a w a^dagger, by the
+  plain iteration (memoized start) and by doubling.
 
 All arithmetic is complex128 on the host; inverses are LAPACK via NumPy.
 Parity pins: tests/test_oracle_obc.py.
@@ -118,3 +121,37 @@ def obc_lesser_greater(sigma_r, f, one_minus_f):
     that neither rounds to zero).  Returns (Sigma^<, Sigma^>)."""
     gamma = 1j * (sigma_r - sigma_r.conj().T)
     return 1j * f * gamma, -1j * one_minus_f * gamma
+
+
+def obc_lyapunov_fixed_point(a, q, w0, n_iter):
+    """Eq. (lyapunov), w = q - a w a^dagger (the W system's lesser/greater
+    surface function), by the plain iteration w_{i+1} = q - a w_i a^dagger
+    from a given start (zeros, or the previous self-consistent iteration's w
+    as in Sec. "OBC Memoization").  Returns (w_N, ||w_N - w_{N-1}||_F /
+    ||w_N||_F)."""
+    if n_iter < 1:
+        raise ValueError("n_iter must be >= 1")
+    w = np.array(w0, dtype=np.complex128)
+    prev = w
+    ah = a.conj().T
+    for _ in range(n_iter):
+        prev = w
+        w = q - a @ w @ ah
+    return w, _fro(w - prev) / max(_fro(w), np.finfo(float).tiny)
+
+
+def obc_lyapunov_doubling(a, q, steps):
+    """Eq. (lyapunov) by doubling (Smith's method): the solution is the
+    series w = sum_j (-1)^j a^j q (a^dagger)^j; with A_k = a^(2^k),
+        S_1 = q - a q a^dagger,   S_{k+1} = S_k + A_k S_k A_k^dagger  (k >= 1),
+    S_k holds the first 2^k terms.  Returns (S_steps, ||A_steps||_F / ||a||_F)."""
+    if steps < 1:
+        raise ValueError("steps must be >= 1")
+    A = np.array(a, dtype=np.complex128)
+    S = q - A @ q @ A.conj().T
+    for _ in range(1, steps):
+        A = A @ A
+        S = S + A @ S @ A.conj().T
+    A = A @ A
+    na = _fro(a)
+    return S, (_fro(A) / na if na > 0 else 0.0)

@@ -205,3 +205,63 @@ def test_equilibrium_device_with_lesser_boundary_blocks():
         assert _rel(XL[k], CL[k]) < 1e-12
     gl_eq = -f * (XR[0] - np.conj(np.swapaxes(XR[0], 1, 2)))
     assert _rel(XL[0], gl_eq) < 1e-12
+
+
+# ------------------------------------------------ Lyapunov (W lesser/greater)
+
+def _lyap_direct(a, q):
+    """Brute force: (I + conj(a) kron a) vec(w) = vec(q), column-major vec."""
+    b = a.shape[0]
+    K = np.eye(b * b) + np.kron(a.conj(), a)
+    v = np.linalg.solve(K, q.reshape(-1, order="F"))
+    return v.reshape((b, b), order="F")
+
+
+def _contraction(b, seed, rho=0.6):
+    rng = np.random.default_rng(seed)
+    a = synth.cn(rng, (b, b), 1.0)
+    a *= rho / np.max(np.abs(np.linalg.eigvals(a)))
+    q = synth.cn(rng, (b, b), 1.0)
+    return a, q
+
+
+@pytest.mark.parametrize("b", [1, 3, 7])
+def test_lyapunov_solvers_match_kronecker_solve(b):
+    from oracle import obc_lyapunov_fixed_point, obc_lyapunov_doubling
+    a, q = _contraction(b, 50 + b)
+    exact = _lyap_direct(a, q)
+    wf, upd = obc_lyapunov_fixed_point(a, q, np.zeros((b, b), np.complex128), 200)
+    assert _rel(wf, exact) < 1e-12 and upd < 1e-13
+    wd, rest = obc_lyapunov_doubling(a, q, 8)
+    assert _rel(wd, exact) < 1e-12 and rest < 1e-12
+
+
+def test_lyapunov_scalar_closed_form_and_symmetry():
+    from oracle import obc_lyapunov_doubling
+    a, q = np.array([[0.5 + 0.2j]]), np.array([[1.3 - 0.4j]])
+    wd, _ = obc_lyapunov_doubling(a, q, 10)
+    assert abs(wd[0, 0] - q[0, 0] / (1 + abs(a[0, 0]) ** 2)) < 1e-14
+    # anti-Hermitian q (a lesser/greater quantity) gives anti-Hermitian w
+    A, Q = _contraction(5, 9)
+    Q = Q - Q.conj().T
+    w, _ = obc_lyapunov_doubling(A, Q, 8)
+    assert _rel(w, -w.conj().T) < 1e-13
+
+
+def test_lyapunov_partial_sums_and_memoized_start():
+    from oracle import obc_lyapunov_fixed_point, obc_lyapunov_doubling
+    a, q = _contraction(4, 3, rho=0.9)
+    ah = a.conj().T
+    # doubling step k holds the first 2^k terms of the alternating series
+    s4 = sum((-1) ** j * np.linalg.matrix_power(a, j) @ q @ np.linalg.matrix_power(ah, j)
+             for j in range(4))
+    w2, _ = obc_lyapunov_doubling(a, q, 2)
+    assert _rel(w2, s4) < 1e-13
+    # the plain iteration from zero after N steps holds the first N terms
+    w3, _ = obc_lyapunov_fixed_point(a, q, np.zeros((4, 4), np.complex128), 3)
+    s3 = sum((-1) ** j * np.linalg.matrix_power(a, j) @ q @ np.linalg.matrix_power(ah, j)
+             for j in range(3))
+    assert _rel(w3, s3) < 1e-13
+    exact = _lyap_direct(a, q)
+    wm, upd = obc_lyapunov_fixed_point(a, q, exact, 2)
+    assert _rel(wm, exact) < 1e-13 and upd < 1e-13
