@@ -72,9 +72,11 @@ def parse():
                          "path, F_BT flop model); use --energies 96 to fit HBM")
     ap.add_argument("--obc-iters", type=int, default=20,
                     help="obc: fixed-point iterations (or decimation steps) per call")
-    ap.add_argument("--obc-method", default="fixed", choices=["fixed", "sancho"],
-                    help="obc: memoized fixed-point iterations, or Sancho-Rubio decimation "
-                         "from scratch")
+    ap.add_argument("--obc-method", default="fixed",
+                    choices=["fixed", "sancho", "lyap-fixed", "lyap-doubling"],
+                    help="obc: retarded surface function by memoized fixed-point iterations "
+                         "or Sancho-Rubio decimation; or the W system's lesser/greater "
+                         "surface function (Eq. lyapunov) by memoized iterations or doubling")
     ap.add_argument("--per-b", action="store_true",
                     help="uneven: also time the merged batch of each block size alone")
     ap.add_argument("--no-profile", action="store_true",
@@ -803,6 +805,81 @@ PAPER_CONTEXT = {
 }
 
 
+def run_lyapunov(args):
+    """w = q - a w a^dagger for all energies per call (memoized iterations
+    from the previous call's w, or doubling from scratch)."""
+    import torch
+    from paper_2508_19138_amd import qtx_rgf as Q
+    from paper_2508_19138_amd import synth
+    b, ne, it = args.block_size, args.energies, args.obc_iters
+    dbl = args.obc_method == "lyap-doubling"
+    a, q = synth.lyapunov_blocks(args.seed, b, ne)
+    da, dq = torch.from_numpy(a).to("cuda:0"), torch.from_numpy(q).to("cuda:0")
+    w = torch.zeros((ne, b, b), dtype=torch.complex128, device="cuda:0")
+    out = torch.empty(ne, dtype=torch.float64, device="cuda:0")
+    n_prod = (2 + 3 * (it - 1) + 1) if dbl else 2 * it
+    flops_call = ne * n_prod * 8.0 * b ** 3
+
+    def run(ctx):
+        if dbl:
+            ctx.obc_lyapunov_doubling(b, ne, da, b * b, dq, b * b, w, out, it)
+        else:
+            ctx.obc_lyapunov_fixed_point(b, ne, da, b * b, dq, b * b, w, out, it)
+
+    with Q.Context(0, profile=not args.no_profile) as ctx:
+        torch.cuda.synchronize()
+        for _ in range(max(1, args.warmup)):
+            run(ctx)
+        torch.cuda.synchronize()
+        ctx.reset_stats()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run(ctx)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        roof = None if args.no_profile else _gemm_roofline(
+            ctx, "zgemm", FP64_MFMA_PEAK_TFLOPS,
+            "zgemm_kernel (complex FP64, 4 real MFMA per complex product)")
+        if roof is not None:
+            roof["traffic"] = None
+    o = out.cpu().numpy()
+    cpu = None
+    if args.cpu_energies > 0:
+        from oracle import obc_lyapunov_fixed_point, obc_lyapunov_doubling
+        k = min(ne, max(args.cpu_energies, 32))
+        idx = [int(i) for i in np.linspace(0, ne - 1, k).round()]
+        t1 = time.perf_counter()
+        for e in idx:
+            if dbl:
+                obc_lyapunov_doubling(a[e], q[e], it)
+            else:
+                obc_lyapunov_fixed_point(a[e], q[e], np.zeros((b, b), np.complex128), it)
+        dc = time.perf_counter() - t1
+        cpu = {"value": len(idx) / dc, "unit": "energy-points/s",
+               "cores": os.cpu_count() or 1, "kind": "oracle",
+               "sample": "%d of the %d energies (evenly spaced), %d %s each, NumPy/OpenBLAS, "
+                         "%.1f s" % (len(idx), ne, it, "steps" if dbl else "iterations", dc)}
+    res = {
+        "mode": "obc", "metric": "W lesser/greater surface functions/s (energy-points/s) + "
+                                 "% FP64 MFMA peak",
+        "value": round(ne / dt, 3), "unit": "energy-points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Eq. lyapunov w = q - a w a^dagger by %d %s per call, b=%d, "
+                               "%d energies, a ~ CN(0, 0.64/b), q anti-Hermitian"
+                               % (it, "doubling steps (from scratch)" if dbl else
+                                  "fixed-point iterations (memoized start)", b, ne),
+                   "block_size": b, "n_energies": ne, "method": args.obc_method,
+                   "iterations": it, "seed": args.seed},
+        "tflops": round(flops_call / dt / 1e12, 3),
+        "pct_fp64_mfma_peak": round(100 * flops_call / dt / 1e12 / FP64_MFMA_PEAK_TFLOPS, 2),
+        "flops_per_call": flops_call,
+        ("remaining_max" if dbl else "last_update_max"): float(o.max()),
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def run_obc(args):
     """Lead surface function (retarded OBC) in the memoized mode: every call
     runs a fixed number of fixed-point iterations over all energies, starting
@@ -1006,6 +1083,8 @@ def main():
         run_uneven(args)
     elif args.mode == "gemm":
         run_gemm(args)
+    elif args.mode == "obc" and args.obc_method.startswith("lyap"):
+        run_lyapunov(args)
     elif args.mode == "obc":
         run_obc(args)
     elif args.mode == "observables":

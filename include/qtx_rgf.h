@@ -375,6 +375,42 @@ qtx_status qtx_rgf_obc_lesser_greater(qtx_rgf_ctx* ctx, int32_t b, int32_t batch
  * batch >= 0; returns when written.  Scratch of (n-1) b*b complex128 per
  * call.  Errors: QTX_ERR_INVALID_ARG, QTX_ERR_NOMEM, QTX_ERR_BUSY,
  * QTX_ERR_HIP. */
+/* The screened interaction's lesser/greater surface function (Sec.
+ * "Lesser/Greater OBC"): the solution w of Eq. (lyapunov),
+ *     w = q - a w a^dagger,
+ * for every energy of a batch, q and a being b x b blocks extracted from P,
+ * V and w^R by the caller.  The series sum_j (-1)^j a^j q (a^dagger)^j
+ * converges when the spectral radius of a is below 1.
+ *
+ * qtx_rgf_obc_lyapunov_fixed_point: n_iter iterations of
+ * w_{i+1} = q - a w_i a^dagger from the start held in w (zeros, or the
+ * previous self-consistent iteration's w: the memoized mode of Sec. "OBC
+ * Memoization"); update (device double[batch] or NULL) receives
+ * ||w_N - w_{N-1}||_F / ||w_N||_F.
+ *
+ * qtx_rgf_obc_lyapunov_doubling: doubling over the series, S_1 = q - a q
+ * a^dagger, then n_steps - 1 steps A <- A A, S <- S + A S A^dagger (S_k holds
+ * the first 2^k terms); w is output only; remaining (device double[batch] or
+ * NULL) receives ||a^(2^n_steps)||_F / ||a||_F, the caller's convergence
+ * test.
+ *
+ *   a, q     row-major b x b complex128 device blocks; the block of energy e
+ *            at base + e * s_* elements (0 = shared, else >= b*b).
+ *   w        [batch][b][b] device, contiguous; must not overlap a or q.
+ * 1 <= b <= 1024, batch >= 0, n_iter / n_steps >= 1.  Scratch of 2 (fixed
+ * point) or 3 (doubling) * batch * b*b complex128 per call.  Errors:
+ * QTX_ERR_INVALID_ARG, QTX_ERR_NOMEM, QTX_ERR_BUSY, QTX_ERR_HIP. */
+qtx_status qtx_rgf_obc_lyapunov_fixed_point(qtx_rgf_ctx* ctx, int32_t b,
+                                            int32_t batch, const void* a,
+                                            int64_t s_a, const void* q,
+                                            int64_t s_q, void* w,
+                                            double* update, int32_t n_iter);
+qtx_status qtx_rgf_obc_lyapunov_doubling(qtx_rgf_ctx* ctx, int32_t b,
+                                         int32_t batch, const void* a,
+                                         int64_t s_a, const void* q,
+                                         int64_t s_q, void* w,
+                                         double* remaining, int32_t n_steps);
+
 qtx_status qtx_rgf_observables(qtx_rgf_ctx* ctx, int32_t n_blocks, int32_t b,
                                int32_t batch, const void* XL_diag,
                                const void* XG_diag, const void* XL_lower,

@@ -531,9 +531,11 @@ struct LeadLane {
   static size_t inv_work(int b, int batch) {
     return (size_t)batch * b * (2 * kPanel + 2 * kSuper) * 16 + (size_t)batch * b * 8 + 4096;
   }
-  // D = alpha A B + beta C (strides in elements between energies)
+  // D = alpha op(A) op(B) + beta C (strides in elements between energies;
+  // op 'C' = adjoint)
   void gemm(const void* A, long long sA, const void* B, long long sB, const void* C,
-            long long sC, void* D, double alpha, double beta) {
+            long long sC, void* D, double alpha, double beta, char opa = 'N',
+            char opb = 'N') {
     GemmDesc d{};
     d.A = A; d.sA = sA; d.lda = b;
     d.B = B; d.sB = sB; d.ldb = b;
@@ -546,7 +548,7 @@ struct LeadLane {
     L.gd.push_back(d);
     Op o;
     o.k = OpK::Gemm;
-    o.opa = 'N'; o.opb = 'N'; o.fp32 = false;
+    o.opa = opa; o.opb = opb; o.fp32 = false;
     o.cfg = cfg;
     o.first = (int)L.gd.size() - 1; o.count = 1;
     o.flops = 8.0 * (double)bb * b * batch;
@@ -592,8 +594,8 @@ struct LeadLane {
 
 qtx_status lead_args_ok(int32_t b, int32_t batch, const void* m, int64_t s_m, const void* n,
                         int64_t s_n, const void* n_prime, int64_t s_np, const void* x,
-                        const int32_t* info, int32_t count) {
-  if (b < 1 || b > 1024 || batch < 0 || count < 1 || !m || !n || !n_prime || !x || !info)
+                        int32_t count) {
+  if (b < 1 || b > 1024 || batch < 0 || count < 1 || !m || !n || !n_prime || !x)
     return QTX_ERR_INVALID_ARG;
   const long long bb = (long long)b * b;
   auto bad_stride = [bb](int64_t st) { return st != 0 && st < bb; };
@@ -613,7 +615,8 @@ qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t batch, con
                                    int64_t s_np, void* x, void* sigma, double* update,
                                    int32_t* info, int32_t n_iter) {
   if (!c) return QTX_ERR_INVALID_ARG;
-  const qtx_status ok = lead_args_ok(b, batch, m, s_m, n, s_n, n_prime, s_np, x, info, n_iter);
+  if (!info) return QTX_ERR_INVALID_ARG;
+  const qtx_status ok = lead_args_ok(b, batch, m, s_m, n, s_n, n_prime, s_np, x, n_iter);
   if (ok != QTX_OK) return ok;
   if (c->busy) return QTX_ERR_BUSY;
   if (batch == 0) return QTX_OK;
@@ -674,7 +677,8 @@ qtx_status qtx_rgf_obc_sancho_rubio(qtx_rgf_ctx* c, int32_t b, int32_t batch, co
                                     const void* n_prime, int64_t s_np, void* x, void* sigma,
                                     double* coupling, int32_t* info, int32_t n_steps) {
   if (!c) return QTX_ERR_INVALID_ARG;
-  const qtx_status ok = lead_args_ok(b, batch, m, s_m, n, s_n, n_prime, s_np, x, info, n_steps);
+  if (!info) return QTX_ERR_INVALID_ARG;
+  const qtx_status ok = lead_args_ok(b, batch, m, s_m, n, s_n, n_prime, s_np, x, n_steps);
   if (ok != QTX_OK) return ok;
   if (c->busy) return QTX_ERR_BUSY;
   if (batch == 0) return QTX_OK;
@@ -858,6 +862,116 @@ qtx_status qtx_rgf_observables(qtx_rgf_ctx* c, int32_t n_blocks, int32_t b, int3
     if (hd) {
       (void)hipDeviceSynchronize();
       (void)hipFree(hd);
+    }
+    return (qtx_status)fl.st;
+  }
+  return QTX_OK;
+}
+
+// Eq. (lyapunov) by the plain iteration, all energies at once: two
+// products per iteration (T = w a^dagger, w' = q - a T), ping-pong buffers.
+qtx_status qtx_rgf_obc_lyapunov_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t batch,
+                                            const void* a, int64_t s_a, const void* q,
+                                            int64_t s_q, void* w, double* update,
+                                            int32_t n_iter) {
+  if (!c) return QTX_ERR_INVALID_ARG;
+  const qtx_status ok = lead_args_ok(b, batch, a, s_a, q, s_q, q, s_q, w, n_iter);
+  if (ok != QTX_OK) return ok;
+  if (c->busy) return QTX_ERR_BUSY;
+  if (batch == 0) return QTX_OK;
+  BusyGuard g(c);
+  c->err.clear();
+  char* work = nullptr;
+  try {
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long bb = (long long)b * b;
+    const size_t blk = (size_t)batch * bb * 16;
+    if (hipMalloc((void**)&work, 2 * blk) != hipSuccess) {
+      (void)hipGetLastError();
+      work = nullptr;
+      c->err = "scratch allocation of the Lyapunov iteration failed";
+      return QTX_ERR_NOMEM;
+    }
+    void* T = work;
+    void* wb = work + blk;
+    LeadLane lane(c, b, batch, nullptr);
+    void* cur = w;
+    void* nxt = wb;
+    for (int it = 0; it < n_iter; ++it) {
+      lane.gemm(cur, bb, a, s_a, nullptr, 0, T, 1.0, 0.0, 'N', 'C');   // T = w a^dagger
+      lane.gemm(a, s_a, T, bb, q, s_q, nxt, -1.0, 1.0);               // w' = q - a T
+      std::swap(cur, nxt);
+    }
+    std::vector<Lane*> lp{&lane.L};
+    run_lanes_to_end(c, lp);
+    const hipStream_t st = c->pool->exe(0).stream();
+    if (update) HIPCHK(c, launch_update_norm(cur, nxt, update, bb, batch, st));
+    if (cur != w) HIPCHK(c, hipMemcpyAsync(w, cur, blk, hipMemcpyDeviceToDevice, st));
+    c->pool->exe(0).sync_and_collect(c->stats);
+    HIPCHK(c, hipFree(work));
+  } catch (const Fail& fl) {
+    if (c->err.empty()) c->err = fl.what;
+    if (work) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(work);
+    }
+    return (qtx_status)fl.st;
+  }
+  return QTX_OK;
+}
+
+// Eq. (lyapunov) by doubling, all energies at once: S_1 = q - a q a^dagger,
+// then per step A <- A A and S <- S + A S A^dagger (three products).
+qtx_status qtx_rgf_obc_lyapunov_doubling(qtx_rgf_ctx* c, int32_t b, int32_t batch,
+                                         const void* a, int64_t s_a, const void* q,
+                                         int64_t s_q, void* w, double* remaining,
+                                         int32_t n_steps) {
+  if (!c) return QTX_ERR_INVALID_ARG;
+  const qtx_status ok = lead_args_ok(b, batch, a, s_a, q, s_q, q, s_q, w, n_steps);
+  if (ok != QTX_OK) return ok;
+  if (c->busy) return QTX_ERR_BUSY;
+  if (batch == 0) return QTX_OK;
+  BusyGuard g(c);
+  c->err.clear();
+  char* work = nullptr;
+  try {
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long bb = (long long)b * b;
+    const size_t blk = (size_t)batch * bb * 16;
+    if (hipMalloc((void**)&work, 3 * blk) != hipSuccess) {
+      (void)hipGetLastError();
+      work = nullptr;
+      c->err = "scratch allocation of the Lyapunov doubling failed";
+      return QTX_ERR_NOMEM;
+    }
+    void* T = work;
+    void* A2[2] = {work + blk, work + 2 * blk};
+    LeadLane lane(c, b, batch, nullptr);
+    lane.gemm(q, s_q, a, s_a, nullptr, 0, T, 1.0, 0.0, 'N', 'C');      // T = q a^dagger
+    lane.gemm(a, s_a, T, bb, q, s_q, w, -1.0, 1.0);                    // S = q - a T
+    const void* A = a;
+    long long sA = s_a;
+    for (int k = 1; k <= n_steps; ++k) {
+      void* An = A2[k & 1];
+      lane.gemm(A, sA, A, sA, nullptr, 0, An, 1.0, 0.0);               // A <- A A
+      A = An;
+      sA = bb;
+      if (k == n_steps) break;                 // the last square only measures
+      lane.gemm(w, bb, A, sA, nullptr, 0, T, 1.0, 0.0, 'N', 'C');      // T = S A^dagger
+      lane.gemm(A, sA, T, bb, w, bb, w, 1.0, 1.0);                     // S += A T
+    }
+    std::vector<Lane*> lp{&lane.L};
+    run_lanes_to_end(c, lp);
+    const hipStream_t st = c->pool->exe(0).stream();
+    if (remaining)
+      HIPCHK(c, launch_coupling_norm(A, A, a, s_a, a, s_a, remaining, bb, batch, st));
+    c->pool->exe(0).sync_and_collect(c->stats);
+    HIPCHK(c, hipFree(work));
+  } catch (const Fail& fl) {
+    if (c->err.empty()) c->err = fl.what;
+    if (work) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(work);
     }
     return (qtx_status)fl.st;
   }

@@ -136,6 +136,12 @@ def lib():
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_void_p]
     L.qtx_rgf_observables.restype = ctypes.c_int
+    lyap = [c_ctx, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+    L.qtx_rgf_obc_lyapunov_fixed_point.argtypes = lyap
+    L.qtx_rgf_obc_lyapunov_fixed_point.restype = ctypes.c_int
+    L.qtx_rgf_obc_lyapunov_doubling.argtypes = lyap
+    L.qtx_rgf_obc_lyapunov_doubling.restype = ctypes.c_int
     L.qtx_rgf_submit.argtypes = [c_ctx, ctypes.POINTER(Problem),
                                  ctypes.POINTER(ctypes.c_uint64)]
     L.qtx_rgf_submit.restype = ctypes.c_int
@@ -154,7 +160,8 @@ def exported_symbols():
             "qtx_rgf_reset_stats", "qtx_rgf_zgemm", "qtx_rgf_cgemm",
             "qtx_rgf_zinv", "qtx_rgf_submit", "qtx_rgf_poll",
             "qtx_rgf_obc_fixed_point", "qtx_rgf_obc_sancho_rubio",
-            "qtx_rgf_obc_lesser_greater", "qtx_rgf_observables"]
+            "qtx_rgf_obc_lesser_greater", "qtx_rgf_observables",
+            "qtx_rgf_obc_lyapunov_fixed_point", "qtx_rgf_obc_lyapunov_doubling"]
 
 
 def status_string(st):
@@ -311,6 +318,18 @@ class Context:
                                        _ptr(XL_lower), _ptr(H_upper), _ptr(dos),
                                        _ptr(density), _ptr(current))
         return self._check(st, "qtx_rgf_observables")
+
+    def obc_lyapunov_fixed_point(self, b, batch, a, s_a, q, s_q, w, update, n_iter):
+        """n_iter iterations of w <- q - a w a^dagger; see the C header."""
+        st = lib().qtx_rgf_obc_lyapunov_fixed_point(self._h, b, batch, _ptr(a), s_a, _ptr(q),
+                                                    s_q, _ptr(w), _ptr(update), n_iter)
+        return self._check(st, "qtx_rgf_obc_lyapunov_fixed_point")
+
+    def obc_lyapunov_doubling(self, b, batch, a, s_a, q, s_q, w, remaining, n_steps):
+        """Doubling over the series of w = q - a w a^dagger; see the C header."""
+        st = lib().qtx_rgf_obc_lyapunov_doubling(self._h, b, batch, _ptr(a), s_a, _ptr(q),
+                                                 s_q, _ptr(w), _ptr(remaining), n_steps)
+        return self._check(st, "qtx_rgf_obc_lyapunov_doubling")
 
 
 def make_g_problem(energies_host, H, sigma_r, sigma_l, sigma_g, XR, XL=None,

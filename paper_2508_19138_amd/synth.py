@@ -236,3 +236,15 @@ def lead_blocks(seed, b, energies, eta=0.05):
     m = (E[:, None, None] + 1j * eta) * eye[None] - h00[None]
     return np.ascontiguousarray(m), np.ascontiguousarray(-h01), \
         np.ascontiguousarray(-h01.conj().T)
+
+
+def lyapunov_blocks(seed, b, n_e, rho=0.8):
+    """Operands of w = q - a w a^dagger for n_e energies: a complex
+    N(0, rho^2/b) (spectral radius about rho by the circular law), q
+    anti-Hermitian, (Y - Y^dagger)/2 with Y complex N(0, 1/b), as a lesser or
+    greater quantity is.  Draw order: all a, then all Y."""
+    rng = np.random.default_rng(seed)
+    a = cn(rng, (n_e, b, b), rho * rho / b)
+    Y = cn(rng, (n_e, b, b), 1.0 / b)
+    q = 0.5 * (Y - np.conj(np.swapaxes(Y, 1, 2)))
+    return np.ascontiguousarray(a), np.ascontiguousarray(q)

@@ -368,3 +368,89 @@ def test_lesser_greater_invalid_arguments(ctx):
         with pytest.raises(Q.QtxError) as ei:
             ctx.obc_lesser_greater(*args)
         assert ei.value.status == Q.QTX_ERR_INVALID_ARG
+
+
+# ------------------------------------------------ Lyapunov (W lesser/greater)
+
+def _run_lyap(ctx, a, q, w0, count, method, shared_a=False):
+    ne, b = q.shape[0], q.shape[1]
+    da, dq = G.dev(a), G.dev(q)
+    w = G.dev(w0) if w0 is not None else G.empty((ne, b, b))
+    out = torch.empty(ne, dtype=torch.float64, device=G.DEV)
+    s_a = 0 if shared_a else b * b
+    torch.cuda.synchronize()
+    if method == "fixed":
+        ctx.obc_lyapunov_fixed_point(b, ne, da, s_a, dq, b * b, w, out, count)
+    else:
+        ctx.obc_lyapunov_doubling(b, ne, da, s_a, dq, b * b, w, out, count)
+    torch.cuda.synchronize()
+    return w.cpu().numpy(), out.cpu().numpy()
+
+
+@pytest.mark.parametrize("b,ne,it", [(1, 4, 10), (32, 3, 6), (65, 2, 4), (256, 2, 3)])
+def test_lyapunov_fixed_point_matches_oracle(ctx, b, ne, it):
+    from oracle import obc_lyapunov_fixed_point
+    a, q = synth.lyapunov_blocks(60 + b, b, ne)
+    w0 = np.zeros_like(q)
+    w, upd = _run_lyap(ctx, a, q, w0, it, "fixed")
+    for e in range(ne):
+        rw, ru = obc_lyapunov_fixed_point(a[e], q[e], w0[e], it)
+        assert float(block_rel_err(w[e][None], rw[None])[0]) < TOL, e
+        assert abs(upd[e] - ru) <= 1e-8 * ru + 1e-12, (e, upd[e], ru)
+
+
+@pytest.mark.parametrize("b,ne,steps", [(1, 4, 3), (32, 3, 1), (33, 3, 4), (100, 2, 3),
+                                        (256, 2, 2)])
+def test_lyapunov_doubling_matches_oracle(ctx, b, ne, steps):
+    from oracle import obc_lyapunov_doubling
+    a, q = synth.lyapunov_blocks(70 + b, b, ne)
+    w, rest = _run_lyap(ctx, a, q, None, steps, "doubling")
+    for e in range(ne):
+        rw, rr = obc_lyapunov_doubling(a[e], q[e], steps)
+        assert float(block_rel_err(w[e][None], rw[None])[0]) < TOL, e
+        assert abs(rest[e] - rr) <= 1e-8 * rr + 1e-14, (e, rest[e], rr)
+
+
+def test_lyapunov_shared_a_converges_to_the_kronecker_solution(ctx):
+    b, ne = 12, 3
+    a, q = synth.lyapunov_blocks(5, b, ne, rho=0.7)
+    a1 = np.ascontiguousarray(a[:1])
+    K = np.eye(b * b) + np.kron(a1[0].conj(), a1[0])
+    wd, rest = _run_lyap(ctx, a1, q, None, 7, "doubling", shared_a=True)
+    wf, upd = _run_lyap(ctx, a1, q, np.zeros_like(q), 120, "fixed", shared_a=True)
+    for e in range(ne):
+        exact = np.linalg.solve(K, q[e].reshape(-1, order="F")).reshape((b, b), order="F")
+        assert np.linalg.norm(wd[e] - exact) / np.linalg.norm(exact) < 1e-12
+        assert np.linalg.norm(wf[e] - exact) / np.linalg.norm(exact) < 1e-12
+        assert np.linalg.norm(wd[e] + wd[e].conj().T) / np.linalg.norm(wd[e]) < 1e-13
+        assert rest[e] < 1e-12 and upd[e] < 1e-12
+
+
+def test_lyapunov_memoized_start_and_arguments(ctx):
+    from oracle import obc_lyapunov_doubling
+    b, ne = 20, 2
+    a, q = synth.lyapunov_blocks(8, b, ne, rho=0.6)
+    ws = np.stack([obc_lyapunov_doubling(a[e], q[e], 10)[0] for e in range(ne)])
+    w, upd = _run_lyap(ctx, a, q, ws, 2, "fixed")
+    for e in range(ne):
+        assert np.linalg.norm(w[e] - ws[e]) / np.linalg.norm(ws[e]) < 1e-12
+        assert upd[e] < 1e-12
+    x = G.empty((1, 4, 4))
+    for args in [(4, 1, x, 0, x, 0, x, None, 0), (4, 1, x, 5, x, 0, x, None, 1),
+                 (4, 1, None, 0, x, 0, x, None, 1), (0, 1, x, 0, x, 0, x, None, 1)]:
+        for fn in (ctx.obc_lyapunov_fixed_point, ctx.obc_lyapunov_doubling):
+            with pytest.raises(Q.QtxError) as ei:
+                fn(*args)
+            assert ei.value.status == Q.QTX_ERR_INVALID_ARG
+
+
+def test_lyapunov_full_size_sampled_energies(ctx):
+    from oracle import obc_lyapunov_doubling
+    b, ne, steps = 512, 8, 4
+    a, q = synth.lyapunov_blocks(2026, b, ne)
+    w, rest = _run_lyap(ctx, a, q, None, steps, "doubling")
+    assert np.all(np.isfinite(rest))
+    for e in (0, ne - 1):
+        rw, rr = obc_lyapunov_doubling(a[e], q[e], steps)
+        assert float(block_rel_err(w[e][None], rw[None])[0]) < TOL
+        assert abs(rest[e] - rr) <= 1e-8 * rr + 1e-14
