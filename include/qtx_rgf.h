@@ -298,8 +298,9 @@ qtx_status qtx_rgf_zinv(qtx_rgf_ctx* ctx, int32_t b, void* A, void* X,
  *                  meaningless and the others are unaffected.
  * 1 <= b <= 1024, batch >= 0, n_iter >= 1.  Inputs must be complete on the
  * device before the call; the call returns when the results are written.
- * Scratch of 3 * batch * b*b complex128 plus the inverse's panel buffers is
- * allocated and freed per call (QTX_ERR_NOMEM if that fails).  Errors:
+ * Scratch of 3 * batch * b*b complex128 plus the inverse's panel buffers
+ * comes from the context's workspace, which grows to the largest request
+ * and is kept (QTX_ERR_NOMEM if growing fails).  Errors:
  * QTX_ERR_INVALID_ARG (bad sizes, strides or NULL), QTX_ERR_BUSY,
  * QTX_ERR_HIP. */
 qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* ctx, int32_t b, int32_t batch,
@@ -327,8 +328,8 @@ qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* ctx, int32_t b, int32_t batch,
  *              met an exactly zero / non-finite pivot: k = step (1-based),
  *              n_steps + 1 for the final inverse of m_s.
  * 1 <= b <= 1024, batch >= 0, n_steps >= 1.  Scratch of 11 * batch * b*b
- * complex128 plus the inverse's panel buffers is allocated and freed per
- * call.  Errors as for qtx_rgf_obc_fixed_point. */
+ * complex128 plus the inverse's panel buffers comes from the context's
+ * workspace.  Errors as for qtx_rgf_obc_fixed_point. */
 qtx_status qtx_rgf_obc_sancho_rubio(qtx_rgf_ctx* ctx, int32_t b, int32_t batch,
                                     const void* m, int64_t s_m, const void* n,
                                     int64_t s_n, const void* n_prime,
@@ -372,8 +373,8 @@ qtx_status qtx_rgf_obc_lesser_greater(qtx_rgf_ctx* ctx, int32_t b, int32_t batch
  *                     double[batch][n-1] or NULL (then XL_lower and H_upper
  *                     may be NULL).  XG_diag may be NULL if dos is.
  * Integration over energy is left to the caller.  1 <= b <= 1024, n >= 1,
- * batch >= 0; returns when written.  Scratch of (n-1) b*b complex128 per
- * call.  Errors: QTX_ERR_INVALID_ARG, QTX_ERR_NOMEM, QTX_ERR_BUSY,
+ * batch >= 0; returns when written.  Scratch of (n-1) b*b complex128 from
+ * the context's workspace.  Errors: QTX_ERR_INVALID_ARG, QTX_ERR_NOMEM, QTX_ERR_BUSY,
  * QTX_ERR_HIP. */
 /* The screened interaction's lesser/greater surface function (Sec.
  * "Lesser/Greater OBC"): the solution w of Eq. (lyapunov),
@@ -398,7 +399,8 @@ qtx_status qtx_rgf_obc_lesser_greater(qtx_rgf_ctx* ctx, int32_t b, int32_t batch
  *            at base + e * s_* elements (0 = shared, else >= b*b).
  *   w        [batch][b][b] device, contiguous; must not overlap a or q.
  * 1 <= b <= 1024, batch >= 0, n_iter / n_steps >= 1.  Scratch of 2 (fixed
- * point) or 3 (doubling) * batch * b*b complex128 per call.  Errors:
+ * point) or 3 (doubling) * batch * b*b complex128 from the context's
+ * workspace.  Errors:
  * QTX_ERR_INVALID_ARG, QTX_ERR_NOMEM, QTX_ERR_BUSY, QTX_ERR_HIP. */
 qtx_status qtx_rgf_obc_lyapunov_fixed_point(qtx_rgf_ctx* ctx, int32_t b,
                                             int32_t batch, const void* a,

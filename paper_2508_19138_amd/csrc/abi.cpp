@@ -627,12 +627,8 @@ qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t batch, con
     HIPCHK(c, hipSetDevice(c->device));
     const long long bb = (long long)b * b;
     const size_t blk = (size_t)batch * bb * 16;
-    if (hipMalloc((void**)&work, 3 * blk + LeadLane::inv_work(b, batch)) != hipSuccess) {
-      (void)hipGetLastError();
-      work = nullptr;
-      c->err = "scratch allocation of the fixed-point iteration failed";
-      return QTX_ERR_NOMEM;
-    }
+    ensure(c, &c->ws, &c->ws_bytes, 3 * blk + LeadLane::inv_work(b, batch));   // grow-only, reused
+    work = c->ws;
     void* T = work;
     void* W = work + blk;
     void* xb = work + 2 * blk;
@@ -656,13 +652,8 @@ qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t batch, con
     if (update) HIPCHK(c, launch_update_norm(cur, nxt, update, bb, batch, st));
     if (cur != x) HIPCHK(c, hipMemcpyAsync(x, cur, blk, hipMemcpyDeviceToDevice, st));
     c->pool->exe(0).sync_and_collect(c->stats);
-    HIPCHK(c, hipFree(work));
   } catch (const Fail& f) {
     if (c->err.empty()) c->err = f.what;
-    if (work) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(work);
-    }
     return (qtx_status)f.st;
   }
   return QTX_OK;
@@ -690,12 +681,8 @@ qtx_status qtx_rgf_obc_sancho_rubio(qtx_rgf_ctx* c, int32_t b, int32_t batch, co
     const long long bb = (long long)b * b;
     const size_t blk = (size_t)batch * bb * 16;
     constexpr int kBlocks = 11;
-    if (hipMalloc((void**)&work, kBlocks * blk + LeadLane::inv_work(b, batch)) != hipSuccess) {
-      (void)hipGetLastError();
-      work = nullptr;
-      c->err = "scratch allocation of the decimation failed";
-      return QTX_ERR_NOMEM;
-    }
+    ensure(c, &c->ws, &c->ws_bytes, kBlocks * blk + LeadLane::inv_work(b, batch));   // grow-only, reused
+    work = c->ws;
     char* w = work;
     void* ms = w;            void* mb = w + blk;       void* W = w + 2 * blk;
     void* gi = w + 3 * blk;  void* ga = w + 4 * blk;   void* gc = w + 5 * blk;
@@ -737,13 +724,8 @@ qtx_status qtx_rgf_obc_sancho_rubio(qtx_rgf_ctx* c, int32_t b, int32_t batch, co
     if (coupling)
       HIPCHK(c, launch_coupling_norm(a, cp, n, s_n, n_prime, s_np, coupling, bb, batch, st));
     c->pool->exe(0).sync_and_collect(c->stats);
-    HIPCHK(c, hipFree(work));
   } catch (const Fail& f) {
     if (c->err.empty()) c->err = f.what;
-    if (work) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(work);
-    }
     return (qtx_status)f.st;
   }
   return QTX_OK;
@@ -827,12 +809,8 @@ qtx_status qtx_rgf_observables(qtx_rgf_ctx* c, int32_t n_blocks, int32_t b, int3
     const long long bb = (long long)b * b;
     const hipStream_t st = c->pool->exe(0).stream();
     if (want_cur) {
-      if (hipMalloc(&hd, (size_t)(n_blocks - 1) * bb * 16) != hipSuccess) {
-        (void)hipGetLastError();
-        hd = nullptr;
-        c->err = "scratch allocation of the adjoint couplings failed";
-        return QTX_ERR_NOMEM;
-      }
+      ensure(c, &c->ws, &c->ws_bytes, (size_t)(n_blocks - 1) * bb * 16);   // grow-only
+      hd = c->ws;
       Lane L;
       TransDesc t{};
       t.C = nullptr;
@@ -856,13 +834,8 @@ qtx_status qtx_rgf_observables(qtx_rgf_ctx* c, int32_t n_blocks, int32_t b, int3
                                  density, want_cur ? current : nullptr, n_blocks, b, batch,
                                  st));
     c->pool->exe(0).sync_and_collect(c->stats);
-    if (hd) HIPCHK(c, hipFree(hd));
   } catch (const Fail& fl) {
     if (c->err.empty()) c->err = fl.what;
-    if (hd) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(hd);
-    }
     return (qtx_status)fl.st;
   }
   return QTX_OK;
@@ -886,12 +859,8 @@ qtx_status qtx_rgf_obc_lyapunov_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t b
     HIPCHK(c, hipSetDevice(c->device));
     const long long bb = (long long)b * b;
     const size_t blk = (size_t)batch * bb * 16;
-    if (hipMalloc((void**)&work, 2 * blk) != hipSuccess) {
-      (void)hipGetLastError();
-      work = nullptr;
-      c->err = "scratch allocation of the Lyapunov iteration failed";
-      return QTX_ERR_NOMEM;
-    }
+    ensure(c, &c->ws, &c->ws_bytes, 2 * blk);   // grow-only, reused
+    work = c->ws;
     void* T = work;
     void* wb = work + blk;
     LeadLane lane(c, b, batch, nullptr);
@@ -908,13 +877,8 @@ qtx_status qtx_rgf_obc_lyapunov_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t b
     if (update) HIPCHK(c, launch_update_norm(cur, nxt, update, bb, batch, st));
     if (cur != w) HIPCHK(c, hipMemcpyAsync(w, cur, blk, hipMemcpyDeviceToDevice, st));
     c->pool->exe(0).sync_and_collect(c->stats);
-    HIPCHK(c, hipFree(work));
   } catch (const Fail& fl) {
     if (c->err.empty()) c->err = fl.what;
-    if (work) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(work);
-    }
     return (qtx_status)fl.st;
   }
   return QTX_OK;
@@ -938,12 +902,8 @@ qtx_status qtx_rgf_obc_lyapunov_doubling(qtx_rgf_ctx* c, int32_t b, int32_t batc
     HIPCHK(c, hipSetDevice(c->device));
     const long long bb = (long long)b * b;
     const size_t blk = (size_t)batch * bb * 16;
-    if (hipMalloc((void**)&work, 3 * blk) != hipSuccess) {
-      (void)hipGetLastError();
-      work = nullptr;
-      c->err = "scratch allocation of the Lyapunov doubling failed";
-      return QTX_ERR_NOMEM;
-    }
+    ensure(c, &c->ws, &c->ws_bytes, 3 * blk);   // grow-only, reused
+    work = c->ws;
     void* T = work;
     void* A2[2] = {work + blk, work + 2 * blk};
     LeadLane lane(c, b, batch, nullptr);
@@ -966,13 +926,8 @@ qtx_status qtx_rgf_obc_lyapunov_doubling(qtx_rgf_ctx* c, int32_t b, int32_t batc
     if (remaining)
       HIPCHK(c, launch_coupling_norm(A, A, a, s_a, a, s_a, remaining, bb, batch, st));
     c->pool->exe(0).sync_and_collect(c->stats);
-    HIPCHK(c, hipFree(work));
   } catch (const Fail& fl) {
     if (c->err.empty()) c->err = fl.what;
-    if (work) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(work);
-    }
     return (qtx_status)fl.st;
   }
   return QTX_OK;
