@@ -145,3 +145,82 @@ def test_ballistic_device_end_to_end(ctx):
     assert np.max(np.abs(cur - rcur)) <= 1e-10 * np.max(rcur)
     assert np.max(np.abs(dos.cpu().numpy()[0] - rdos)) <= 1e-10 * np.max(rdos)
     assert np.max(np.abs(dens.cpu().numpy()[0] - rdens)) <= 1e-10 * np.max(rdos)
+
+
+def test_device_pipeline_leads_to_current(ctx):
+    """Everything on the device through the C ABI: the leads' surface
+    functions by decimation, the lesser/greater boundary blocks, the solve
+    and the observables.  A disordered ballistic device between two
+    different leads at f_L > f_R conducts the same current through every
+    interface, equal to the oracle pipeline's."""
+    from oracle import obc_sancho_rubio
+    n, b, E, eta = 6, 16, 0.15, 1e-6
+    fL, fR = 0.9, 0.1
+    rng = np.random.default_rng(123)
+
+    def herm(var):
+        X = synth.cn(rng, (b, b), var / b)
+        return 0.5 * (X + X.conj().T)
+
+    Hd = np.stack([herm(0.5) for _ in range(n)])
+    Hu = np.stack([synth.cn(rng, (b, b), 0.25 / b) + 0.5 * np.eye(b) for _ in range(n - 1)])
+    I = np.eye(b)
+    z = E + 1j * eta
+    # left lead repeats block 0 and the first coupling outward (n = H_01^dagger
+    # towards the lead, since the lead extends to the left), right lead block
+    # n-1 and the last coupling
+    mL, nL, npL = z * I - Hd[0], -Hu[0].conj().T, -Hu[0]
+    mR, nR, npR = z * I - Hd[-1], -Hu[-1], -Hu[-1].conj().T
+    m = np.stack([mL, mR])
+    nn = np.stack([nL, nR])
+    nnp = np.stack([npL, npR])
+    dm, dn, dnp = G.dev(m), G.dev(nn), G.dev(nnp)
+    x = G.empty((2, b, b))
+    sig = G.empty((2, b, b))
+    cpl = torch.empty(2, dtype=torch.float64, device=G.DEV)
+    info = torch.zeros(2, dtype=torch.int32, device=G.DEV)
+    torch.cuda.synchronize()
+    ctx.obc_sancho_rubio(b, 2, dm, b * b, dn, b * b, dnp, b * b, x, sig, cpl, info, 40)
+    torch.cuda.synchronize()
+    assert int(info.abs().max().item()) == 0 and float(cpl.max().item()) < 1e-12
+    sl = G.empty((2, b, b))
+    sg = G.empty((2, b, b))
+    ctx.obc_lesser_greater(b, 2, sig, b * b, np.array([fL, fR]), np.array([1 - fL, 1 - fR]),
+                           sl, sg)
+    torch.cuda.synchronize()
+    # device self-energies: only the two contact blocks are non-zero
+    sr_d = torch.zeros((1, n, b, b), dtype=torch.complex128, device=G.DEV)
+    sl_d = torch.zeros_like(sr_d)
+    sg_d = torch.zeros_like(sr_d)
+    sr_d[0, 0], sr_d[0, -1] = sig[0], sig[1]
+    sl_d[0, 0], sl_d[0, -1] = sl[0], sl[1]
+    sg_d[0, 0], sg_d[0, -1] = sg[0], sg[1]
+    Ea = np.ascontiguousarray([E], dtype=np.float64)
+    XR, XL, XG = G.outputs(1, n, b), G.outputs(1, n, b), G.outputs(1, n, b)
+    dHu = G.dev(Hu)
+    prob = Q.make_g_problem(Ea, (G.dev(Hd), dHu, None), (sr_d, None, None),
+                            (sl_d, None, None), (sg_d, None, None), XR, XL, XG)
+    torch.cuda.synchronize()
+    assert ctx.solve_batch([prob]) == Q.QTX_OK
+    torch.cuda.synchronize()
+    cur = torch.empty((1, n - 1), dtype=torch.float64, device=G.DEV)
+    ctx.observables(n, b, 1, XL[0], None, XL[2], dHu, None, None, cur)
+    torch.cuda.synchronize()
+    cur = cur.cpu().numpy()[0]
+    assert np.all(cur > 0) and np.ptp(cur) <= 1e-8 * np.max(cur)
+    # oracle pipeline (the eta above only selects the retarded branch)
+    sigL = nL @ obc_sancho_rubio(mL, nL, npL)[0] @ npL
+    sigR = nR @ obc_sancho_rubio(mR, nR, npR)[0] @ npR
+    slL, sgL = obc_lesser_greater(sigL, fL, 1 - fL)
+    slR, sgR = obc_lesser_greater(sigR, fR, 1 - fR)
+    d = (E * I)[None] - Hd
+    d[0] = d[0] - sigL
+    d[-1] = d[-1] - sigR
+    A = (d, -Hu, -np.conj(np.swapaxes(Hu, 1, 2)))
+    zz = np.zeros((n - 1, b, b), np.complex128)
+    bl = np.zeros((n, b, b), np.complex128)
+    bg = np.zeros((n, b, b), np.complex128)
+    bl[0], bl[-1], bg[0], bg[-1] = slL, slR, sgL, sgR
+    _, (XLo, XGo) = rgf_selected(A, [(bl, zz, zz), (bg, zz, zz)])
+    _, _, rcur = observables(XLo, XGo, Hu)
+    assert np.max(np.abs(cur - rcur)) <= 1e-9 * np.max(rcur)
