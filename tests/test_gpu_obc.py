@@ -454,3 +454,25 @@ def test_lyapunov_full_size_sampled_energies(ctx):
         rw, rr = obc_lyapunov_doubling(a[e], q[e], steps)
         assert float(block_rel_err(w[e][None], rw[None])[0]) < TOL
         assert abs(rest[e] - rr) <= 1e-8 * rr + 1e-14
+
+
+def test_maximum_block_size(ctx):
+    """b = 1024 (the largest block the inverse takes): every lead solver on
+    two energies against the oracle."""
+    from oracle import obc_sancho_rubio_steps, obc_lyapunov_doubling
+    b, ne = 1024, 2
+    m, n, np_ = synth.lead_blocks(31, b, [-0.5, 0.5], eta=0.05)
+    x0 = np.zeros((ne, b, b), np.complex128)
+    got = _run(ctx, m, n, np_, x0, 2)
+    _check(m, n, np_, x0, 2, got)
+    x, sig, cpl, info = _run_sr(ctx, m, n, np_, 2)
+    for e in range(ne):
+        rx, rs, rc = obc_sancho_rubio_steps(m[e], n, np_, 2)
+        assert info[e] == 0
+        assert float(block_rel_err(x[e][None], rx[None])[0]) < TOL
+        assert float(block_rel_err(sig[e][None], rs[None])[0]) < TOL
+    a, q = synth.lyapunov_blocks(32, b, ne)
+    w, rest = _run_lyap(ctx, a, q, None, 2, "doubling")
+    for e in range(ne):
+        rw, rr = obc_lyapunov_doubling(a[e], q[e], 2)
+        assert float(block_rel_err(w[e][None], rw[None])[0]) < TOL
