@@ -627,8 +627,10 @@ qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t batch, con
     HIPCHK(c, hipSetDevice(c->device));
     const long long bb = (long long)b * b;
     const size_t blk = (size_t)batch * bb * 16;
-    ensure(c, &c->ws, &c->ws_bytes, 3 * blk + LeadLane::inv_work(b, batch));   // grow-only, reused
+    const size_t iwb = LeadLane::inv_work(b, batch);
+    ensure(c, &c->ws, &c->ws_bytes, 3 * blk + iwb + norm_scratch_bytes(bb, batch));   // grow-only
     work = c->ws;
+    double* part = (double*)(work + 3 * blk + iwb);
     void* T = work;
     void* W = work + blk;
     void* xb = work + 2 * blk;
@@ -649,7 +651,7 @@ qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t batch, con
     std::vector<Lane*> lp{&q.L};
     run_lanes_to_end(c, lp);
     const hipStream_t st = c->pool->exe(0).stream();
-    if (update) HIPCHK(c, launch_update_norm(cur, nxt, update, bb, batch, st));
+    if (update) HIPCHK(c, launch_update_norm(cur, nxt, update, bb, batch, part, st));
     if (cur != x) HIPCHK(c, hipMemcpyAsync(x, cur, blk, hipMemcpyDeviceToDevice, st));
     c->pool->exe(0).sync_and_collect(c->stats);
   } catch (const Fail& f) {
@@ -681,8 +683,10 @@ qtx_status qtx_rgf_obc_sancho_rubio(qtx_rgf_ctx* c, int32_t b, int32_t batch, co
     const long long bb = (long long)b * b;
     const size_t blk = (size_t)batch * bb * 16;
     constexpr int kBlocks = 11;
-    ensure(c, &c->ws, &c->ws_bytes, kBlocks * blk + LeadLane::inv_work(b, batch));   // grow-only, reused
-    work = c->ws;
+    const size_t iwb = LeadLane::inv_work(b, batch);
+    ensure(c, &c->ws, &c->ws_bytes, kBlocks * blk + iwb + norm_scratch_bytes(bb, batch));
+    work = c->ws;                                   // grow-only, reused
+    double* part = (double*)(work + kBlocks * blk + iwb);
     char* w = work;
     void* ms = w;            void* mb = w + blk;       void* W = w + 2 * blk;
     void* gi = w + 3 * blk;  void* ga = w + 4 * blk;   void* gc = w + 5 * blk;
@@ -722,7 +726,8 @@ qtx_status qtx_rgf_obc_sancho_rubio(qtx_rgf_ctx* c, int32_t b, int32_t batch, co
     run_lanes_to_end(c, lp);
     const hipStream_t st = c->pool->exe(0).stream();
     if (coupling)
-      HIPCHK(c, launch_coupling_norm(a, cp, n, s_n, n_prime, s_np, coupling, bb, batch, st));
+      HIPCHK(c, launch_coupling_norm(a, cp, n, s_n, n_prime, s_np, coupling, bb, batch, part,
+                                     st));
     c->pool->exe(0).sync_and_collect(c->stats);
   } catch (const Fail& f) {
     if (c->err.empty()) c->err = f.what;
@@ -859,8 +864,9 @@ qtx_status qtx_rgf_obc_lyapunov_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t b
     HIPCHK(c, hipSetDevice(c->device));
     const long long bb = (long long)b * b;
     const size_t blk = (size_t)batch * bb * 16;
-    ensure(c, &c->ws, &c->ws_bytes, 2 * blk);   // grow-only, reused
+    ensure(c, &c->ws, &c->ws_bytes, 2 * blk + norm_scratch_bytes(bb, batch));   // grow-only
     work = c->ws;
+    double* part = (double*)(work + 2 * blk);
     void* T = work;
     void* wb = work + blk;
     LeadLane lane(c, b, batch, nullptr);
@@ -874,7 +880,7 @@ qtx_status qtx_rgf_obc_lyapunov_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t b
     std::vector<Lane*> lp{&lane.L};
     run_lanes_to_end(c, lp);
     const hipStream_t st = c->pool->exe(0).stream();
-    if (update) HIPCHK(c, launch_update_norm(cur, nxt, update, bb, batch, st));
+    if (update) HIPCHK(c, launch_update_norm(cur, nxt, update, bb, batch, part, st));
     if (cur != w) HIPCHK(c, hipMemcpyAsync(w, cur, blk, hipMemcpyDeviceToDevice, st));
     c->pool->exe(0).sync_and_collect(c->stats);
   } catch (const Fail& fl) {
@@ -902,8 +908,9 @@ qtx_status qtx_rgf_obc_lyapunov_doubling(qtx_rgf_ctx* c, int32_t b, int32_t batc
     HIPCHK(c, hipSetDevice(c->device));
     const long long bb = (long long)b * b;
     const size_t blk = (size_t)batch * bb * 16;
-    ensure(c, &c->ws, &c->ws_bytes, 3 * blk);   // grow-only, reused
+    ensure(c, &c->ws, &c->ws_bytes, 3 * blk + norm_scratch_bytes(bb, batch));   // grow-only
     work = c->ws;
+    double* part = (double*)(work + 3 * blk);
     void* T = work;
     void* A2[2] = {work + blk, work + 2 * blk};
     LeadLane lane(c, b, batch, nullptr);
@@ -924,7 +931,7 @@ qtx_status qtx_rgf_obc_lyapunov_doubling(qtx_rgf_ctx* c, int32_t b, int32_t batc
     run_lanes_to_end(c, lp);
     const hipStream_t st = c->pool->exe(0).stream();
     if (remaining)
-      HIPCHK(c, launch_coupling_norm(A, A, a, s_a, a, s_a, remaining, bb, batch, st));
+      HIPCHK(c, launch_coupling_norm(A, A, a, s_a, a, s_a, remaining, bb, batch, part, st));
     c->pool->exe(0).sync_and_collect(c->stats);
   } catch (const Fail& fl) {
     if (c->err.empty()) c->err = fl.what;

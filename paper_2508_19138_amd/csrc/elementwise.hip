@@ -127,57 +127,43 @@ void transcomb_kernel(FlatLaunch L) {
   }
 }
 
-// Relative size of the last fixed-point update of every matrix: one
-// workgroup per matrix sums |x - prev|^2 and |x|^2 over its elements
-// (strided by the workgroup, then a tree in LDS).
-__global__ __launch_bounds__(256)
-void update_norm_kernel(const double2* __restrict__ x, const double2* __restrict__ prev,
-                        double* __restrict__ out, long long bb) {
-  const long long e = blockIdx.x;
-  const double2* a = x + e * bb;
-  const double2* p = prev + e * bb;
-  double sd = 0.0, sx = 0.0;
-  for (long long i = threadIdx.x; i < bb; i += 256) {
-    const double2 u = a[i], v = p[i];
-    const double dx = u.x - v.x, dy = u.y - v.y;
-    sd += dx * dx + dy * dy;
-    sx += u.x * u.x + u.y * u.y;
-  }
-  __shared__ double rd[256], rx[256];
-  const int t = threadIdx.x;
-  rd[t] = sd;
-  rx[t] = sx;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (t < h) {
-      rd[t] += rd[t + h];
-      rx[t] += rx[t + h];
-    }
-    __syncthreads();
-  }
-  if (t == 0) out[e] = rx[0] > 0.0 ? sqrt(rd[0]) / sqrt(rx[0]) : (rd[0] > 0.0 ? HUGE_VAL : 0.0);
-}
+// Sums of squared moduli over matrices, in two passes so that every matrix
+// is spread over many workgroups: pass one writes per-chunk partial sums of
+// up to four terms (|u|^2, or |u - v|^2 when v is given), pass two combines
+// them per matrix.  Deterministic: fixed chunking and reduction order.
+struct NormTerms {
+  const double2* u[4];
+  const double2* v[4];
+  long long su[4], sv[4];
+  int nt;
+};
 
-// Remaining coupling of the decimation per matrix:
-// (||a_e||_F + ||c_e||_F) / (||a0_e||_F + ||c0_e||_F), where a0/c0 may be one
-// block shared by all matrices (stride 0).
 __global__ __launch_bounds__(256)
-void coupling_norm_kernel(const double2* __restrict__ a, const double2* __restrict__ c,
-                          const double2* __restrict__ a0, long long sa0,
-                          const double2* __restrict__ c0, long long sc0,
-                          double* __restrict__ out, long long bb) {
-  const long long e = blockIdx.x;
-  const double2* src[4] = {a + e * bb, c + e * bb, a0 + e * sa0, c0 + e * sc0};
-  __shared__ double red[4][256];
+void norm_partial_kernel(NormTerms T, long long bb, int chunks, double* __restrict__ part) {
+  const long long e = blockIdx.x / chunks;
+  const int ch = blockIdx.x % chunks;
+  const long long per = (bb + chunks - 1) / chunks;
+  const long long q0 = ch * per;
+  const long long q1 = q0 + per < bb ? q0 + per : bb;
   const int t = threadIdx.x;
+  __shared__ double red[4][256];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    double s = 0.0;
-    for (long long i = t; i < bb; i += 256) {
-      const double2 u = src[k][i];
-      s += u.x * u.x + u.y * u.y;
+    double acc = 0.0;
+    if (k < T.nt) {                          // uniform across the workgroup
+      const double2* u = T.u[k] + e * T.su[k];
+      const double2* v = T.v[k] ? T.v[k] + e * T.sv[k] : nullptr;
+      for (long long q = q0 + t; q < q1; q += 256) {
+        double2 a = u[q];
+        if (v) {
+          const double2 w = v[q];
+          a.x -= w.x;
+          a.y -= w.y;
+        }
+        acc += a.x * a.x + a.y * a.y;
+      }
     }
-    red[k][t] = s;
+    red[k][t] = acc;
   }
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
@@ -187,11 +173,38 @@ void coupling_norm_kernel(const double2* __restrict__ a, const double2* __restri
     }
     __syncthreads();
   }
-  if (t == 0) {
-    const double num = sqrt(red[0][0]) + sqrt(red[1][0]);
-    const double den = sqrt(red[2][0]) + sqrt(red[3][0]);
+  if (t < 4) part[(e * chunks + ch) * 4 + t] = red[t][0];
+}
+
+// mode 0: ||u0 - v0|| / ||u1|| (the relative update; infinite if ||u1|| = 0
+// and the update is not); mode 1: (||u0|| + ||u1||) / (||u2|| + ||u3||)
+__global__ __launch_bounds__(256)
+void norm_final_kernel(const double* __restrict__ part, int chunks, int batch, int mode,
+                       double* __restrict__ out) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= batch) return;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int ch = 0; ch < chunks; ++ch)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[k] += part[((long long)e * chunks + ch) * 4 + k];
+  if (mode == 0) {
+    out[e] = s[1] > 0.0 ? sqrt(s[0]) / sqrt(s[1]) : (s[0] > 0.0 ? HUGE_VAL : 0.0);
+  } else {
+    const double num = sqrt(s[0]) + sqrt(s[1]);
+    const double den = sqrt(s[2]) + sqrt(s[3]);
     out[e] = den > 0.0 ? num / den : 0.0;
   }
+}
+
+hipError_t launch_norms(const NormTerms& T, long long bb, int batch, int mode, double* out,
+                        double* part, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  const int chunks = norm_chunks(bb);
+  hipLaunchKernelGGL(norm_partial_kernel, dim3((unsigned)((long long)batch * chunks)), dim3(256),
+                     0, s, T, bb, chunks, part);
+  hipLaunchKernelGGL(norm_final_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, part, chunks,
+                     batch, mode, out);
+  return hipGetLastError();
 }
 
 // Observables per energy e: workgroups k < n take block k's traces
@@ -266,20 +279,23 @@ hipError_t launch_observables(const void* gl_d, const void* gg_d, const void* gl
 
 hipError_t launch_coupling_norm(const void* a, const void* c, const void* a0, long long sa0,
                                 const void* c0, long long sc0, double* out, long long bb,
-                                int batch, hipStream_t s) {
-  if (batch <= 0) return hipSuccess;
-  hipLaunchKernelGGL(coupling_norm_kernel, dim3(batch), dim3(256), 0, s, (const double2*)a,
-                     (const double2*)c, (const double2*)a0, sa0, (const double2*)c0, sc0, out,
-                     bb);
-  return hipGetLastError();
+                                int batch, double* part, hipStream_t s) {
+  NormTerms T{};
+  T.u[0] = (const double2*)a;  T.su[0] = bb;
+  T.u[1] = (const double2*)c;  T.su[1] = bb;
+  T.u[2] = (const double2*)a0; T.su[2] = sa0;
+  T.u[3] = (const double2*)c0; T.su[3] = sc0;
+  T.nt = 4;
+  return launch_norms(T, bb, batch, 1, out, part, s);
 }
 
 hipError_t launch_update_norm(const void* x, const void* prev, double* out, long long bb,
-                              int batch, hipStream_t s) {
-  if (batch <= 0) return hipSuccess;
-  hipLaunchKernelGGL(update_norm_kernel, dim3(batch), dim3(256), 0, s, (const double2*)x,
-                     (const double2*)prev, out, bb);
-  return hipGetLastError();
+                              int batch, double* part, hipStream_t s) {
+  NormTerms T{};
+  T.u[0] = (const double2*)x; T.v[0] = (const double2*)prev; T.su[0] = bb; T.sv[0] = bb;
+  T.u[1] = (const double2*)x; T.su[1] = bb;
+  T.nt = 2;
+  return launch_norms(T, bb, batch, 0, out, part, s);
 }
 
 hipError_t launch_lincomb(const FlatLaunch& l, hipStream_t s) {

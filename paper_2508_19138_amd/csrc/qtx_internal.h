@@ -135,21 +135,31 @@ struct TransDesc {
 constexpr int kTransTile = 32;
 hipError_t launch_lincomb(const FlatLaunch& l, hipStream_t s);
 hipError_t launch_transcomb(const FlatLaunch& l, hipStream_t s);
-// out[e] = ||x_e - prev_e||_F / ||x_e||_F for `batch` contiguous matrices of
-// bb complex elements each (one workgroup per matrix).
-hipError_t launch_update_norm(const void* x, const void* prev, double* out, long long bb,
-                              int batch, hipStream_t s);
-// out[e] = (||a_e||_F + ||c_e||_F) / (||a0_e||_F + ||c0_e||_F); a0, c0 at strides
-// sa0, sc0 (0 = one shared block).
 // Per energy: dos[n], density[n] from the diagonal blocks of G^< / G^>,
 // current[n-1] from the lower blocks of G^< and Hd = H_{i,i+1}^dagger
 // ([n-1][b][b], shared by all energies).  Null outputs are skipped.
 hipError_t launch_observables(const void* gl_d, const void* gg_d, const void* gl_l,
                               const void* hd, double* dos, double* dens, double* cur, int n,
                               int b, int batch, hipStream_t s);
+// Per-matrix norms in two passes (partial sums per chunk, then per matrix);
+// `part` is device scratch of norm_scratch_bytes(bb, batch) bytes.
+constexpr long long kNormChunkElems = 8192;
+inline int norm_chunks(long long bb) {
+  const long long c = (bb + kNormChunkElems - 1) / kNormChunkElems;
+  return (int)(c < 1 ? 1 : (c > 64 ? 64 : c));
+}
+inline size_t norm_scratch_bytes(long long bb, int batch) {
+  return (size_t)batch * norm_chunks(bb) * 4 * sizeof(double) + 256;
+}
+// out[e] = ||x_e - prev_e||_F / ||x_e||_F for `batch` contiguous matrices of
+// bb complex elements each.
+hipError_t launch_update_norm(const void* x, const void* prev, double* out, long long bb,
+                              int batch, double* part, hipStream_t s);
+// out[e] = (||a_e||_F + ||c_e||_F) / (||a0_e||_F + ||c0_e||_F); a, c contiguous,
+// a0, c0 at strides sa0, sc0 (0 = one shared block).
 hipError_t launch_coupling_norm(const void* a, const void* c, const void* a0, long long sa0,
                                 const void* c0, long long sc0, double* out, long long bb,
-                                int batch, hipStream_t s);
+                                int batch, double* part, hipStream_t s);
 
 // workgroups per matrix of the elementwise kernels
 __host__ __device__ inline int lincomb_chunks(int b) { return (int)(((long long)b * b + kLinChunk - 1) / kLinChunk); }
