@@ -301,8 +301,8 @@ qtx_status qtx_rgf_zinv(qtx_rgf_ctx* ctx, int32_t b, void* A, void* X,
  * Scratch of 3 * batch * b*b complex128 plus the inverse's panel buffers
  * comes from the context's workspace, which grows to the largest request
  * and is kept (QTX_ERR_NOMEM if growing fails).  Errors:
- * QTX_ERR_INVALID_ARG (bad sizes, strides or NULL), QTX_ERR_BUSY,
- * QTX_ERR_HIP. */
+ * QTX_ERR_INVALID_ARG (bad sizes, strides or NULL, or x / sigma sharing
+ * memory with an input or each other), QTX_ERR_BUSY, QTX_ERR_HIP. */
 qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* ctx, int32_t b, int32_t batch,
                                    const void* m, int64_t s_m, const void* n,
                                    int64_t s_n, const void* n_prime,
@@ -348,7 +348,8 @@ qtx_status qtx_rgf_obc_sancho_rubio(qtx_rgf_ctx* ctx, int32_t b, int32_t batch,
  *                     energy and its complement, both evaluated by the
  *                     caller (so that neither rounds to zero).
  *   sigma_l, sigma_g  [batch][b][b] device outputs; either may be NULL, not
- *                     both.  Outputs must not overlap sigma_r.
+ *                     both.  Outputs must not overlap sigma_r or each other
+ *                     (QTX_ERR_INVALID_ARG).
  * 1 <= b <= 1024, batch >= 0; returns when written.  Errors:
  * QTX_ERR_INVALID_ARG, QTX_ERR_BUSY, QTX_ERR_HIP. */
 qtx_status qtx_rgf_obc_lesser_greater(qtx_rgf_ctx* ctx, int32_t b, int32_t batch,
@@ -397,7 +398,8 @@ qtx_status qtx_rgf_obc_lesser_greater(qtx_rgf_ctx* ctx, int32_t b, int32_t batch
  *
  *   a, q     row-major b x b complex128 device blocks; the block of energy e
  *            at base + e * s_* elements (0 = shared, else >= b*b).
- *   w        [batch][b][b] device, contiguous; must not overlap a or q.
+ *   w        [batch][b][b] device, contiguous; must not overlap a or q
+ *            (QTX_ERR_INVALID_ARG).
  * 1 <= b <= 1024, batch >= 0, n_iter / n_steps >= 1.  Scratch of 2 (fixed
  * point) or 3 (doubling) * batch * b*b complex128 from the context's
  * workspace.  Errors:

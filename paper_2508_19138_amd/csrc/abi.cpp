@@ -592,6 +592,18 @@ struct LeadLane {
   }
 };
 
+// Byte range [lo, hi) of `batch` b x b complex128 blocks at stride s
+// elements (0 = one shared block).
+struct Span {
+  uintptr_t lo, hi;
+};
+Span span_of(const void* p, long long bb, int64_t s, int batch) {
+  const uintptr_t lo = (uintptr_t)p;
+  const long long last = (s == 0 || batch <= 1) ? 0 : (long long)(batch - 1) * s;
+  return Span{lo, lo + (uintptr_t)((last + bb) * 16)};
+}
+bool overlap(const Span& a, const Span& b) { return a.lo < b.hi && b.lo < a.hi; }
+
 qtx_status lead_args_ok(int32_t b, int32_t batch, const void* m, int64_t s_m, const void* n,
                         int64_t s_n, const void* n_prime, int64_t s_np, const void* x,
                         int32_t count) {
@@ -618,6 +630,16 @@ qtx_status qtx_rgf_obc_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t batch, con
   if (!info) return QTX_ERR_INVALID_ARG;
   const qtx_status ok = lead_args_ok(b, batch, m, s_m, n, s_n, n_prime, s_np, x, n_iter);
   if (ok != QTX_OK) return ok;
+  {
+    const long long bb = (long long)b * b;
+    const Span in[3] = {span_of(m, bb, s_m, batch), span_of(n, bb, s_n, batch),
+                        span_of(n_prime, bb, s_np, batch)};
+    const Span sx = span_of(x, bb, bb, batch);
+    for (const Span& r : in)
+      if (overlap(sx, r) || (sigma && overlap(span_of(sigma, bb, bb, batch), r)))
+        return QTX_ERR_INVALID_ARG;
+    if (sigma && overlap(sx, span_of(sigma, bb, bb, batch))) return QTX_ERR_INVALID_ARG;
+  }
   if (c->busy) return QTX_ERR_BUSY;
   if (batch == 0) return QTX_OK;
   BusyGuard g(c);
@@ -673,6 +695,16 @@ qtx_status qtx_rgf_obc_sancho_rubio(qtx_rgf_ctx* c, int32_t b, int32_t batch, co
   if (!info) return QTX_ERR_INVALID_ARG;
   const qtx_status ok = lead_args_ok(b, batch, m, s_m, n, s_n, n_prime, s_np, x, n_steps);
   if (ok != QTX_OK) return ok;
+  {
+    const long long bb = (long long)b * b;
+    const Span in[3] = {span_of(m, bb, s_m, batch), span_of(n, bb, s_n, batch),
+                        span_of(n_prime, bb, s_np, batch)};
+    const Span sx = span_of(x, bb, bb, batch);
+    for (const Span& r : in)
+      if (overlap(sx, r) || (sigma && overlap(span_of(sigma, bb, bb, batch), r)))
+        return QTX_ERR_INVALID_ARG;
+    if (sigma && overlap(sx, span_of(sigma, bb, bb, batch))) return QTX_ERR_INVALID_ARG;
+  }
   if (c->busy) return QTX_ERR_BUSY;
   if (batch == 0) return QTX_OK;
   BusyGuard g(c);
@@ -747,6 +779,14 @@ qtx_status qtx_rgf_obc_lesser_greater(qtx_rgf_ctx* c, int32_t b, int32_t batch,
   if ((sigma_l && !f) || (sigma_g && !one_minus_f)) return QTX_ERR_INVALID_ARG;
   const long long bb = (long long)b * b;
   if (s_sr != 0 && s_sr < bb) return QTX_ERR_INVALID_ARG;
+  if (batch > 0) {
+    const Span in = span_of(sigma_r, bb, s_sr, batch);
+    if ((sigma_l && overlap(span_of(sigma_l, bb, bb, batch), in)) ||
+        (sigma_g && overlap(span_of(sigma_g, bb, bb, batch), in)) ||
+        (sigma_l && sigma_g &&
+         overlap(span_of(sigma_l, bb, bb, batch), span_of(sigma_g, bb, bb, batch))))
+      return QTX_ERR_INVALID_ARG;
+  }
   if (c->busy) return QTX_ERR_BUSY;
   if (batch == 0) return QTX_OK;
   BusyGuard g(c);
@@ -855,6 +895,12 @@ qtx_status qtx_rgf_obc_lyapunov_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t b
   if (!c) return QTX_ERR_INVALID_ARG;
   const qtx_status ok = lead_args_ok(b, batch, a, s_a, q, s_q, q, s_q, w, n_iter);
   if (ok != QTX_OK) return ok;
+  {
+    const long long bb = (long long)b * b;
+    const Span sw = span_of(w, bb, bb, batch);
+    if (overlap(sw, span_of(a, bb, s_a, batch)) || overlap(sw, span_of(q, bb, s_q, batch)))
+      return QTX_ERR_INVALID_ARG;
+  }
   if (c->busy) return QTX_ERR_BUSY;
   if (batch == 0) return QTX_OK;
   BusyGuard g(c);
@@ -899,6 +945,12 @@ qtx_status qtx_rgf_obc_lyapunov_doubling(qtx_rgf_ctx* c, int32_t b, int32_t batc
   if (!c) return QTX_ERR_INVALID_ARG;
   const qtx_status ok = lead_args_ok(b, batch, a, s_a, q, s_q, q, s_q, w, n_steps);
   if (ok != QTX_OK) return ok;
+  {
+    const long long bb = (long long)b * b;
+    const Span sw = span_of(w, bb, bb, batch);
+    if (overlap(sw, span_of(a, bb, s_a, batch)) || overlap(sw, span_of(q, bb, s_q, batch)))
+      return QTX_ERR_INVALID_ARG;
+  }
   if (c->busy) return QTX_ERR_BUSY;
   if (batch == 0) return QTX_OK;
   BusyGuard g(c);

@@ -476,3 +476,26 @@ def test_maximum_block_size(ctx):
     for e in range(ne):
         rw, rr = obc_lyapunov_doubling(a[e], q[e], 2)
         assert float(block_rel_err(w[e][None], rw[None])[0]) < TOL
+
+
+def test_overlapping_outputs_are_rejected(ctx):
+    """Outputs that share memory with inputs would be read after being
+    overwritten; the entry points refuse them before any work."""
+    b, ne = 8, 2
+    m = G.empty((ne, b, b))
+    n = G.empty((ne, b, b))
+    x = G.empty((ne, b, b))
+    info = torch.zeros(ne, dtype=torch.int32, device=G.DEV)
+    cases = [
+        lambda: ctx.obc_fixed_point(b, ne, m, b * b, n, 0, n, 0, m, None, None, info, 1),
+        lambda: ctx.obc_fixed_point(b, ne, m, b * b, n, 0, n, 0, x, n, None, info, 1),
+        lambda: ctx.obc_sancho_rubio(b, ne, m, b * b, n, 0, n, 0, x, x, None, info, 1),
+        lambda: ctx.obc_lyapunov_fixed_point(b, ne, m, b * b, n, b * b, n, None, 1),
+        lambda: ctx.obc_lyapunov_doubling(b, ne, m, b * b, n, b * b, m[1:], None, 1),
+        lambda: ctx.obc_lesser_greater(b, ne, m, b * b, np.ones(ne), np.ones(ne), m, None),
+        lambda: ctx.obc_lesser_greater(b, ne, m, b * b, np.ones(ne), np.ones(ne), x, x),
+    ]
+    for call in cases:
+        with pytest.raises(Q.QtxError) as ei:
+            call()
+        assert ei.value.status == Q.QTX_ERR_INVALID_ARG
