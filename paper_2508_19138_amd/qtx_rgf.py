@@ -306,6 +306,9 @@ class Context:
         float64 numpy arrays of length batch (kept alive by the caller)."""
         fp = None if f is None else np.ascontiguousarray(f, dtype=np.float64)
         gp = None if one_minus_f is None else np.ascontiguousarray(one_minus_f, dtype=np.float64)
+        for a in (fp, gp):
+            if a is not None and a.size < batch:
+                raise ValueError("occupation arrays need one value per energy")
         dp = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
         st = lib().qtx_rgf_obc_lesser_greater(self._h, b, batch, _ptr(sigma_r), s_sr, dp(fp),
                                               dp(gp), _ptr(sigma_l), _ptr(sigma_g))

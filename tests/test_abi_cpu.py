@@ -82,3 +82,13 @@ def test_create_without_device_fails_cleanly():
     assert st != Q.QTX_OK and not h.value
     st = Q.lib().qtx_rgf_create(ctypes.byref(h), -1, 0, None, 0)
     assert st == Q.QTX_ERR_INVALID_ARG
+
+
+def test_occupation_arrays_are_checked_before_the_call():
+    """The lesser/greater binding refuses host occupation arrays shorter than
+    the batch before reaching the library (no device needed)."""
+    import numpy as np
+    from paper_2508_19138_amd import qtx_rgf as Q
+    ctx = Q.Context.__new__(Q.Context)            # no device: the check comes first
+    with pytest.raises(ValueError):
+        Q.Context.obc_lesser_greater(ctx, 4, 3, None, 0, np.ones(2), np.ones(3), None, None)
