@@ -499,3 +499,28 @@ def test_overlapping_outputs_are_rejected(ctx):
         with pytest.raises(Q.QtxError) as ei:
             call()
         assert ei.value.status == Q.QTX_ERR_INVALID_ARG
+
+
+def test_many_energies_small_blocks(ctx):
+    """1500 energies of b = 4 (one norm chunk per matrix, a wide grid):
+    fixed point, decimation and Lyapunov doubling on sampled energies."""
+    from oracle import obc_sancho_rubio_steps, obc_lyapunov_doubling
+    b, ne = 4, 1500
+    E = np.linspace(-2.0, 2.0, ne)
+    m, n, np_ = synth.lead_blocks(41, b, E, eta=0.05)
+    x0 = np.zeros((ne, b, b), np.complex128)
+    x, sig, upd, info = _run(ctx, m, n, np_, x0, 3)
+    xs, sigs, cpl, infos = _run_sr(ctx, m, n, np_, 3)
+    a, q = synth.lyapunov_blocks(42, b, ne)
+    w, rest = _run_lyap(ctx, a, q, None, 3, "doubling")
+    assert np.all(info == 0) and np.all(infos == 0)
+    for e in (0, 1, 749, 1498, 1499):
+        rx, rs, ru = obc_fixed_point(m[e], n, np_, x0[e], 3)
+        assert float(block_rel_err(x[e][None], rx[None])[0]) < TOL
+        assert abs(upd[e] - ru) <= 1e-8 * ru + 1e-12
+        rx, rs, rc = obc_sancho_rubio_steps(m[e], n, np_, 3)
+        assert float(block_rel_err(xs[e][None], rx[None])[0]) < TOL
+        assert abs(cpl[e] - rc) <= 1e-8 * rc + 1e-14
+        rw, rr = obc_lyapunov_doubling(a[e], q[e], 3)
+        assert float(block_rel_err(w[e][None], rw[None])[0]) < TOL
+        assert abs(rest[e] - rr) <= 1e-8 * rr + 1e-14
