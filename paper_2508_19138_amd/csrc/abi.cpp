@@ -768,8 +768,8 @@ qtx_status qtx_rgf_obc_sancho_rubio(qtx_rgf_ctx* c, int32_t b, int32_t batch, co
   return QTX_OK;
 }
 
-// D_e = z_e Sigma^R_e + g_e (Sigma^R_e)^dagger with per-energy coefficients:
-// one adjoint-combination descriptor per energy, merged into few launches.
+// Both outputs in one pass over the retarded blocks: the per-energy
+// occupations go to the device once, then one launch over (energy, tile).
 qtx_status qtx_rgf_obc_lesser_greater(qtx_rgf_ctx* c, int32_t b, int32_t batch,
                                       const void* sigma_r, int64_t s_sr, const double* f,
                                       const double* one_minus_f, void* sigma_l,
@@ -793,38 +793,17 @@ qtx_status qtx_rgf_obc_lesser_greater(qtx_rgf_ctx* c, int32_t b, int32_t batch,
   c->err.clear();
   try {
     HIPCHK(c, hipSetDevice(c->device));
-    Lane L;
-    constexpr int kPerOp = 1024;              // descriptors per merged launch
-    auto add = [&](void* out, const double* occ, double sign) {
-      if (!out) return;
-      for (int e0 = 0; e0 < batch; e0 += kPerOp) {
-        const int cnt = std::min(kPerOp, batch - e0);
-        Op o;
-        o.k = OpK::Trans;
-        o.first = (int)L.td.size();
-        o.count = cnt;
-        for (int e = e0; e < e0 + cnt; ++e) {
-          // Sigma^< = -f (S - S^dag), Sigma^> = (1 - f)(S - S^dag)
-          const double w = sign * occ[e];
-          TransDesc t{};
-          t.C = nullptr;
-          t.Z = (const double2*)sigma_r + (long long)e * s_sr;
-          t.D = (double2*)out + (long long)e * bb;
-          t.sC = 0; t.sZ = bb; t.sD = bb;
-          t.a = zc{0.0, 0.0};
-          t.z = zc{w, 0.0};
-          t.g = zc{-w, 0.0};
-          t.b = b; t.batch = 1;
-          L.td.push_back(t);
-        }
-        o.bytes = 32.0 * (double)bb * cnt;
-        L.ops.push_back(o);
-      }
-    };
-    add(sigma_l, f, -1.0);
-    add(sigma_g, one_minus_f, 1.0);
-    std::vector<Lane*> lp{&L};
-    run_lanes_to_end(c, lp);
+    std::vector<double> occ(2 * (size_t)batch);
+    for (int e = 0; e < batch; ++e) {
+      occ[2 * (size_t)e] = f ? f[e] : 0.0;
+      occ[2 * (size_t)e + 1] = one_minus_f ? one_minus_f[e] : 0.0;
+    }
+    ensure(c, &c->aux, &c->aux_bytes, occ.size() * sizeof(double) + 256);
+    const hipStream_t st = c->pool->exe(0).stream();
+    HIPCHK(c, hipMemcpyAsync(c->aux, occ.data(), occ.size() * sizeof(double),
+                             hipMemcpyHostToDevice, st));
+    HIPCHK(c, launch_lesser_greater(sigma_r, s_sr, (const double*)c->aux, sigma_l, sigma_g, b,
+                                    batch, st));
     c->pool->exe(0).sync_and_collect(c->stats);
   } catch (const Fail& fl) {
     if (c->err.empty()) c->err = fl.what;

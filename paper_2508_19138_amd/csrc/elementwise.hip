@@ -127,6 +127,49 @@ void transcomb_kernel(FlatLaunch L) {
   }
 }
 
+// Lesser/greater boundary blocks from the retarded one, both outputs in one
+// pass: d = S - S^dagger per 32 x 32 tile (the transposed tile through LDS),
+// then L = -f_e d and G = (1 - f_e) d.  Grid: batch x trans_tiles(b).
+__global__ __launch_bounds__(256)
+void lesser_greater_kernel(const double2* __restrict__ S, long long sS,
+                           const double* __restrict__ occ, double2* __restrict__ L,
+                           double2* __restrict__ G, int b) {
+  __shared__ double2 tile[kTransTile][kTransTile + 1];
+  const int tiles = trans_tiles(b);
+  const int tilesC = (b + kTransTile - 1) / kTransTile;
+  const long long e = blockIdx.x / tiles;
+  const int tl = blockIdx.x % tiles;
+  const int r0 = (tl / tilesC) * kTransTile;
+  const int c0 = (tl % tilesC) * kTransTile;
+  const long long bb = (long long)b * b;
+  const double2* Se = S + e * sS;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  constexpr int kRows = kTransTile / 8;
+  // tile[i][j] = S[c0 + i][r0 + j]; out-of-range slots read element 0
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    const int zr = c0 + ty + 8 * k, zc = r0 + tx;
+    const bool ok = zr < b && zc < b;
+    double2 v = Se[ok ? (long long)zr * b + zc : 0];
+    if (!ok) v = make_double2(0.0, 0.0);
+    tile[ty + 8 * k][tx] = v;
+  }
+  __syncthreads();
+  const double f = occ[2 * e], g = occ[2 * e + 1];
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    const int r = r0 + ty + 8 * k, c = c0 + tx;
+    if (r < b && c < b) {
+      const double2 s = Se[(long long)r * b + c];
+      const double2 t = tile[tx][ty + 8 * k];          // S[c][r]
+      const double dx = s.x - t.x, dy = s.y + t.y;     // (S - S^dagger)[r][c]
+      const long long q = e * bb + (long long)r * b + c;
+      if (L) L[q] = make_double2(-f * dx, -f * dy);
+      if (G) G[q] = make_double2(g * dx, g * dy);
+    }
+  }
+}
+
 // Sums of squared moduli over matrices, in two passes so that every matrix
 // is spread over many workgroups: pass one writes per-chunk partial sums of
 // up to four terms (|u|^2, or |u - v|^2 when v is given), pass two combines
@@ -274,6 +317,15 @@ hipError_t launch_observables(const void* gl_d, const void* gg_d, const void* gl
   hipLaunchKernelGGL(observables_kernel, dim3((unsigned)grid), dim3(256), 0, s,
                      (const double2*)gl_d, (const double2*)gg_d, (const double2*)gl_l,
                      (const double2*)hd, dos, dens, cur, n, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_lesser_greater(const void* S, long long sS, const double* occ, void* L,
+                                 void* G, int b, int batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  const long long grid = (long long)batch * trans_tiles(b);
+  hipLaunchKernelGGL(lesser_greater_kernel, dim3((unsigned)grid), dim3(256), 0, s,
+                     (const double2*)S, sS, occ, (double2*)L, (double2*)G, b);
   return hipGetLastError();
 }
 

@@ -141,6 +141,11 @@ hipError_t launch_transcomb(const FlatLaunch& l, hipStream_t s);
 hipError_t launch_observables(const void* gl_d, const void* gg_d, const void* gl_l,
                               const void* hd, double* dos, double* dens, double* cur, int n,
                               int b, int batch, hipStream_t s);
+// L_e = -f_e (S_e - S_e^dagger), G_e = (1 - f_e)(S_e - S_e^dagger) with
+// occ[2e] = f_e, occ[2e + 1] = 1 - f_e (device); S_e at stride sS (0 = shared),
+// L and G contiguous, either may be null.
+hipError_t launch_lesser_greater(const void* S, long long sS, const double* occ, void* L,
+                                 void* G, int b, int batch, hipStream_t s);
 // Per-matrix norms in two passes (partial sums per chunk, then per matrix);
 // `part` is device scratch of norm_scratch_bytes(bb, batch) bytes.
 constexpr long long kNormChunkElems = 8192;
