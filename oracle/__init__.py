@@ -20,6 +20,9 @@ paper (arXiv 2508.19138, "QuaTrEx"):
                  continuants (independent pin for block size 1).
 * ``observables`` - local density of states, charge density and current
                  from the selected blocks (Sec. "Observables").
+* ``nested``   - nested-dissection selected inversion (the partitioned
+                 solver of Sec. 4.4): per-partition elimination, the reduced
+                 system on the separators, per-partition recovery.
 * ``obc``      - the lead surface function of Sec. "Retarded OBC": the
                  fixed-point iteration of Eq. (naive) and Sancho-Rubio
                  decimation, the boundary block n x n', and the
