@@ -32,7 +32,7 @@ paper (arXiv 2508.19138, "QuaTrEx"):
 All arithmetic is complex128 (IEEE binary64), the paper's precision.
 """
 
-from .rgf import rgf_selected, rgf_selected_batch
+from .rgf import rgf_selected
 from .dense import dense_from_bt, dense_selected
 from .assembly import assemble_g, assemble_w, w_retarded_diag
 from .chain import chain_closed_form, chain_lead_self_energy
@@ -43,7 +43,7 @@ from .obc import (obc_fixed_point, obc_sancho_rubio, obc_sancho_rubio_steps,
 from .observables import observables
 
 __all__ = [
-    "rgf_selected", "rgf_selected_batch", "dense_from_bt", "dense_selected",
+    "rgf_selected", "dense_from_bt", "dense_selected",
     "assemble_g", "assemble_w", "w_retarded_diag", "chain_closed_form",
     "chain_lead_self_energy", "tridiag_inverse_selected", "rgf_flops",
     "w_assembly_flops", "obc_fixed_point", "obc_sancho_rubio",

@@ -24,8 +24,14 @@ and the steps are the scheme's three phases:
        X_IS = -A_II^{-1} A_IS X_SS,   X_SI = -X_SS A_SI A_II^{-1},
        X_II = A_II^{-1} + A_II^{-1} A_IS X_SS A_SI A_II^{-1}.
 
-The selected blocks of X^R = A^{-1} (diagonal, first off-diagonals) are read
-from the un-permuted result.  Plain dense arithmetic per step (complex128),
+The lesser/greater solutions X^s = A^{-1} B^s A^{-dagger} follow the same
+three phases: the right-hand side is permuted like A and carried through
+the block factorisation A = L diag(A_II, S) U, which gives the reduced
+right-hand side of the separators in phase 1, X^s_SS = X_SS B~ X_SS^dagger
+in phase 2 and the interior blocks in phase 3 (formulas in the code).
+
+The selected blocks (diagonal, first off-diagonals) are read from the
+un-permuted results.  Plain dense arithmetic per step (complex128),
 meant to be checked by eye; pins in tests/test_oracle_nested.py.
 """
 
@@ -67,15 +73,23 @@ def _dense(d, u, l):
     return A
 
 
-def nested_dissection_selected(Mt, P):
-    """Selected blocks of X^R = Mt^{-1} by the partitioned scheme.
+def nested_dissection_selected(Mt, P, Bs=()):
+    """Selected blocks of X^R = Mt^{-1} and X^s = X^R B^s X^R^dagger by the
+    partitioned scheme.
 
-    Mt: (diag[n,b,b], upper[n-1,b,b], lower[n-1,b,b]); P: partitions.
-    Returns ((diag, upper, lower) of X^R, reduced system S (dense, separator
-    order), separator block indices)."""
+    Mt: (diag[n,b,b], upper[n-1,b,b], lower[n-1,b,b]); P: partitions; Bs:
+    right-hand sides B^s as triples of the same shape (general blocks, no
+    symmetry assumed).  Returns a dict with
+      XR   (diag, upper, lower) of X^R,
+      XS   [(diag, upper, lower) of X^s per right-hand side],
+      S    reduced system (dense, separator order),
+      BS   [reduced right-hand side per B^s (dense, separator order)],
+      sep  separator block indices.
+    """
     d, u, l = (np.asarray(t, dtype=np.complex128) for t in Mt)
     n, b = d.shape[0], d.shape[1]
     A = _dense(d, u, l)
+    Bd = [_dense(*(np.asarray(t, dtype=np.complex128) for t in B)) for B in Bs]
     sep = separators(n, P)
     parts = partitions(n, P)
     interior = [[i for i in range(lo, hi) if i not in sep] for lo, hi in parts]
@@ -86,32 +100,60 @@ def nested_dissection_selected(Mt, P):
             if blocks else np.zeros(0, int)
 
     rI, rS = rows(inter), rows(sep)
-    A_II = A[np.ix_(rI, rI)]
-    A_IS = A[np.ix_(rI, rS)]
-    A_SI = A[np.ix_(rS, rI)]
-    A_SS = A[np.ix_(rS, rS)]
+    cut = lambda M, r, c: M[np.ix_(r, c)]
+    A_II, A_IS, A_SI, A_SS = cut(A, rI, rI), cut(A, rI, rS), cut(A, rS, rI), cut(A, rS, rS)
+    h = lambda M: M.conj().T
     # phase 1: interiors independently (A_II is block diagonal by partition)
-    iA_II = np.zeros_like(A_II)
+    a = np.zeros_like(A_II)
     off = 0
     for blk in interior:
         k = len(blk) * b
         if k:
-            iA_II[off:off + k, off:off + k] = np.linalg.inv(A_II[off:off + k, off:off + k])
+            a[off:off + k, off:off + k] = np.linalg.inv(A_II[off:off + k, off:off + k])
         off += k
     # phase 2: the reduced system on the separators
-    S = A_SS - A_SI @ iA_II @ A_IS
+    S = A_SS - A_SI @ a @ A_IS
     X_SS = np.linalg.inv(S)
     # phase 3: interiors independently
-    X_IS = -iA_II @ A_IS @ X_SS
-    X_SI = -X_SS @ A_SI @ iA_II
-    X_II = iA_II + iA_II @ A_IS @ X_SS @ A_SI @ iA_II
+    X_IS = -a @ A_IS @ X_SS
+    X_SI = -X_SS @ A_SI @ a
+    X_II = a + a @ A_IS @ X_SS @ A_SI @ a
     X = np.zeros_like(A)
     X[np.ix_(rI, rI)] = X_II
     X[np.ix_(rI, rS)] = X_IS
     X[np.ix_(rS, rI)] = X_SI
     X[np.ix_(rS, rS)] = X_SS
+
+    # Lesser/greater: with A = L diag(A_II, S) U (L, U unit block
+    # triangular), X^s = U^{-1} diag(a, X_SS) [L^{-1} B L^{-dagger}]
+    # diag(a, X_SS)^dagger U^{-dagger}; every factor is applied in turn.
+    XSs, BSs = [], []
+    for B in Bd:
+        B_II, B_IS, B_SI, B_SS = cut(B, rI, rI), cut(B, rI, rS), cut(B, rS, rI), cut(B, rS, rS)
+        # phase 1: the reduced right-hand side (L^{-1} B L^{-dagger})_SS
+        BS = B_SS - A_SI @ a @ B_IS - B_SI @ h(a) @ h(A_SI) + A_SI @ a @ B_II @ h(a) @ h(A_SI)
+        # phase 2: the separators' block of the solution
+        XS_SS = X_SS @ BS @ h(X_SS)
+        # phase 3: the interiors
+        C_IS = a @ (B_IS - B_II @ h(a) @ h(A_SI)) @ h(X_SS)
+        C_SI = X_SS @ (B_SI - A_SI @ a @ B_II) @ h(a)
+        XS_IS = C_IS - a @ A_IS @ XS_SS
+        XS_SI = C_SI - XS_SS @ h(A_IS) @ h(a)
+        XS_II = (a @ B_II @ h(a) - a @ A_IS @ C_SI - C_IS @ h(A_IS) @ h(a)
+                 + a @ A_IS @ XS_SS @ h(A_IS) @ h(a))
+        Y = np.zeros_like(A)
+        Y[np.ix_(rI, rI)] = XS_II
+        Y[np.ix_(rI, rS)] = XS_IS
+        Y[np.ix_(rS, rI)] = XS_SI
+        Y[np.ix_(rS, rS)] = XS_SS
+        XSs.append(_selected(Y, n, b))
+        BSs.append(BS)
+    return {"XR": _selected(X, n, b), "XS": XSs, "S": S, "BS": BSs, "sep": sep}
+
+
+def _selected(X, n, b):
     blk = lambda i, j: X[i * b:(i + 1) * b, j * b:(j + 1) * b]
-    XR = (np.stack([blk(i, i) for i in range(n)]),
-          np.stack([blk(i, i + 1) for i in range(n - 1)]),
-          np.stack([blk(i + 1, i) for i in range(n - 1)]))
-    return XR, S, sep
+    z = np.zeros((0, b, b), np.complex128)
+    return (np.stack([blk(i, i) for i in range(n)]),
+            np.stack([blk(i, i + 1) for i in range(n - 1)]) if n > 1 else z,
+            np.stack([blk(i + 1, i) for i in range(n - 1)]) if n > 1 else z)

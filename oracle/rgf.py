@@ -114,26 +114,3 @@ def rgf_selected(Mt, Bs=()):
     XR = (XRd, XRu, XRl)
     XS = [(XSd[s], XSu[s], XSl[s]) for s in range(len(Bs))]
     return XR, XS
-
-
-def rgf_selected_batch(Mt_batch, Bs_batch=None):
-    """Loop of ``rgf_selected`` over energies.
-
-    Mt_batch : (diag[N_E,n,b,b], upper[N_E,n-1,b,b], lower[N_E,n-1,b,b])
-    Bs_batch : sequence of such triples (one per right-hand side), or None
-    Returns (XR, [XS...]) with a leading energy axis on every array.
-    """
-    Md, Mu, Ml = Mt_batch
-    ne = Md.shape[0]
-    Bs_batch = list(Bs_batch or [])
-    outR = [np.empty_like(Md), np.empty_like(Mu), np.empty_like(Ml)]
-    outS = [[np.empty_like(Md), np.empty_like(Mu), np.empty_like(Ml)]
-            for _ in Bs_batch]
-    for e in range(ne):
-        Bs = [(B[0][e], B[1][e], B[2][e]) for B in Bs_batch]
-        XR, XS = rgf_selected((Md[e], Mu[e], Ml[e]), Bs)
-        for k in range(3):
-            outR[k][e] = XR[k]
-            for s in range(len(Bs_batch)):
-                outS[s][k][e] = XS[s][k]
-    return tuple(outR), [tuple(o) for o in outS]

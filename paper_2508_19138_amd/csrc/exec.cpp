@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <filesystem>
 #include <fstream>
 #include <sstream>
 
@@ -60,10 +61,11 @@ void Tuner::load() {
 void Tuner::save() const {
   const std::string p = cache_path();
   const size_t slash = p.rfind('/');
-  if (slash != std::string::npos) {
-    std::string dir = p.substr(0, slash);
-    std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
-    (void)!std::system(cmd.c_str());
+  if (slash != std::string::npos && slash > 0) {
+    // in-process directory creation: no child process is started from a
+    // process that has initialised the GPU
+    std::error_code ec;
+    std::filesystem::create_directories(p.substr(0, slash), ec);
   }
   std::ofstream f(p);
   if (!f) return;

@@ -267,15 +267,97 @@ def test_assemble_w_dense():
         assert np.abs(WR[i] - Wd[i * b:(i + 1) * b, i * b:(i + 1) * b]).max() < 1e-12
 
 
+def _place(d, u, l):
+    """Dense matrix of a BT triple, written out block by block (np.block)."""
+    n, b = d.shape[0], d.shape[1]
+    z = np.zeros((b, b), np.complex128)
+    rows = []
+    for i in range(n):
+        row = []
+        for j in range(n):
+            if j == i:
+                row.append(d[i])
+            elif j == i + 1 and u is not None:
+                row.append(u[i])
+            elif i == j + 1 and l is not None:
+                row.append(l[j])
+            else:
+                row.append(z)
+        rows.append(row)
+    return np.block(rows)
+
+
+def _assembly_g_error(assemble):
+    """Largest deviation of assemble_g from E S - H - Sigma^R written densely,
+    over block-diagonal and block-tridiagonal S and Sigma^R (non-Hermitian
+    off-diagonal blocks, so that upper and lower cannot be confused)."""
+    rng = np.random.default_rng(41)
+    n, b = 4, 5
+    H = synth.hermitian_bt(rng, n, b)
+    worst = 0.0
+    for E in (0.37, -1.9):
+        for bt_s in (False, True):
+            for bt_r in (False, True):
+                Sd = np.eye(b)[None] + 0.1 * synth.cn(rng, (n, b, b), 1.0)
+                Su = 0.2 * synth.cn(rng, (n - 1, b, b), 1.0) if bt_s else None
+                Sl = 0.2 * synth.cn(rng, (n - 1, b, b), 1.0) if bt_s else None
+                Rd = synth.cn(rng, (n, b, b), 1.0)
+                Ru = synth.cn(rng, (n - 1, b, b), 1.0) if bt_r else None
+                Rl = synth.cn(rng, (n - 1, b, b), 1.0) if bt_r else None
+                got = assemble(E, H, (Rd, Ru, Rl), (Sd, Su, Sl))
+                ref = E * _place(Sd, Su, Sl) - _place(*H) - _place(Rd, Ru, Rl)
+                worst = max(worst, float(np.abs(_place(*got) - ref).max()))
+    # S omitted means the identity
+    Rd = synth.cn(rng, (n, b, b), 1.0)
+    got = assemble(0.5, H, (Rd, None, None))
+    ref = 0.5 * np.eye(n * b) - _place(*H) - _place(Rd, None, None)
+    return max(worst, float(np.abs(_place(*got) - ref).max()))
+
+
 def test_assemble_g_definition():
-    p = synth.g_problem(3, 4, 5, n_e=2)
-    E = p["energies"][1]
-    sr = tuple(None if t is None else t[1] for t in p["sigma_r"])
-    d, u, l = assemble_g(E, p["H"], sr)
-    Hd = dense_from_bt(*p["H"])
-    Sd = dense_from_bt(p["sigma_r"][0][1], np.zeros((3, 5, 5)), np.zeros((3, 5, 5)))
-    ref = E * np.eye(20) - Hd - Sd
-    assert np.abs(dense_from_bt(d, u, l) - ref).max() == 0.0
+    """Table quantities: A = E S - H - Sigma^R, including the off-diagonal
+    blocks of S and Sigma^R."""
+    assert _assembly_g_error(assemble_g) < 1e-14
+
+
+def _w_products_by_pattern(n, n_rhs, want_wr):
+    """Block products of the W assembly counted from block sparsity patterns
+    alone: a product A_ik B_kj is needed once for every k where both blocks
+    are structurally nonzero, for the blocks (i, j) the result keeps."""
+    band = lambda w: np.array([[1 if abs(i - j) <= w else 0 for j in range(n)]
+                               for i in range(n)], dtype=np.int64)
+    V, P, X = band(1), band(1), band(1)
+    VP = V @ P                              # products per block of V P
+    keep = band(1)                          # truncation to the BT pattern
+    lhs = int(np.sum(VP * keep))
+    # B^s: diagonal and upper blocks of (V P^s) V^dagger; V^dagger has V's pattern
+    need_B = np.array([[1 if j in (i, i + 1) else 0 for j in range(n)] for i in range(n)])
+    T = (VP > 0).astype(np.int64)
+    used_T = np.zeros((n, n), np.int64)     # blocks of V P^s that B^s reads
+    rhs_B = 0
+    for i in range(n):
+        for j in range(n):
+            if need_B[i, j]:
+                for k in range(n):
+                    if T[i, k] and V[j, k]:
+                        rhs_B += 1
+                        used_T[i, k] = 1
+    rhs_T = int(np.sum(VP * used_T))
+    total = lhs + n_rhs * (rhs_T + rhs_B)
+    if want_wr:
+        total += int(np.trace(X @ V))       # (X^R V)_ii over selected X^R blocks
+    return total
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 7])
+def test_w_assembly_products_from_patterns(n):
+    """The W assembly's product count against an independent count from the
+    block sparsity patterns, and the closed form 7n - 6 of trunc(V P^R)."""
+    from oracle.flops import gemm_eq_w_assembly
+    for n_rhs in (0, 1, 2):
+        for wr in (False, True):
+            assert gemm_eq_w_assembly(n, n_rhs, wr) == _w_products_by_pattern(n, n_rhs, wr)
+    assert gemm_eq_w_assembly(n, 0, False) == 7 * n - 6
 
 
 def test_generator_draws():

@@ -1,8 +1,12 @@
 """Pins of the nested-dissection oracle (Sec. 4.4, partitioned solver).
 
-* The selected blocks equal the dense definition (Eq. system-solve) for
-  general non-symmetric block-tridiagonal matrices, for 2..5 partitions,
-  block sizes 1 and 3, and uneven partition sizes.
+* The selected blocks of X^R and of X^s = A^{-1} B A^{-dagger} equal the
+  dense definition (Eq. system-solve) for general non-symmetric
+  block-tridiagonal A and B, for 2..5 partitions, block sizes 1 to 3, and
+  uneven partition sizes.
+* The reduced right-hand side is what the separators see: X^s_SS =
+  S^{-1} B~ S^{-dagger} equals the separator block of the dense X^s, and B~
+  is block tridiagonal in separator order like S.
 * The reduced system has the structure the scheme predicts: block
   tridiagonal in separator order, where the two separators of a middle
   partition are coupled only through fill-in (they are not neighbours in A),
@@ -33,10 +37,13 @@ def _rel(a, b):
                                    (10, 1, 3)])
 def test_selected_blocks_match_dense(n, b, P):
     Mt = _bt(100 * n + P, n, b)
-    XR, S, sep = nested_dissection_selected(Mt, P)
-    ref = dense_selected(Mt)[0]
+    Bs = [_bt(100 * n + P + 1, n, b), _bt(100 * n + P + 2, n, b)]
+    r = nested_dissection_selected(Mt, P, Bs)
+    refR, refS = dense_selected(Mt, Bs)
     for k in range(3):
-        assert _rel(XR[k], ref[k]) < 1e-12
+        assert _rel(r["XR"][k], refR[k]) < 1e-12
+        for s in range(2):
+            assert _rel(r["XS"][s][k], refS[s][k]) < 1e-12
 
 
 def test_partitions_and_separators():
@@ -52,7 +59,9 @@ def test_partitions_and_separators():
 def test_reduced_system_structure_and_schur_identity():
     n, b, P = 12, 2, 4
     Mt = _bt(5, n, b)
-    XR, S, sep = nested_dissection_selected(Mt, P)
+    B = _bt(6, n, b)
+    r = nested_dissection_selected(Mt, P, [B])
+    S, sep, BS = r["S"], r["sep"], r["BS"][0]
     m = len(sep)
     Sb = lambda i, j: S[i * b:(i + 1) * b, j * b:(j + 1) * b]
     # block tridiagonal in separator order
@@ -74,4 +83,21 @@ def test_reduced_system_structure_and_schur_identity():
             A[i * b:(i + 1) * b, (i + 1) * b:(i + 2) * b] = u[i]
             A[(i + 1) * b:(i + 2) * b, i * b:(i + 1) * b] = l[i]
     rS = np.concatenate([np.arange(k * b, (k + 1) * b) for k in sep])
-    assert _rel(np.linalg.inv(S), np.linalg.inv(A)[np.ix_(rS, rS)]) < 1e-12
+    Ai = np.linalg.inv(A)
+    assert _rel(np.linalg.inv(S), Ai[np.ix_(rS, rS)]) < 1e-12
+    # the reduced right-hand side: block tridiagonal in separator order, and
+    # S^{-1} B~ S^{-dagger} is the separator block of the dense X^s
+    Bb = lambda i, j: BS[i * b:(i + 1) * b, j * b:(j + 1) * b]
+    for i in range(m):
+        for j in range(m):
+            if abs(i - j) > 1:
+                assert np.linalg.norm(Bb(i, j)) < 1e-12 * np.linalg.norm(BS)
+    Bdense = np.zeros_like(A)
+    for i in range(n):
+        Bdense[i * b:(i + 1) * b, i * b:(i + 1) * b] = B[0][i]
+        if i + 1 < n:
+            Bdense[i * b:(i + 1) * b, (i + 1) * b:(i + 2) * b] = B[1][i]
+            Bdense[(i + 1) * b:(i + 2) * b, i * b:(i + 1) * b] = B[2][i]
+    XSd = Ai @ Bdense @ Ai.conj().T
+    Si = np.linalg.inv(S)
+    assert _rel(Si @ BS @ Si.conj().T, XSd[np.ix_(rS, rS)]) < 1e-12
