@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--cpu-energies", type=int, default=2,
                     help="energies in the CPU-oracle sample (0 = skip)")
+    ap.add_argument("--cpu-reps", type=int, default=3,
+                    help="repetitions of the CPU-oracle sample (median reported)")
     ap.add_argument("--bt-sigma", action="store_true",
                     help="plain/mixed: self-energies with block-tridiagonal parts (general "
                          "path, F_BT flop model); use --energies 96 to fit HBM")
@@ -141,8 +143,11 @@ def build_inputs(n, b, n_e, seed, bt_sigma=False):
     return p, H, sig
 
 
-def cpu_baseline(p, n_cpu):
-    """Time the oracle (as it stands) on `n_cpu` energies of the workload."""
+def cpu_baseline(p, n_cpu, reps=3):
+    """Time the oracle (as it stands) on `n_cpu` energies of the workload,
+    `reps` times; the median repetition is reported.  Also returns the
+    oracle's selected blocks of those energies (from the first repetition)
+    so the caller can compare the GPU results with them."""
     from oracle import rgf_selected, assemble_g
     from paper_2508_19138_amd import synth
     try:
@@ -157,17 +162,40 @@ def cpu_baseline(p, n_cpu):
         np.linspace(0, len(E_all) - 1, n_cpu).astype(int))
     sr, sl, sg = p["sigma_scalars"]
     z = np.zeros((n - 1, b, b), np.complex128)
-    t0 = time.perf_counter()
-    for e in idx:
-        A = assemble_g(E_all[e], p["H"], (synth.eye_blocks(sr[e], b), None, None))
-        rgf_selected(A, [(synth.eye_blocks(sl[e], b), z, z),
-                         (synth.eye_blocks(sg[e], b), z, z)])
-    dt = time.perf_counter() - t0
-    return {"value": len(idx) / dt, "unit": "energy-points/s", "cores": int(threads),
+    times, results = [], {}
+    for r in range(max(1, reps)):
+        t0 = time.perf_counter()
+        for e in idx:
+            A = assemble_g(E_all[e], p["H"], (synth.eye_blocks(sr[e], b), None, None))
+            out = rgf_selected(A, [(synth.eye_blocks(sl[e], b), z, z),
+                                   (synth.eye_blocks(sg[e], b), z, z)])
+            if r == 0:
+                results[e] = out
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    info = {"value": len(idx) / dt, "unit": "energy-points/s", "cores": int(threads),
             "kind": "oracle",
             "sample": "%d of the %d energies (indices %s) of the same workload, "
-                      "assembly + full forward/backward recursion, NumPy/OpenBLAS, "
-                      "%.1f s" % (len(idx), len(E_all), idx, dt)}
+                      "assembly + full forward/backward recursion, NumPy/OpenBLAS; "
+                      "median of %d repetitions (%s s)"
+                      % (len(idx), len(E_all), idx, len(times),
+                         ", ".join("%.2f" % t for t in times))}
+    return info, results
+
+
+def oracle_max_error(results, XR, XL, XG):
+    """Largest per-block relative Frobenius error of the device outputs
+    against the oracle over the sampled energies (all nine outputs)."""
+    worst = 0.0
+    for e, (OR, OS) in results.items():
+        for X, R in zip((XR, XL, XG), (OR,) + tuple(OS)):
+            for x, r in zip(X, R):
+                g = x[e].cpu().numpy()
+                num = np.linalg.norm(g - r, axis=(-2, -1))
+                den = np.linalg.norm(r, axis=(-2, -1))
+                den = np.where(den < 1e-13 * den.max(), den.max(), den)
+                worst = max(worst, float(np.max(num / np.where(den == 0, 1.0, den))))
+    return worst
 
 
 def _gemm_roofline(ctx, cls, peak, label):
@@ -209,9 +237,12 @@ def run_plain(args, mixed=False):
         assert prob.status == 0, prob.status
     torch.cuda.synchronize()
     ctx.reset_stats()
+    step_s = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.solve_batch([prob])
+        ts = time.perf_counter()
+        ctx.solve_batch([prob])               # synchronous: returns when done
+        step_s.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     assert prob.status == 0, prob.status
@@ -249,9 +280,10 @@ def run_plain(args, mixed=False):
         torch.cuda.synchronize()
         del x, y
 
-    cpu = None
+    cpu, oracle_err = None, None
     if args.cpu_energies > 0 and not mixed and not args.bt_sigma:
-        cpu = cpu_baseline(p, args.cpu_energies)
+        cpu, ref = cpu_baseline(p, args.cpu_energies, args.cpu_reps)
+        oracle_err = oracle_max_error(ref, XR, XL, XG)
 
     out = {
         "metric": "RGF energy-points/s + % FP64 MFMA peak; p50/p99 solve latency",
@@ -270,6 +302,11 @@ def run_plain(args, mixed=False):
         "flops_per_energy": flops_e,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "latency_s": {"p50": round(float(np.percentile(step_s, 50)), 4),
+                      "p99": round(float(np.percentile(step_s, 99)), 4),
+                      "what": "wall time of one solve_batch call (all %d energies) "
+                              "over the %d timed steps" % (n_e, args.steps)},
+        "oracle_max_block_rel_err": oracle_err,
         "context": PAPER_CONTEXT,
     }
     if mixed:

@@ -357,7 +357,7 @@ def test_mixed_precision_error_vs_fp64_oracle(ctx):
             for part, g_, r_ in zip("dul", _sel(got, e), ref):
                 worst[name + part] = max(worst.get(name + part, 0.0), max_rel_err(g_, r_))
     print("mixed-precision max block rel err:", worst)
-    assert max(worst.values()) < 1e-3
+    assert max(worst.values()) < 1e-4
     assert max(worst.values()) > 1e-9          # the FP32 path really ran
 
 
@@ -373,6 +373,40 @@ def test_maximum_block_size_solve(ctx):
     assert triple_err(_sel(XR, 0), OR) < TOL
     assert triple_err(_sel(XL, 0), OL) < TOL
     assert triple_err(_sel(XG, 0), OG) < TOL
+
+
+def test_upper_triangle_only_lesser_greater_outputs(ctx):
+    """Symmetric storage (Sec. 4.2): with the lower blocks of X^< and X^>
+    not requested (NULL), the diagonal and upper blocks are the same bits as
+    with full storage and match the oracle; X^s_{i+1,i} = -(X^s_{i,i+1})^dagger
+    is left to the reader."""
+    gh = _gh()
+    n, b, n_e = 6, 48, 3
+    p = synth.g_problem(61, n, b, n_e=n_e, bt_sigma=True)
+    E = np.ascontiguousarray(p["energies"])
+    H = (gh.dev(p["H"][0]), gh.dev(p["H"][1]), None)
+    sr = tuple(gh.dev(t) for t in p["sigma_r"])
+    sl = (gh.dev(p["sigma_l"][0]), gh.dev(p["sigma_l"][1]), None)
+    sg = (gh.dev(p["sigma_g"][0]), gh.dev(p["sigma_g"][1]), None)
+    full = [gh.outputs(n_e, n, b) for _ in range(3)]
+    half = [gh.outputs(n_e, n, b)] + [gh.outputs(n_e, n, b, with_lower=False) for _ in range(2)]
+    for outs in (full, half):
+        prob = Q.make_g_problem(E, H, sr, sl, sg, *outs)
+        ctx.solve_batch([prob])
+        assert prob.status == 0
+    torch.cuda.synchronize()
+    for F, Hh in zip(full, half):
+        for k in range(2):
+            assert torch.equal(F[k], Hh[k])
+    adj = lambda T: np.conj(np.swapaxes(T, -1, -2))
+    XL = gh.host(half[1])
+    XG = gh.host(half[2])
+    for e in range(n_e):
+        OR, (OL, OG) = _oracle_g(p, e)
+        for got, ref in ((XL, OL), (XG, OG)):
+            assert max_rel_err(got[0][e], ref[0]) < TOL
+            assert max_rel_err(got[1][e], ref[1]) < TOL
+            assert max_rel_err(-adj(got[1][e]), ref[2]) < TOL
 
 
 def test_empty_batch(ctx):

@@ -1,7 +1,8 @@
 """GPU tests of the request loop (qtx_rgf_submit / qtx_rgf_poll): problems
 submitted one by one, some while others are already running, must each give
-exactly the result of solving them alone with qtx_rgf_solve_batch; failures
-stay with their problem; completions carry consistent timings."""
+exactly the result of solving them alone with qtx_rgf_solve_batch, and that
+result must match the CPU oracle (1e-10 per block); failures stay with their
+problem; completions carry consistent timings."""
 
 import time
 
@@ -12,9 +13,13 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
+from oracle import assemble_g, assemble_w, rgf_selected  # noqa: E402
 from paper_2508_19138_amd import synth  # noqa: E402
 from paper_2508_19138_amd import qtx_rgf as Q  # noqa: E402
+from blockcmp import triple_err  # noqa: E402
 import gpu_helpers as G  # noqa: E402
+
+TOL = 1e-10
 
 
 class Job:
@@ -55,6 +60,26 @@ class Job:
     def results(self):
         torch.cuda.synchronize()
         return [G.host(T) for T in (self.XR, self.XL, self.XG)]
+
+    def oracle_error(self):
+        """Largest per-block error of the device results against the oracle
+        over every energy and output."""
+        p, n = self.p, self.spec["n"]
+        got = self.results()
+        adj = lambda T: np.conj(np.swapaxes(T, -1, -2))
+        worst = 0.0
+        for e in range(self.spec["ne"]):
+            if self.spec["kind"] == "G":
+                A = assemble_g(p["energies"][e], p["H"], (p["sigma_r"][0][e], None, None))
+                z = np.zeros((n - 1,) + p["sigma_l"][0].shape[-2:], np.complex128)
+                Bs = [(p["sigma_l"][0][e], z, z), (p["sigma_g"][0][e], z, z)]
+            else:
+                at = lambda T: tuple(t[e] for t in T)
+                A, Bs = assemble_w(p["V"], at(p["P_r"]), [at(p["P_l"]), at(p["P_g"])])
+            OR, (OL, OG) = rgf_selected(A, Bs)
+            for X, R in zip(got, (OR, OL, OG)):
+                worst = max(worst, triple_err(tuple(t[e] for t in X), R))
+        return worst
 
 
 def _specs(seed, count, bs=(16, 40, 64, 96), ns=(1, 9), ne=(1, 6)):
@@ -121,6 +146,7 @@ def test_served_requests_equal_alone():
         assert cs == [] and pend == 0
     for j, r in zip(jobs, ref):
         _equal(j.results(), r, j.spec)
+        assert j.oracle_error() < TOL, j.spec
 
 
 def test_served_admission_into_small_workspace():
@@ -137,6 +163,7 @@ def test_served_admission_into_small_workspace():
         assert all(c["status"] == Q.QTX_OK for c in done.values())
     for j, r in zip(jobs, ref):
         _equal(j.results(), r, j.spec)
+        assert j.oracle_error() < TOL, j.spec
 
 
 def test_served_failure_stays_with_its_request():
