@@ -134,6 +134,28 @@ def _check_nested(m):
     return worst
 
 
+def _check_nested_blocks(m):
+    """The block form against the dense definition, the Schur identity
+    S^{-1} = (A^{-1})_SS and the separators' block of the dense X^s."""
+    worst = 0.0
+    for n, b, P in ((9, 2, 3), (12, 2, 4)):
+        Mt = _bt(310 + n, n, b)
+        Bs = [_bt(311 + n, n, b)]
+        r = m.nested_dissection_blocks(Mt, P, Bs)
+        refR, refS = dense_selected(Mt, Bs)
+        for k in range(3):
+            worst = max(worst, _rel(r["XR"][k], refR[k]), _rel(r["XS"][0][k], refS[0][k]))
+        A = oracle.dense_from_bt(*Mt)
+        B = oracle.dense_from_bt(*Bs[0])
+        rows = np.concatenate([np.arange(k * b, (k + 1) * b) for k in r["sep"]])
+        Ai = np.linalg.inv(A)
+        Si = np.linalg.inv(r["S"])
+        worst = max(worst, _rel(Si, Ai[np.ix_(rows, rows)]),
+                    _rel(Si @ r["BS"][0] @ Si.conj().T,
+                         (Ai @ B @ Ai.conj().T)[np.ix_(rows, rows)]))
+    return worst
+
+
 # --------------------------------------------------------------- mutations
 
 _CASES = [
@@ -188,6 +210,20 @@ _CASES = [
      "XS_IS = C_IS", _check_nested),
     ("nested", "X^s_SI with A_SI for A_IS^dagger", "XS_SI = C_SI - XS_SS @ h(A_IS) @ h(a)",
      "XS_SI = C_SI - XS_SS @ A_SI @ h(a)", _check_nested),
+    # Sec. 4.4 in block form (per-partition elimination with fill-in)
+    ("nested", "sign of the fill-in column", "qn = -ln @ q", "qn = ln @ q", _check_nested_blocks),
+    ("nested", "fill-in row with the lower coupling", "rn = -lT @ A(c, nx)",
+     "rn = -lT @ A(nx, c)", _check_nested_blocks),
+    ("nested", "top separator's block not updated", "STT = STT - lT @ q", "STT = STT",
+     _check_nested_blocks),
+    ("nested", "right-hand side fill-in without its x^s term",
+     "RnT = [-ln @ RkT[s] - blk(B, nx, c) @ h(lT) + ln @ Rkk[s] @ h(lT)",
+     "RnT = [-ln @ RkT[s] - blk(B, nx, c) @ h(lT)", _check_nested_blocks),
+    ("nested", "backward X^s_kk without the Z terms",
+     " + Zk @ xs[s] + xs[s] @ h(Zk)\n", "\n", _check_nested_blocks),
+    ("nested", "backward X^s_kN without the right-hand side coupling",
+     "XskN.append(-Pk @ XsNN[s] - xs[s] @ h(XNN @ MNk) + x @ RkN[s] @ h(XNN))",
+     "XskN.append(-Pk @ XsNN[s] - xs[s] @ h(XNN @ MNk))", _check_nested_blocks),
 ]
 
 

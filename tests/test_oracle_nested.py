@@ -11,13 +11,18 @@
   tridiagonal in separator order, where the two separators of a middle
   partition are coupled only through fill-in (they are not neighbours in A),
   and it equals the inverse of the separator-restricted block of A^{-1}.
+* The block form (each partition's elimination with fill-in, as one device
+  would run it) gives the same selected blocks as the dense definition and
+  the same reduced system and right-hand sides, including middle
+  partitions of two blocks (no interior) and block size 1.
 """
 
 import numpy as np
 import pytest
 
 from oracle import dense_selected
-from oracle.nested import nested_dissection_selected, partitions, separators
+from oracle.nested import (nested_dissection_blocks, nested_dissection_selected, partitions,
+                           separators)
 from paper_2508_19138_amd import synth
 
 
@@ -101,3 +106,21 @@ def test_reduced_system_structure_and_schur_identity():
     XSd = Ai @ Bdense @ Ai.conj().T
     Si = np.linalg.inv(S)
     assert _rel(Si @ BS @ Si.conj().T, XSd[np.ix_(rS, rS)]) < 1e-12
+
+
+@pytest.mark.parametrize("n,b,P", [(6, 1, 2), (7, 3, 2), (9, 3, 3), (11, 2, 4), (13, 3, 5),
+                                   (8, 2, 4), (2, 2, 2), (3, 2, 2), (12, 2, 6)])
+def test_block_form_matches_dense_and_reduced_system(n, b, P):
+    Mt = _bt(7 * n + P, n, b)
+    Bs = [_bt(7 * n + P + 1, n, b), _bt(7 * n + P + 2, n, b)]
+    r = nested_dissection_blocks(Mt, P, Bs)
+    rd = nested_dissection_selected(Mt, P, Bs)
+    refR, refS = dense_selected(Mt, Bs)
+    for k in range(3):
+        assert _rel(r["XR"][k], refR[k]) < 1e-12
+        for s in range(2):
+            assert _rel(r["XS"][s][k], refS[s][k]) < 1e-12
+    assert r["sep"] == rd["sep"]
+    assert _rel(r["S"], rd["S"]) < 1e-12
+    for s in range(2):
+        assert _rel(r["BS"][s], rd["BS"][s]) < 1e-12
