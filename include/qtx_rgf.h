@@ -271,6 +271,31 @@ qtx_status qtx_rgf_cgemm(qtx_rgf_ctx* ctx, char opa, char opb, int32_t m,
 qtx_status qtx_rgf_zinv(qtx_rgf_ctx* ctx, int32_t b, void* A, void* X,
                         int32_t* info, int32_t batch);
 
+/* Allocation-free variant of qtx_rgf_zinv, for callers that cannot allocate
+ * device memory (code under stream capture into a graph, serving loops that
+ * forbid allocation).  Same arguments, layout and results as qtx_rgf_zinv
+ * (the same kernels run in the same order, so the results are bitwise the
+ * same), with three differences:
+ *   - the work buffers and launch descriptors live in a static device array
+ *     of QTX_NOALLOC_SCRATCH_BYTES (plus 64 KiB of descriptors) that every
+ *     GPU the library runs on holds until the process ends; a call allocates,
+ *     copies and clears nothing, it only launches kernels;
+ *   - the call is asynchronous: it returns once the kernels are queued on
+ *     the context's stream, and the results are ready when that stream's
+ *     work is complete (no wait inside, so it can be captured);
+ *   - batch * (2*16 + 2*64) * 16 * b bytes of panel buffers plus 8 * batch * b
+ *     bytes of pivot bookkeeping (each part rounded up to 256 bytes) must fit
+ *     QTX_NOALLOC_SCRATCH_BYTES; larger calls return QTX_ERR_INVALID_ARG with
+ *     the sizes in qtx_rgf_last_error (e.g. at most 51 matrices of 512, 25 of
+ *     1024).
+ * All calls on one GPU share its array, which keeps the last call's contents
+ * (nothing in it needs to start at zero): calls that overlap in time on one
+ * GPU race on it and must be serialised by the caller (one stream, or
+ * events).  A and X must not be shared with a concurrent call either. */
+#define QTX_NOALLOC_SCRATCH_BYTES (64ull << 20)
+qtx_status qtx_rgf_zinv_noalloc(qtx_rgf_ctx* ctx, int32_t b, void* A, void* X,
+                                int32_t* info, int32_t batch);
+
 /* Retarded open-boundary surface function of a lead (Sec. "Retarded OBC"):
  * the solution x of Eq. (retarded-recursion), x = (m - n x n')^{-1}, by
  * n_iter iterations of Eq. (naive),

@@ -274,6 +274,12 @@ qtx_status qtx_rgf_create(qtx_rgf_ctx** out, int device, uint64_t budget, void* 
   const char* t = std::getenv("QTX_TUNE");
   c->tuner.set_enabled(!(t && t[0] == '0'));
   if (hipSetDevice(device) != hipSuccess) { delete c; return QTX_ERR_HIP; }
+  // the allocation-free inverse's static scratch: its address on this device
+  if (qtx::noalloc_init(device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return QTX_ERR_HIP;
+  }
   if (stream) {
     c->stream = (hipStream_t)stream;
   } else {

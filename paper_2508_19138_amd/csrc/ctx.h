@@ -96,4 +96,10 @@ std::string validate_problem(const qtx_rgf_problem& p);
 // Drain and stop the context's request loop, if it was started.
 void stop_server(qtx_rgf_ctx* c);
 
+// Resolve, once per device and with that device current, the address of the
+// static scratch array of qtx_rgf_zinv_noalloc.
+hipError_t noalloc_init(int device);
+// Scratch bytes qtx_rgf_zinv_noalloc needs for `batch` matrices of size b.
+size_t noalloc_work_bytes(int b, int batch);
+
 }  // namespace qtx

@@ -212,41 +212,6 @@ static int group_cfg(const std::vector<std::pair<Lane*, Op*>>& ops) {
   return cfg;
 }
 
-bool inv_panel_update(const InvDesc& v, int k0, GemmDesc* out) {
-  const int K0 = k0 - k0 % kSuper;
-  const int hi = std::min(v.b, K0 + kSuper);
-  const int nbe = std::min(kPanel, v.b - k0);
-  if (k0 >= v.b || hi - K0 <= nbe) return false;
-  GemmDesc g{};
-  g.M = v.b; g.N = hi - K0; g.K = kPanel;
-  g.A = v.panel; g.sA = (long long)v.b * kPanel; g.lda = kPanel;
-  g.B = (double2*)v.brow + K0; g.sB = (long long)kPanel * v.b; g.ldb = v.b;
-  g.C = (double2*)v.S + K0; g.sC = v.sS; g.ldc = v.b;
-  g.D = (double2*)v.S + K0; g.sD = v.sS; g.ldd = v.b;
-  g.alpha = zc{1.0, 0.0};
-  g.beta = zc{1.0, 0.0};
-  g.batch = v.batch; g.batch2 = 1;
-  g.tiles = gemm_tiles(kGemmInvUpdate, g.M, g.N);
-  *out = g;
-  return true;
-}
-
-bool inv_super_update(const InvDesc& v, int K0, GemmDesc* out) {
-  if (v.b <= K0 || v.b <= kSuper) return false;
-  GemmDesc g{};
-  g.M = v.b; g.N = v.b; g.K = kSuper;
-  g.A = v.spanel; g.sA = (long long)v.b * kSuper; g.lda = kSuper;
-  g.B = v.sbrow; g.sB = (long long)kSuper * v.b; g.ldb = v.b;
-  g.C = v.S; g.sC = v.sS; g.ldc = v.b;
-  g.D = v.S; g.sD = v.sS; g.ldd = v.b;
-  g.alpha = zc{1.0, 0.0};
-  g.beta = zc{1.0, 0.0};
-  g.batch = v.batch; g.batch2 = 1;
-  g.tiles = gemm_tiles(kGemmInvUpdate, g.M, g.N);
-  *out = g;
-  return true;
-}
-
 void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
   const Op& f = *ops[0].second;
   if (f.k == OpK::Gemm) {

@@ -78,14 +78,6 @@ class Tuner {
   std::map<std::string, int> table_;
 };
 
-// Update products of the blocked inverse (see zinv.hip), shared by every
-// launcher of the inverse: the rank-kPanel update of the rest of the
-// super-panel after the panel at column k0 (false: nothing left to update),
-// and the rank-kSuper update of the whole matrix after the super-panel at
-// K0 (false: the matrix has a single super-panel or ends before K0).
-bool inv_panel_update(const InvDesc& v, int k0, GemmDesc* g);
-bool inv_super_update(const InvDesc& v, int K0, GemmDesc* g);
-
 // One kernel launch of a merged schedule.
 struct LaunchRec {
   enum Kind : uint8_t { Gemm, Panel, Gather, Permute, Lin, Trans } kind;

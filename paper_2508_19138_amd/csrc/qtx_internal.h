@@ -104,6 +104,52 @@ hipError_t launch_inv_super_gather(int K0, const FlatLaunch& l, hipStream_t s);
 __host__ __device__ inline int super_gather_chunks(int b) {
   return (int)((2LL * b * kSuper + kGatherItems - 1) / kGatherItems);
 }
+// Tile of the inverse's update products (the kGemmInvUpdate configuration).
+constexpr int kInvUpdTile = 32;
+
+// Update products of the blocked inverse, shared by every launcher of the
+// inverse (host) and by the device-side descriptor set-up of the
+// allocation-free entry point: the rank-kPanel update of the rest of the
+// super-panel after the panel at column k0 (false: nothing left to update),
+// and the rank-kSuper update of the whole matrix after the super-panel at
+// K0 (false: the matrix has a single super-panel or ends before K0).
+__host__ __device__ inline int inv_update_tiles(int M, int N) {
+  return ((M + kInvUpdTile - 1) / kInvUpdTile) * ((N + kInvUpdTile - 1) / kInvUpdTile);
+}
+__host__ __device__ inline bool inv_panel_update(const InvDesc& v, int k0, GemmDesc* out) {
+  const int K0 = k0 - k0 % kSuper;
+  const int hi = v.b < K0 + kSuper ? v.b : K0 + kSuper;
+  const int nbe = kPanel < v.b - k0 ? kPanel : v.b - k0;
+  if (k0 >= v.b || hi - K0 <= nbe) return false;
+  GemmDesc g{};
+  g.M = v.b; g.N = hi - K0; g.K = kPanel;
+  g.A = v.panel; g.sA = (long long)v.b * kPanel; g.lda = kPanel;
+  g.B = (double2*)v.brow + K0; g.sB = (long long)kPanel * v.b; g.ldb = v.b;
+  g.C = (double2*)v.S + K0; g.sC = v.sS; g.ldc = v.b;
+  g.D = (double2*)v.S + K0; g.sD = v.sS; g.ldd = v.b;
+  g.alpha = zc{1.0, 0.0};
+  g.beta = zc{1.0, 0.0};
+  g.batch = v.batch; g.batch2 = 1;
+  g.tiles = inv_update_tiles(g.M, g.N);
+  *out = g;
+  return true;
+}
+__host__ __device__ inline bool inv_super_update(const InvDesc& v, int K0, GemmDesc* out) {
+  if (v.b <= K0 || v.b <= kSuper) return false;
+  GemmDesc g{};
+  g.M = v.b; g.N = v.b; g.K = kSuper;
+  g.A = v.spanel; g.sA = (long long)v.b * kSuper; g.lda = kSuper;
+  g.B = v.sbrow; g.sB = (long long)kSuper * v.b; g.ldb = v.b;
+  g.C = v.S; g.sC = v.sS; g.ldc = v.b;
+  g.D = v.S; g.sD = v.sS; g.ldd = v.b;
+  g.alpha = zc{1.0, 0.0};
+  g.beta = zc{1.0, 0.0};
+  g.batch = v.batch; g.batch2 = 1;
+  g.tiles = inv_update_tiles(g.M, g.N);
+  *out = g;
+  return true;
+}
+
 // Final permutation X[k][p_j] = S[p_k][j]; 8 rows per workgroup.
 constexpr int kPermRows = 8;
 hipError_t launch_inv_permute(const FlatLaunch& l, hipStream_t s);

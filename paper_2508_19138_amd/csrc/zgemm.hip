@@ -64,6 +64,7 @@ typedef Cfg<64, 64, 16, 2, 2> Cfg0;     // general
 typedef Cfg<128, 64, 8, 2, 2> Cfg1;    // large blocks: 64 x 32 per wave
 typedef Cfg<32, 32, 16, 2, 2> Cfg2;     // small blocks
 typedef Cfg2 CfgU;                      // the inverse's update products
+static_assert(CfgU::BM == kInvUpdTile && CfgU::BN == kInvUpdTile, "update tile");
 
 __device__ __forceinline__ int xcd_remap(int w, int G) {
   constexpr int kXcd = 8;

@@ -119,6 +119,8 @@ def lib():
     L.qtx_rgf_zinv.argtypes = [c_ctx, ctypes.c_int32, ctypes.c_void_p,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
     L.qtx_rgf_zinv.restype = ctypes.c_int
+    L.qtx_rgf_zinv_noalloc.argtypes = L.qtx_rgf_zinv.argtypes
+    L.qtx_rgf_zinv_noalloc.restype = ctypes.c_int
     L.qtx_rgf_obc_fixed_point.argtypes = [
         c_ctx, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
@@ -158,7 +160,7 @@ def exported_symbols():
             "qtx_rgf_status_string", "qtx_rgf_last_error",
             "qtx_rgf_flops_per_energy", "qtx_rgf_kernel_stats",
             "qtx_rgf_reset_stats", "qtx_rgf_zgemm", "qtx_rgf_cgemm",
-            "qtx_rgf_zinv", "qtx_rgf_submit", "qtx_rgf_poll",
+            "qtx_rgf_zinv", "qtx_rgf_zinv_noalloc", "qtx_rgf_submit", "qtx_rgf_poll",
             "qtx_rgf_obc_fixed_point", "qtx_rgf_obc_sancho_rubio",
             "qtx_rgf_obc_lesser_greater", "qtx_rgf_observables",
             "qtx_rgf_obc_lyapunov_fixed_point", "qtx_rgf_obc_lyapunov_doubling"]
@@ -283,6 +285,11 @@ class Context:
     def zinv(self, b, A, X, info, batch):
         st = lib().qtx_rgf_zinv(self._h, b, _ptr(A), _ptr(X), _ptr(info), batch)
         return self._check(st, "qtx_rgf_zinv")
+
+    def zinv_noalloc(self, b, A, X, info, batch):
+        """Asynchronous on the context's stream: synchronise before reading X."""
+        st = lib().qtx_rgf_zinv_noalloc(self._h, b, _ptr(A), _ptr(X), _ptr(info), batch)
+        return self._check(st, "qtx_rgf_zinv_noalloc")
 
     def obc_fixed_point(self, b, batch, m, s_m, n, s_n, n_prime, s_np, x, sigma,
                         update, info, n_iter):
