@@ -163,6 +163,50 @@ qtx_status qtx_rgf_create(qtx_rgf_ctx** out, int device,
 qtx_status qtx_rgf_solve_batch(qtx_rgf_ctx* ctx, qtx_rgf_problem* problems,
                                int32_t n_problems);
 
+/* ---- partitioned solve (nested dissection) ----------------------------- */
+
+/* Options of qtx_rgf_solve_nested.
+ *   n_partitions  P_S >= 2.  Partition p holds the contiguous blocks
+ *                 [lo_p, hi_p); sizes are n / P_S, the first n % P_S of them
+ *                 one larger.  The first and last partitions need >= 1
+ *                 block, middle ones >= 2 (else QTX_ERR_INVALID_ARG).
+ *   reduced       optional (diag NULL = not returned): the reduced system on
+ *                 the ns = 2 (P_S - 1) separators, in separator order
+ *                 (last block of the top partition, first and last block of
+ *                 each middle partition, first block of the bottom one):
+ *                 diag [N_E][ns][b][b], upper and lower [N_E][ns-1][b][b].
+ *   reduced_l, reduced_g
+ *                 optional (diag NULL = not returned): the reduced right-hand
+ *                 sides of X^< and X^> (diag and upper as above; the lower
+ *                 blocks are -upper^dagger and are not written). */
+typedef struct {
+  int32_t n_partitions;
+  int32_t reserved;
+  qtx_bt_out reduced;
+  qtx_bt_out reduced_l, reduced_g;
+} qtx_rgf_nested;
+
+/* One problem solved by the partitioned scheme of Sec. 4.4 (Fig.
+ * nested-dissection) on this device: the same outputs, layout, symmetry
+ * contract and error reporting as qtx_rgf_solve_batch of the problem alone
+ * (results agree to rounding, not bitwise).  The blocks are split into
+ * n_partitions partitions (one top, P_S - 2 middle, one bottom).  Phase 1:
+ * every partition eliminates its interior blocks towards its separators --
+ * top-down in the top partition, bottom-up in the bottom one, top-down with
+ * the fill-in coupling to its first block in a middle one -- and writes its
+ * separators' blocks of the reduced system.  Phase 2: the reduced system
+ * (block tridiagonal over the separators) is solved by the recursion of
+ * Sec. 3.2.3.  Phase 3: every partition recovers its selected blocks from
+ * its separators' solution.  The partitions of one phase are independent
+ * and run in shared launches, so the longest dependent chain per energy is
+ * about n / P_S + 2 P_S inverses instead of n (a single-energy solve gains
+ * parallelism); the price is the fill-in work of the middle partitions and
+ * the reduced system.  Workspace (inside the context's budget, in energy
+ * chunks) is about (5 + 2 n_rhs) n + 26 P_S + 10 ns blocks per energy.
+ * fail_block is the global block whose inverse failed.  Synchronous. */
+qtx_status qtx_rgf_solve_nested(qtx_rgf_ctx* ctx, qtx_rgf_problem* problem,
+                                const qtx_rgf_nested* options);
+
 /* Release the context's workspace, streams and events.  Caller memory is
  * untouched.  Waits for work in flight, including every problem submitted
  * to the request loop. */

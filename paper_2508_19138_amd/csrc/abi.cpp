@@ -24,17 +24,18 @@ using namespace qtx;
 
 namespace {
 
-constexpr size_t kArenaLimit = 32u << 20;    // descriptor bytes per segment
 constexpr int kSplitMinEnergies = 64;          // energies before a problem is split
 
-size_t budget_now(qtx_rgf_ctx* c) {
+}  // namespace
+
+size_t qtx::budget_now(qtx_rgf_ctx* c) {
   if (c->budget) return c->budget;
   size_t fr = 0, tot = 0;
   HIPCHK(c, hipMemGetInfo(&fr, &tot));
   return (size_t)(0.9 * (double)(fr + c->ws_bytes));
 }
 
-void ensure(qtx_rgf_ctx* c, char** p, size_t* have, size_t need) {
+void qtx::ensure(qtx_rgf_ctx* c, char** p, size_t* have, size_t need) {
   if (*have >= need) return;
   c->pool->sync();
   if (*p) {
@@ -51,8 +52,6 @@ void ensure(qtx_rgf_ctx* c, char** p, size_t* have, size_t need) {
   }
   *have = need;
 }
-
-}  // namespace
 
 std::string qtx::validate_problem(const qtx_rgf_problem& p) {
   if (p.kind != QTX_KIND_G && p.kind != QTX_KIND_W) return "unknown kind";
@@ -91,7 +90,9 @@ struct BusyGuard {
   ~BusyGuard() { c->busy = false; }
 };
 
-void run_lanes_to_end(qtx_rgf_ctx* c, std::vector<Lane*>& lanes) {
+}  // namespace
+
+void qtx::run_lanes_to_end(qtx_rgf_ctx* c, std::vector<Lane*>& lanes) {
   const bool prof = (c->flags & QTX_FLAG_PROFILE) != 0;
   Executor& x = c->pool->exe(0);
   while (true) {
@@ -100,6 +101,8 @@ void run_lanes_to_end(qtx_rgf_ctx* c, std::vector<Lane*>& lanes) {
     x.flush(prof, c->graphs, c->stats);
   }
 }
+
+namespace {
 
 qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
   const bool prof = (c->flags & QTX_FLAG_PROFILE) != 0;

@@ -93,6 +93,17 @@ class Regions {
 // an error message or an empty string.
 std::string validate_problem(const qtx_rgf_problem& p);
 
+constexpr size_t kArenaLimit = 32u << 20;    // descriptor bytes per segment
+
+// Workspace budget of a call: the context's, else 90% of the free memory
+// plus what the context already holds.
+size_t budget_now(qtx_rgf_ctx* c);
+// Grow-only device buffer *p of *have bytes to at least `need` bytes (the
+// pool is drained and its graphs released first); QTX_ERR_NOMEM on failure.
+void ensure(qtx_rgf_ctx* c, char** p, size_t* have, size_t need);
+// Run lanes to completion in merged launches on the pool's first stream.
+void run_lanes_to_end(qtx_rgf_ctx* c, std::vector<Lane*>& lanes);
+
 // Drain and stop the context's request loop, if it was started.
 void stop_server(qtx_rgf_ctx* c);
 

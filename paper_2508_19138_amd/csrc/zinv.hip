@@ -290,9 +290,12 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
   }
   if (t < nbe) pe[k0 + t] = pivs[t];
   if (t == 0 && d.info) {
+    // several inverses of one energy may share a launch (the partitions of
+    // a partitioned solve): only a failure is written, so a success never
+    // overwrites another inverse's failure
     int* inf = d.info + e;
-    const int cur = (k0 == 0 && d.reset_info) ? 0 : *inf;
-    if (cur == 0) *inf = first_bad;
+    if (k0 == 0 && d.reset_info) *inf = first_bad;
+    else if (first_bad != 0 && *inf == 0) *inf = first_bad;
   }
 #pragma unroll
   for (int g = 0; g < kG; ++g) {

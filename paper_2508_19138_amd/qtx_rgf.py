@@ -59,6 +59,11 @@ class Problem(ctypes.Structure):
     ]
 
 
+class Nested(ctypes.Structure):
+    _fields_ = [("n_partitions", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("reduced", BtOut), ("reduced_l", BtOut), ("reduced_g", BtOut)]
+
+
 class Completion(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32),
                 ("fail_energy", ctypes.c_int32), ("fail_block", ctypes.c_int32),
@@ -120,6 +125,8 @@ def lib():
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
     L.qtx_rgf_zinv.restype = ctypes.c_int
     L.qtx_rgf_zinv_noalloc.argtypes = L.qtx_rgf_zinv.argtypes
+    L.qtx_rgf_solve_nested.argtypes = [c_ctx, ctypes.POINTER(Problem), ctypes.POINTER(Nested)]
+    L.qtx_rgf_solve_nested.restype = ctypes.c_int
     L.qtx_rgf_zinv_noalloc.restype = ctypes.c_int
     L.qtx_rgf_obc_fixed_point.argtypes = [
         c_ctx, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
@@ -161,6 +168,7 @@ def exported_symbols():
             "qtx_rgf_flops_per_energy", "qtx_rgf_kernel_stats",
             "qtx_rgf_reset_stats", "qtx_rgf_zgemm", "qtx_rgf_cgemm",
             "qtx_rgf_zinv", "qtx_rgf_zinv_noalloc", "qtx_rgf_submit", "qtx_rgf_poll",
+            "qtx_rgf_solve_nested",
             "qtx_rgf_obc_fixed_point", "qtx_rgf_obc_sancho_rubio",
             "qtx_rgf_obc_lesser_greater", "qtx_rgf_observables",
             "qtx_rgf_obc_lyapunov_fixed_point", "qtx_rgf_obc_lyapunov_doubling"]
@@ -237,6 +245,18 @@ class Context:
             p.fail_energy = arr[i].fail_energy
             p.fail_block = arr[i].fail_block
         return self._check(st, "qtx_rgf_solve_batch")
+
+    def solve_nested(self, problem, n_partitions, reduced=None, reduced_l=None,
+                     reduced_g=None):
+        """One problem by the partitioned scheme.  reduced / reduced_l /
+        reduced_g: optional (diag, upper, lower) device tensors receiving the
+        reduced system and right-hand sides (lower unused for the latter)."""
+        o = Nested(n_partitions, 0,
+                   _bt_out(*(reduced or (None, None, None))),
+                   _bt_out(*(reduced_l or (None, None, None))),
+                   _bt_out(*(reduced_g or (None, None, None))))
+        st = lib().qtx_rgf_solve_nested(self._h, ctypes.byref(problem), ctypes.byref(o))
+        return self._check(st, "qtx_rgf_solve_nested")
 
     def submit(self, problem):
         """Queue one problem on the request loop; returns its ticket.  The

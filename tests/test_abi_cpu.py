@@ -37,7 +37,8 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("cname,pystruct", [("qtx_rgf_problem", "Problem"),
-                                             ("qtx_rgf_completion", "Completion")])
+                                             ("qtx_rgf_completion", "Completion"),
+                                             ("qtx_rgf_nested", "Nested")])
 def test_struct_layout_matches_c(tmp_path, cname, pystruct):
     """Compile a tiny C program against the header (gcc, host only) and
     compare sizeof/offsetof with the ctypes mirror."""
