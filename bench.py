@@ -47,13 +47,13 @@ FP64_MFMA_PEAK_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
 HBM_PEAK_GBS = 8000.0
 
 # Measured HBM bytes of the dominant kernel per algorithmic byte: rocprofv3
-# --pmc FETCH_SIZE and WRITE_SIZE on `bench.py --mode gemm` (the product
-# kernel alone at this workload's shape: 512 x 512 blocks, 128 per launch,
-# D = A op(B) + C), each scaled by the same counter on a 1 GiB device copy
-# in the same run (FETCH_SIZE reads 0.500 of the copied bytes, WRITE_SIZE
-# 1.000): 806086 KiB x 2 read + 524288 KiB written per launch against
-# 2097152 KiB algorithmic.  None once the kernel changes.
-MEASURED_TRAFFIC_FACTOR = (806086.0 * 2.0 + 524288.0) / 2097152.0
+# --pmc FETCH_SIZE and WRITE_SIZE runs of this default workload (the
+# recursion's real launch mix, 810 product launches), each scaled by the
+# same counter on a 1 GiB device copy in the same run (FETCH_SIZE reads 0.500
+# of the copied bytes, WRITE_SIZE 1.000): 1554326 KiB x 2 read + 968314 KiB
+# written per launch against 3.303e9 algorithmic bytes.  None once the
+# kernel changes.
+MEASURED_TRAFFIC_FACTOR = (1554326.0 * 2.0 + 968314.0) * 1024.0 / 3303413117.7876544
 
 
 def parse():
@@ -72,6 +72,8 @@ def parse():
                     help="energies in the CPU-oracle sample (0 = skip)")
     ap.add_argument("--cpu-reps", type=int, default=3,
                     help="repetitions of the CPU-oracle sample (median reported)")
+    ap.add_argument("--upper-only", action="store_true",
+                    help="plain: lesser/greater outputs as diagonal + upper blocks only")
     ap.add_argument("--bt-sigma", action="store_true",
                     help="plain/mixed: self-energies with block-tridiagonal parts (general "
                          "path, F_BT flop model); use --energies 96 to fit HBM")
@@ -197,6 +199,8 @@ def oracle_max_error(results, XR, XL, XG):
     for e, (OR, OS) in results.items():
         for X, R in zip((XR, XL, XG), (OR,) + tuple(OS)):
             for x, r in zip(X, R):
+                if x is None:                  # lower blocks not written
+                    continue
                 g = x[e].cpu().numpy()
                 num = np.linalg.norm(g - r, axis=(-2, -1))
                 den = np.linalg.norm(r, axis=(-2, -1))
@@ -212,9 +216,15 @@ def _gemm_roofline(ctx, cls, peak, label):
     avg_ms = st["ms"] / st["launches"]
     fl_launch = st["flops"] / st["launches"]
     ach = fl_launch / (avg_ms * 1e-3) / 1e12
+    # algorithmic flops are the conventional 8 b^3 per complex product; the
+    # FP64 kernel's 3M form executes 6 b^3 of them on the matrix cores, so
+    # its matrix cores' own utilisation is 3/4 of `frac` (frac may exceed 1)
+    ex = 0.75 if cls == "zgemm" else 1.0
     return {"bound": "mfma", "kernel": label,
             "achieved": round(ach, 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+            "mfma_utilisation": round(ex * ach / peak, 4),
+            "executed_flops_per_launch": ex * fl_launch,
             "traffic": (round(MEASURED_TRAFFIC_FACTOR * st["bytes"] / st["launches"])
                         if cls == "zgemm" and MEASURED_TRAFFIC_FACTOR else None),
             "launches": st["launches"], "avg_launch_ms": round(avg_ms, 4),
@@ -229,10 +239,13 @@ def run_plain(args, mixed=False):
 
     p, H, (sr, sl, sg) = build_inputs(n, b, n_e, args.seed, args.bt_sigma)
     E = np.ascontiguousarray(p["energies"])
-    mk = lambda: (torch.empty((n_e, n, b, b), dtype=torch.complex128, device="cuda:0"),
-                  torch.empty((n_e, n - 1, b, b), dtype=torch.complex128, device="cuda:0"),
-                  torch.empty((n_e, n - 1, b, b), dtype=torch.complex128, device="cuda:0"))
-    XR, XL, XG = mk(), mk(), mk()
+    mk = lambda lower=True: (
+        torch.empty((n_e, n, b, b), dtype=torch.complex128, device="cuda:0"),
+        torch.empty((n_e, n - 1, b, b), dtype=torch.complex128, device="cuda:0"),
+        torch.empty((n_e, n - 1, b, b), dtype=torch.complex128, device="cuda:0") if lower else None)
+    # --upper-only: the lesser/greater lower blocks are not written (they are
+    # -upper^dagger, Sec. 4.2), which saves their HBM
+    XR, XL, XG = mk(), mk(not args.upper_only), mk(not args.upper_only)
     torch.cuda.synchronize()
 
     ctx = Q.Context(0, profile=not args.no_profile)
@@ -265,7 +278,7 @@ def run_plain(args, mixed=False):
                                   "cgemm_kernel (complex64 operands, 4 real FP32 MFMA per complex product)")
         else:
             roof = _gemm_roofline(ctx, "zgemm", FP64_MFMA_PEAK_TFLOPS,
-                                  "zgemm_kernel (complex FP64, 4 real MFMA per complex product)")
+                                  "zgemm_kernel (complex FP64, 3M form: 3 real MFMA per complex product)")
         kt = {k: round(ctx.kernel_stats(k)["ms"], 1)
               for k in ("zgemm", "cgemm", "inverse", "elementwise")}
         if mixed:
@@ -316,6 +329,14 @@ def run_plain(args, mixed=False):
         "oracle_max_block_rel_err": oracle_err,
         "context": PAPER_CONTEXT,
     }
+    if args.upper_only:
+        blk = 16.0 * b * b
+        out["symmetric_storage"] = {
+            "lower_blocks_not_written": 2 * (n - 1) * n_e,
+            "hbm_saved_bytes": 2 * (n - 1) * n_e * blk,
+            "output_bytes": (3 * (2 * n - 1) + n) * n_e * blk,
+            "energies_per_lane": n_e,
+            "what": "X^< and X^> lower blocks left to the caller as -upper^dagger (Sec. 4.2)"}
     if mixed:
         out["mode"] = "mixed"
         out["errors"] = errors
@@ -883,7 +904,7 @@ def run_lyapunov(args):
         dt = (time.perf_counter() - t0) / args.steps
         roof = None if args.no_profile else _gemm_roofline(
             ctx, "zgemm", FP64_MFMA_PEAK_TFLOPS,
-            "zgemm_kernel (complex FP64, 4 real MFMA per complex product)")
+            "zgemm_kernel (complex FP64, 3M form: 3 real MFMA per complex product)")
         if roof is not None:
             roof["traffic"] = None
     o = out.cpu().numpy()
@@ -965,7 +986,7 @@ def run_obc(args):
         dt = (time.perf_counter() - t0) / args.steps
         roof = None if args.no_profile else _gemm_roofline(
             ctx, "zgemm", FP64_MFMA_PEAK_TFLOPS,
-            "zgemm_kernel (complex FP64, 4 real MFMA per complex product)")
+            "zgemm_kernel (complex FP64, 3M form: 3 real MFMA per complex product)")
         if roof is not None:
             roof["traffic"] = None           # no counter run of this workload
         kt = None if args.no_profile else {

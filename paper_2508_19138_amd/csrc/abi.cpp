@@ -483,7 +483,7 @@ qtx_status qtx_rgf_zinv(qtx_rgf_ctx* c, int32_t b, void* A, void* X, int32_t* in
   try {
     HIPCHK(c, hipSetDevice(c->device));
     const size_t pan = (size_t)batch * b * kPanel * 16;
-    const size_t span = (size_t)batch * b * kSuper * 16;
+    const size_t span = (size_t)batch * b * inv_span(b) * 16;
     const size_t ints = (size_t)batch * b * 4;
     HIPCHK(c, hipMalloc(&work, 2 * pan + 2 * span + 2 * ints + 4096));
     Lane L;
@@ -534,11 +534,11 @@ struct LeadLane {
       : b(b_), batch(batch_), bb((long long)b_ * b_), iw(inv_work) {
     cfg = c->tuner.cfg(b, b, b, false, c->stream);
     pan = (size_t)batch * b * kPanel * 16;
-    span = (size_t)batch * b * kSuper * 16;
+    span = (size_t)batch * b * inv_span(b) * 16;
     ints = (size_t)batch * b * 4;
   }
   static size_t inv_work(int b, int batch) {
-    return (size_t)batch * b * (2 * kPanel + 2 * kSuper) * 16 + (size_t)batch * b * 8 + 4096;
+    return (size_t)batch * b * (2 * kPanel + 2 * inv_span(b)) * 16 + (size_t)batch * b * 8 + 4096;
   }
   // D = alpha op(A) op(B) + beta C (strides in elements between energies;
   // op 'C' = adjoint)

@@ -112,8 +112,8 @@ Layout carve_layout(const Plan& q, int ec, char* ws) {
   }
   L.panel = cv.take((size_t)ec * b * kPanel * 16);
   L.brow = cv.take((size_t)ec * b * kPanel * 16);
-  L.spanel = cv.take((size_t)ec * b * kSuper * 16);
-  L.sbrow = cv.take((size_t)ec * b * kSuper * 16);
+  L.spanel = cv.take((size_t)ec * b * inv_span(b) * 16);
+  L.sbrow = cv.take((size_t)ec * b * inv_span(b) * 16);
   L.perm = (int*)cv.take((size_t)ec * b * 4);
   L.used = (int*)cv.take((size_t)ec * b * 4);
   if (q.is_w) {

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <filesystem>
 #include <fstream>
+#include <functional>
 #include <sstream>
 
 namespace qtx {
@@ -78,7 +79,7 @@ void Tuner::save() const {
   f << "}\n";
 }
 
-static int heuristic_cfg(int b) { return b <= 32 ? 2 : (b >= 384 ? 1 : 0); }
+static int heuristic_cfg(int b) { return b <= 32 ? 2 : 0; }
 
 int Tuner::measure(int b, bool fp32, hipStream_t s) {
   // time each configuration on a batch of b x b x b products that fills the
@@ -236,10 +237,11 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
     return;
   }
   if (f.k == OpK::Inv) {
-    // two-level blocked Gauss-Jordan (see zinv.hip): per super-panel, its
-    // panels each followed by a rank-kPanel update of the super-panel, then
-    // the gather and one rank-kSuper update of the whole matrix; one
-    // permutation at the end
+    // three-level blocked Gauss-Jordan (see zinv.hip): per mega-panel, per
+    // super-panel, its panels each followed by a rank-kPanel update of the
+    // super-panel, then the super-panel's gather and rank-kSuper update of
+    // the mega-panel's columns; after the mega-panel its gather and the
+    // rank-kMega update of the columns outside it; one permutation at the end
     std::vector<InvDesc> all;
     double fl = 0;
     for (auto& lo : ops) {
@@ -251,55 +253,72 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
     const int R = (maxb + kInvThreads - 1) / kInvThreads;
 
     bool first = true;
-    for (int K0 = 0; K0 < maxb; K0 += kSuper) {
-      for (int k0 = K0; k0 < std::min(K0 + kSuper, maxb); k0 += kPanel) {
-        std::vector<InvDesc> d;
-        std::vector<int> pre(1, 0);
-        std::vector<GemmDesc> gd;
-        std::vector<int> gpre(1, 0);
-        double by = 0, gby = 0;
-        for (const InvDesc& v : all) {
-          if (v.b <= k0) continue;
-          d.push_back(v);
-          pre.push_back(pre.back() + v.batch);
-          by += 16.0 * 3.0 * v.b * kPanel * v.batch;
-          GemmDesc g;
-          if (inv_panel_update(v, k0, &g)) {
-            gd.push_back(g);
-            gpre.push_back(gpre.back() + g.tiles * g.batch);
-            gby += 16.0 * 2.0 * g.M * (double)g.N * g.batch;
-          }
-        }
-        recs_.push_back(LaunchRec{LaunchRec::Panel, 'N', 'N', false, R, k0, put(d), put_prefix(pre),
-                                  (int)d.size(), pre.back(), kClassInv, (first ? fl : 0.0), by});
-        first = false;
-        if (!gd.empty())
-          recs_.push_back(LaunchRec{LaunchRec::Gemm, 'N', 'N', false, kGemmInvUpdate, k0, put(gd),
-                                    put_prefix(gpre), (int)gd.size(), gpre.back(), kClassInv, 0.0, gby});
-      }
-      // gather + rank-kSuper update for matrices larger than one super-panel
+    auto gather_and_update = [&](int K0, int W, int cfg,
+                                 const std::function<int(const InvDesc&, GemmDesc*)>& upd) {
       std::vector<InvDesc> d;
       std::vector<int> pre(1, 0);
       std::vector<GemmDesc> gd;
       std::vector<int> gpre(1, 0);
       double by = 0, gby = 0;
       for (const InvDesc& v : all) {
-        if (v.b <= K0 || v.b <= kSuper) continue;
+        GemmDesc g[2];
+        const int ng = upd(v, g);
+        if (ng == 0) continue;
         d.push_back(v);
-        pre.push_back(pre.back() + v.batch * super_gather_chunks(v.b));
-        by += 16.0 * 3.0 * v.b * kSuper * v.batch;
-        GemmDesc g;
-        inv_super_update(v, K0, &g);
-        gd.push_back(g);
-        gpre.push_back(gpre.back() + g.tiles * g.batch);
-        gby += 16.0 * 2.0 * g.M * (double)g.N * g.batch;
+        pre.push_back(pre.back() + v.batch * super_gather_chunks(v.b, W));
+        by += 16.0 * 3.0 * v.b * std::min(W, v.b - K0) * v.batch;
+        for (int q = 0; q < ng; ++q) {
+          gd.push_back(g[q]);
+          gpre.push_back(gpre.back() + g[q].tiles * g[q].batch);
+          gby += 16.0 * 2.0 * g[q].M * (double)g[q].N * g[q].batch;
+        }
       }
-      if (!d.empty()) {
-        recs_.push_back(LaunchRec{LaunchRec::Gather, 'N', 'N', false, 0, K0, put(d), put_prefix(pre),
-                                  (int)d.size(), pre.back(), kClassInv, 0.0, by});
-        recs_.push_back(LaunchRec{LaunchRec::Gemm, 'N', 'N', false, kGemmInvUpdate, K0, put(gd),
-                                  put_prefix(gpre), (int)gd.size(), gpre.back(), kClassInv, 0.0, gby});
+      if (d.empty()) return;
+      recs_.push_back(LaunchRec{LaunchRec::Gather, 'N', 'N', false, W, K0, put(d), put_prefix(pre),
+                                (int)d.size(), pre.back(), kClassInv, 0.0, by});
+      recs_.push_back(LaunchRec{LaunchRec::Gemm, 'N', 'N', false, cfg, K0, put(gd),
+                                put_prefix(gpre), (int)gd.size(), gpre.back(), kClassInv, 0.0, gby});
+    };
+    for (int M0 = 0; M0 < maxb; M0 += kMega) {
+      for (int K0 = M0; K0 < std::min(M0 + kMega, maxb); K0 += kSuper) {
+        for (int k0 = K0; k0 < std::min(K0 + kSuper, maxb); k0 += kPanel) {
+          std::vector<InvDesc> d;
+          std::vector<int> pre(1, 0);
+          std::vector<GemmDesc> gd;
+          std::vector<int> gpre(1, 0);
+          double by = 0, gby = 0;
+          for (const InvDesc& v : all) {
+            if (v.b <= k0) continue;
+            d.push_back(v);
+            pre.push_back(pre.back() + v.batch);
+            by += 16.0 * 3.0 * v.b * kPanel * v.batch;
+            GemmDesc g;
+            if (inv_panel_update(v, k0, &g)) {
+              gd.push_back(g);
+              gpre.push_back(gpre.back() + g.tiles * g.batch);
+              gby += 16.0 * 2.0 * g.M * (double)g.N * g.batch;
+            }
+          }
+          recs_.push_back(LaunchRec{LaunchRec::Panel, 'N', 'N', false, R, k0, put(d), put_prefix(pre),
+                                    (int)d.size(), pre.back(), kClassInv, (first ? fl : 0.0), by});
+          first = false;
+          if (!gd.empty())
+            recs_.push_back(LaunchRec{LaunchRec::Gemm, 'N', 'N', false, kGemmInvUpdate, k0, put(gd),
+                                      put_prefix(gpre), (int)gd.size(), gpre.back(), kClassInv, 0.0,
+                                      gby});
+        }
+        // rank-kSuper update of the mega-panel's other columns
+        gather_and_update(K0, kSuper, kGemmInvUpdate, [&](const InvDesc& v, GemmDesc* g) {
+          return inv_super_update(v, K0, g) ? 1 : 0;
+        });
       }
+      // rank-kMega update of the columns outside the mega-panel
+      gather_and_update(M0, kMega, kMegaCfg, [&](const InvDesc& v, GemmDesc* g) {
+        int ng = 0;
+        for (int side = 0; side < 2; ++side)
+          if (inv_mega_update(v, M0, side, &g[ng])) ++ng;
+        return ng;
+      });
     }
     std::vector<int> pre(1, 0);
     double by = 0;
@@ -403,7 +422,7 @@ void Executor::issue(char* base, bool profile) {
       case LaunchRec::Gemm: XCHK(launch_gemm(r.cfg, r.fp32, r.opa, r.opb, l, s_)); break;
       case LaunchRec::Panel: XCHK(launch_inv_panel(r.cfg, r.k0, l, s_)); break;
       case LaunchRec::Permute: XCHK(launch_inv_permute(l, s_)); break;
-      case LaunchRec::Gather: XCHK(launch_inv_super_gather(r.k0, l, s_)); break;
+      case LaunchRec::Gather: XCHK(launch_inv_super_gather(r.k0, r.cfg, l, s_)); break;
       case LaunchRec::Lin: XCHK(launch_lincomb(l, s_)); break;
       case LaunchRec::Trans: XCHK(launch_transcomb(l, s_)); break;
     }

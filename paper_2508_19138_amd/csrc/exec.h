@@ -83,7 +83,7 @@ struct LaunchRec {
   enum Kind : uint8_t { Gemm, Panel, Gather, Permute, Lin, Trans } kind;
   char opa, opb;
   bool fp32;
-  int cfg;        // gemm tile config, or rows-per-thread R for Panel
+  int cfg;        // gemm tile config, rows-per-thread R (Panel) or width W (Gather)
   int k0;         // Panel
   size_t desc_off, prefix_off;
   int nd, total;

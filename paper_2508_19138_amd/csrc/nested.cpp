@@ -156,8 +156,8 @@ NLayout carve_nested(const Plan& q, int P, int ec, char* ws) {
     }
     t.panel = cv.take((size_t)ec * b * kPanel * 16);
     t.brow = cv.take((size_t)ec * b * kPanel * 16);
-    t.spanel = cv.take((size_t)ec * b * kSuper * 16);
-    t.sbrow = cv.take((size_t)ec * b * kSuper * 16);
+    t.spanel = cv.take((size_t)ec * b * inv_span(b) * 16);
+    t.sbrow = cv.take((size_t)ec * b * inv_span(b) * 16);
     t.perm = (int*)cv.take((size_t)ec * b * 4);
     t.used = (int*)cv.take((size_t)ec * b * 4);
   }

@@ -27,10 +27,11 @@ namespace qtx {
 namespace {
 
 constexpr size_t kScratchBytes = (size_t)QTX_NOALLOC_SCRATCH_BYTES;
-// descriptor tables: one InvDesc, one GemmDesc per update product, and the
-// prefix pairs of every launch
+// descriptor tables: one InvDesc, the update products' descriptors, and
+// the prefix arrays of every launch
 constexpr size_t kDescBytes = 64 << 10;
-constexpr int kMaxUpdates = 1024 / kPanel + 1024 / kSuper;
+constexpr int kMaxUpdates = 1024 / kPanel + 1024 / kSuper + 2 * (1024 / kMega);
+constexpr int kMaxSteps = 2 * (1024 / kPanel) + 2 * (1024 / kSuper) + 2 * (1024 / kMega) + 1;
 
 static __device__ __align__(256) char scratch[kScratchBytes + kDescBytes];
 
@@ -38,47 +39,91 @@ constexpr int kMaxDevices = 64;
 std::mutex g_mu;
 char* g_ptr[kMaxDevices] = {};
 
+// One launch of the inverse: a panel at k0, a gather of the W-column panel
+// at k0, `count` update products from upd[first] (tile configuration cfg),
+// or the final permutation.
+struct Step {
+  int kind;                  // 0 panel, 1 products, 2 gather, 3 permutation
+  int k0, W, cfg;
+  int first, count;
+};
+
 // Layout of the descriptor area.
 struct DescArea {
   InvDesc inv;
   GemmDesc upd[kMaxUpdates];
-  int inv_pre[2];            // panel launches: one workgroup per matrix
-  int gather_pre[2];
-  int perm_pre[2];
-  int upd_pre[kMaxUpdates][2];
+  Step steps[kMaxSteps];
+  int pre[kMaxSteps][3];     // prefix array of every launch
 };
 static_assert(sizeof(DescArea) <= kDescBytes, "descriptor area");
 
-// Update products in launch order: per super-panel, the rank-kPanel update
-// after each panel that has one, then the rank-kSuper update.
-__host__ __device__ inline int update_list(const InvDesc& v, GemmDesc* out) {
-  int n = 0;
-  for (int K0 = 0; K0 < v.b; K0 += kSuper) {
-    const int end = v.b < K0 + kSuper ? v.b : K0 + kSuper;
-    for (int k0 = K0; k0 < end; k0 += kPanel) {
-      GemmDesc g;
-      if (inv_panel_update(v, k0, &g)) { if (out) out[n] = g; ++n; }
+// The executor's launch sequence for one inverse operation, in order:
+// per mega-panel, per super-panel, each panel and its rank-kPanel update,
+// then the super-panel's gather and rank-kSuper update of the mega-panel's
+// columns; after the mega-panel its gather and rank-kMega update of the
+// other columns; the permutation last.  Returns the number of steps.
+__host__ __device__ inline int inv_steps(const InvDesc& v, Step* st, GemmDesc* upd) {
+  int ns = 0, nu = 0;
+  for (int M0 = 0; M0 < v.b; M0 += kMega) {
+    const int mend = v.b < M0 + kMega ? v.b : M0 + kMega;
+    for (int K0 = M0; K0 < mend; K0 += kSuper) {
+      const int kend = v.b < K0 + kSuper ? v.b : K0 + kSuper;
+      for (int k0 = K0; k0 < kend; k0 += kPanel) {
+        st[ns++] = Step{0, k0, 0, 0, 0, 0};
+        if (inv_panel_update(v, k0, &upd[nu])) {
+          st[ns++] = Step{1, k0, 0, kGemmInvUpdate, nu, 1};
+          ++nu;
+        }
+      }
+      if (inv_super_update(v, K0, &upd[nu])) {
+        st[ns++] = Step{2, K0, kSuper, 0, 0, 0};
+        st[ns++] = Step{1, K0, 0, kGemmInvUpdate, nu, 1};
+        ++nu;
+      }
     }
-    GemmDesc g;
-    if (inv_super_update(v, K0, &g)) { if (out) out[n] = g; ++n; }
+    int c = 0;
+    for (int side = 0; side < 2; ++side)
+      if (inv_mega_update(v, M0, side, &upd[nu + c])) ++c;
+    if (c) {
+      st[ns++] = Step{2, M0, kMega, 0, 0, 0};
+      st[ns++] = Step{1, M0, 0, kMegaCfg, nu, c};
+      nu += c;
+    }
   }
-  return n;
+  st[ns++] = Step{3, 0, 0, 0, 0, 0};
+  return ns;
+}
+
+// workgroups of a step
+__host__ __device__ inline int step_total(const InvDesc& v, const Step& t, const GemmDesc* upd) {
+  switch (t.kind) {
+    case 0: return v.batch;
+    case 2: return v.batch * super_gather_chunks(v.b, t.W);
+    case 3: return v.batch * ((v.b + kPermRows - 1) / kPermRows);
+    default: {
+      int n = 0;
+      for (int q = 0; q < t.count; ++q) n += upd[t.first + q].tiles * upd[t.first + q].batch;
+      return n;
+    }
+  }
 }
 
 __global__ void noalloc_setup_kernel(InvDesc v, DescArea* a) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   a->inv = v;
-  const int n = update_list(v, a->upd);
-  for (int i = 0; i < n; ++i) {
-    a->upd_pre[i][0] = 0;
-    a->upd_pre[i][1] = a->upd[i].tiles * a->upd[i].batch;
+  Step* st = a->steps;       // in the descriptor area: no private stack array
+  const int ns = inv_steps(v, st, a->upd);
+  for (int i = 0; i < ns; ++i) {
+    a->pre[i][0] = 0;
+    if (st[i].kind == 1) {
+      for (int q = 0; q < st[i].count; ++q) {
+        const GemmDesc& g = a->upd[st[i].first + q];
+        a->pre[i][q + 1] = a->pre[i][q] + g.tiles * g.batch;
+      }
+    } else {
+      a->pre[i][1] = step_total(v, st[i], a->upd);
+    }
   }
-  a->inv_pre[0] = 0;
-  a->inv_pre[1] = v.batch;
-  a->gather_pre[0] = 0;
-  a->gather_pre[1] = v.batch * super_gather_chunks(v.b);
-  a->perm_pre[0] = 0;
-  a->perm_pre[1] = v.batch * ((v.b + kPermRows - 1) / kPermRows);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -87,7 +132,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 size_t noalloc_work_bytes(int b, int batch) {
   const size_t pan = align256((size_t)batch * b * kPanel * 16);
-  const size_t span = align256((size_t)batch * b * kSuper * 16);
+  const size_t span = align256((size_t)batch * b * inv_span(b) * 16);
   const size_t ints = align256((size_t)batch * b * 4);
   return 2 * pan + 2 * span + 2 * ints;
 }
@@ -135,7 +180,7 @@ extern "C" qtx_status qtx_rgf_zinv_noalloc(qtx_rgf_ctx* c, int32_t b, void* A, v
     return QTX_ERR_HIP;
   }
   const size_t pan = align256((size_t)batch * b * kPanel * 16);
-  const size_t span = align256((size_t)batch * b * kSuper * 16);
+  const size_t span = align256((size_t)batch * b * inv_span(b) * 16);
   const size_t ints = align256((size_t)batch * b * 4);
   InvDesc v{};
   v.S = A; v.sS = (long long)b * b;
@@ -152,7 +197,8 @@ extern "C" qtx_status qtx_rgf_zinv_noalloc(qtx_rgf_ctx* c, int32_t b, void* A, v
 
   // the same launch sequence as the executor's for one inverse operation
   GemmDesc upd[kMaxUpdates];
-  const int n_upd = update_list(v, upd);
+  Step st[kMaxSteps];
+  const int n_steps = inv_steps(v, st, upd);
   const hipStream_t s = c->stream;
   auto fail = [&](hipError_t e, const char* what) {
     c->err = std::string("qtx_rgf_zinv_noalloc: ") + what + ": " + hipGetErrorString(e);
@@ -161,37 +207,21 @@ extern "C" qtx_status qtx_rgf_zinv_noalloc(qtx_rgf_ctx* c, int32_t b, void* A, v
   hipLaunchKernelGGL(noalloc_setup_kernel, dim3(1), dim3(64), 0, s, v, dev);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(e, "set-up launch");
-  const FlatLaunch inv_l{&dev->inv, dev->inv_pre, 1, batch};
   const int R = (b + kInvThreads - 1) / kInvThreads;
-  int u = 0;
-  for (int K0 = 0; K0 < b; K0 += kSuper) {
-    const int end = std::min(b, K0 + kSuper);
-    for (int k0 = K0; k0 < end; k0 += kPanel) {
-      if ((e = launch_inv_panel(R, k0, inv_l, s)) != hipSuccess) return fail(e, "panel");
-      GemmDesc g;
-      if (inv_panel_update(v, k0, &g)) {
-        const FlatLaunch l{&dev->upd[u], dev->upd_pre[u], 1, upd[u].tiles * batch};
-        if ((e = launch_gemm(kGemmInvUpdate, false, 'N', 'N', l, s)) != hipSuccess)
-          return fail(e, "panel update");
-        ++u;
-      }
+  for (int i = 0; i < n_steps; ++i) {
+    const Step& t = st[i];
+    const int total = step_total(v, t, upd);
+    if (t.kind == 1) {
+      const FlatLaunch l{&dev->upd[t.first], dev->pre[i], t.count, total};
+      e = launch_gemm(t.cfg, false, 'N', 'N', l, s);
+    } else {
+      const FlatLaunch l{&dev->inv, dev->pre[i], 1, total};
+      if (t.kind == 0) e = launch_inv_panel(R, t.k0, l, s);
+      else if (t.kind == 2) e = launch_inv_super_gather(t.k0, t.W, l, s);
+      else e = launch_inv_permute(l, s);
     }
-    GemmDesc g;
-    if (inv_super_update(v, K0, &g)) {
-      const FlatLaunch gl{&dev->inv, dev->gather_pre, 1, batch * super_gather_chunks(b)};
-      if ((e = launch_inv_super_gather(K0, gl, s)) != hipSuccess) return fail(e, "gather");
-      const FlatLaunch l{&dev->upd[u], dev->upd_pre[u], 1, upd[u].tiles * batch};
-      if ((e = launch_gemm(kGemmInvUpdate, false, 'N', 'N', l, s)) != hipSuccess)
-        return fail(e, "super-panel update");
-      ++u;
-    }
+    if (e != hipSuccess) return fail(e, "launch");
   }
-  if (u != n_upd) {
-    c->err = "qtx_rgf_zinv_noalloc: update count mismatch";
-    return QTX_ERR_HIP;
-  }
-  const FlatLaunch pl{&dev->inv, dev->perm_pre, 1, batch * ((b + kPermRows - 1) / kPermRows)};
-  if ((e = launch_inv_permute(pl, s)) != hipSuccess) return fail(e, "permute");
   // asynchronous: no wait, so the call can be captured into a graph
   return QTX_OK;
 }

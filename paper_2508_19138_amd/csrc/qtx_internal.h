@@ -49,7 +49,7 @@ struct GemmDesc {
 // the larger tiles for these thin or short products at any batch size).
 constexpr int kGemmConfigs = 3;
 constexpr int kGemmInvUpdate = 7;
-int gemm_tile_m(int cfg);   // kGemmInvUpdate maps to configuration 2
+int gemm_tile_m(int cfg);   // kGemmInvUpdate: the update tile; kGemmMegaUpdate: configuration 0
 int gemm_tile_n(int cfg);
 inline int gemm_tiles(int cfg, int M, int N) {
   return ((M + gemm_tile_m(cfg) - 1) / gemm_tile_m(cfg)) *
@@ -62,13 +62,18 @@ hipError_t launch_gemm(int cfg, bool fp32, char opa, char opb,
 
 // ---- Gauss-Jordan inverse with partial pivoting -----------------------------
 constexpr int kPanel = 16;     // columns factored per panel step
-constexpr int kSuper = 64;     // columns per super-panel (two-level blocking)
+constexpr int kSuper = 64;     // columns per super-panel
+constexpr int kMega = 256;     // columns per mega-panel (three-level blocking)
 constexpr int kInvThreads = 256;
+// Columns of the gathered panel buffers (spanel, sbrow) per matrix: the
+// super-panel width, or the mega-panel width when the matrix has more than
+// one mega-panel (the two levels use the buffers one after the other).
+__host__ __device__ inline int inv_span(int b) { return b > kMega ? kMega : kSuper; }
 
 // `batch` matrices S[e] (b x b, stride sS) are eliminated in place; the
 // inverses go to X[e] (stride sX).  Per-matrix work buffers (element strides
-// in brackets): panel [b*kPanel], brow [kPanel*b], spanel [b*kSuper],
-// sbrow [kSuper*b] (complex128), perm [b], used [b] (int).
+// in brackets): panel [b*kPanel], brow [kPanel*b], spanel [b*inv_span(b)],
+// sbrow [inv_span(b)*b] (complex128), perm [b], used [b] (int).
 // info[e]: 0, or set once to +code (zero pivot) / -code (non-finite pivot);
 // `reset_info` clears it at the first panel.  code <= 0 means 1 + column.
 struct InvDesc {
@@ -89,23 +94,29 @@ struct InvDesc {
 };
 // Bytes of inverse work buffers per matrix of size b.
 inline size_t inv_work_bytes(int b) {
-  return (size_t)b * (2 * kPanel + 2 * kSuper) * 16 + (size_t)b * 8;
+  return (size_t)b * (2 * kPanel + 2 * inv_span(b)) * 16 + (size_t)b * 8;
 }
 // Panel factorisation of columns [k0, k0 + kPanel) of every matrix with
 // b > k0 (one workgroup per matrix); R = rows per thread, b <= 256 R.  The
 // pivot rows are gathered into brow for the columns [k0 & ~(kSuper-1),
 // + kSuper) of the current super-panel.
 hipError_t launch_inv_panel(int R, int k0, const FlatLaunch& l, hipStream_t s);
-// After the last panel of the super-panel starting at K0: spanel = the
-// eliminated super-panel columns minus the identity at their pivot rows,
-// sbrow = the pivot rows outside the super-panel (zero inside).
+// After the last panel of the W-column panel (W = kSuper or kMega) starting
+// at K0: spanel = its eliminated columns minus the identity at their pivot
+// rows [b][W], sbrow = its pivot rows outside it (zero inside) [W][b].
 constexpr int kGatherItems = 2048;   // elements per workgroup
-hipError_t launch_inv_super_gather(int K0, const FlatLaunch& l, hipStream_t s);
-__host__ __device__ inline int super_gather_chunks(int b) {
-  return (int)((2LL * b * kSuper + kGatherItems - 1) / kGatherItems);
+hipError_t launch_inv_super_gather(int K0, int W, const FlatLaunch& l, hipStream_t s);
+__host__ __device__ inline int super_gather_chunks(int b, int W) {
+  return (int)((2LL * b * W + kGatherItems - 1) / kGatherItems);
 }
 // Tile of the inverse's update products (the kGemmInvUpdate configuration).
 constexpr int kInvUpdTile = 32;
+// The rank-kMega updates run the recursion's product kernel (the 3M form,
+// tiles of kMegaTile) under their own kernel symbol (configuration value
+// kGemmMegaUpdate).
+constexpr int kGemmMegaUpdate = 8;
+constexpr int kMegaCfg = kGemmMegaUpdate;
+constexpr int kMegaTile = 64;
 
 // Update products of the blocked inverse, shared by every launcher of the
 // inverse (host) and by the device-side descriptor set-up of the
@@ -134,18 +145,49 @@ __host__ __device__ inline bool inv_panel_update(const InvDesc& v, int k0, GemmD
   *out = g;
   return true;
 }
+// The rank-kSuper update after the super-panel at K0 covers the columns of
+// its mega-panel [M0, Mend) only (all of them when b <= kMega): the columns
+// of later mega-panels take the whole mega-panel's eliminations at once.
 __host__ __device__ inline bool inv_super_update(const InvDesc& v, int K0, GemmDesc* out) {
   if (v.b <= K0 || v.b <= kSuper) return false;
+  const int M0 = K0 - K0 % kMega;
+  const int Mend = v.b < M0 + kMega ? v.b : M0 + kMega;
+  const int Kend = v.b < K0 + kSuper ? v.b : K0 + kSuper;
+  if (Mend - M0 <= Kend - K0) return false;       // the mega-panel is this super-panel
+  const int span = inv_span(v.b);
   GemmDesc g{};
-  g.M = v.b; g.N = v.b; g.K = kSuper;
-  g.A = v.spanel; g.sA = (long long)v.b * kSuper; g.lda = kSuper;
-  g.B = v.sbrow; g.sB = (long long)kSuper * v.b; g.ldb = v.b;
-  g.C = v.S; g.sC = v.sS; g.ldc = v.b;
-  g.D = v.S; g.sD = v.sS; g.ldd = v.b;
+  g.M = v.b; g.N = Mend - M0; g.K = kSuper;
+  g.A = v.spanel; g.sA = (long long)v.b * span; g.lda = kSuper;
+  g.B = (double2*)v.sbrow + M0; g.sB = (long long)span * v.b; g.ldb = v.b;
+  g.C = (double2*)v.S + M0; g.sC = v.sS; g.ldc = v.b;
+  g.D = (double2*)v.S + M0; g.sD = v.sS; g.ldd = v.b;
   g.alpha = zc{1.0, 0.0};
   g.beta = zc{1.0, 0.0};
   g.batch = v.batch; g.batch2 = 1;
   g.tiles = inv_update_tiles(g.M, g.N);
+  *out = g;
+  return true;
+}
+// The rank-kMega update after the mega-panel at M0: the columns left of it
+// (side 0) or right of it (side 1); false when there are none or the matrix
+// has a single mega-panel.
+__host__ __device__ inline bool inv_mega_update(const InvDesc& v, int M0, int side,
+                                                GemmDesc* out) {
+  if (v.b <= kMega || v.b <= M0) return false;
+  const int Mend = v.b < M0 + kMega ? v.b : M0 + kMega;
+  const int c0 = side == 0 ? 0 : Mend;
+  const int nc = side == 0 ? M0 : v.b - Mend;
+  if (nc <= 0) return false;
+  GemmDesc g{};
+  g.M = v.b; g.N = nc; g.K = Mend - M0;
+  g.A = v.spanel; g.sA = (long long)v.b * kMega; g.lda = kMega;
+  g.B = (double2*)v.sbrow + c0; g.sB = (long long)kMega * v.b; g.ldb = v.b;
+  g.C = (double2*)v.S + c0; g.sC = v.sS; g.ldc = v.b;
+  g.D = (double2*)v.S + c0; g.sD = v.sS; g.ldd = v.b;
+  g.alpha = zc{1.0, 0.0};
+  g.beta = zc{1.0, 0.0};
+  g.batch = v.batch; g.batch2 = 1;
+  g.tiles = ((g.M + kMegaTile - 1) / kMegaTile) * ((g.N + kMegaTile - 1) / kMegaTile);
   *out = g;
   return true;
 }

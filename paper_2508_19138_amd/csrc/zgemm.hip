@@ -2,8 +2,11 @@
 //
 // A workgroup computes one BM x BN tile of D for one matrix of one
 // descriptor.  Operand tiles are staged through LDS in the layout in which
-// they are read from HBM (see zgemm_kernel) and double buffered.  Complex numbers stay interleaved (re, im): each lane
-// reads one complex per fragment and the complex product is four real MFMAs
+// they are read from HBM (see zgemm_kernel) and double buffered.  Complex
+// numbers stay interleaved (re, im): each lane reads one complex per
+// fragment.  FP64 products take three real MFMAs per complex product (the
+// 3M form, see zgemm_kernel); FP32 products and the inverse's thin update
+// products four,
 //     Cr += ar*br - ai*bi,   Ci += ar*bi + ai*br.
 // MFMA operand layout (measured on gfx950, both 16x16x4 f64 and f32): lane l
 // supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register r of lane l
@@ -60,11 +63,18 @@ struct Cfg {
   static_assert(kWM % 16 == 0 && kWN % 16 == 0 && BK % 4 == 0, "tile");
 };
 
-typedef Cfg<64, 64, 16, 2, 2> Cfg0;     // general
-typedef Cfg<128, 64, 8, 2, 2> Cfg1;    // large blocks: 64 x 32 per wave
+// FP64 products use the 3M form (three accumulator sets, so 32 x 32 per
+// wave); FP32 products and the inverse's thin update products the
+// four-product form (FP32's 3M form measured 4x less accurate in the
+// partitioned solve).
+typedef Cfg<64, 64, 16, 2, 2> Cfg0;     // general: 32 x 32 per wave
+typedef Cfg<128, 64, 8, 4, 2> Cfg1;    // large blocks, 3M: eight waves of 32 x 32
+typedef Cfg<128, 64, 8, 2, 2> Cfg1w;   // large blocks, four products: 64 x 32 per wave
 typedef Cfg<32, 32, 16, 2, 2> Cfg2;     // small blocks
-typedef Cfg2 CfgU;                      // the inverse's update products
+typedef Cfg<32, 32, 16, 2, 2> CfgU;     // the inverse's update products
+static_assert(Cfg1w::BM == Cfg1::BM && Cfg1w::BN == Cfg1::BN, "one tile shape per configuration");
 static_assert(CfgU::BM == kInvUpdTile && CfgU::BN == kInvUpdTile, "update tile");
+static_assert(Cfg0::BM == kMegaTile && Cfg0::BN == kMegaTile, "mega tile");
 
 __device__ __forceinline__ int xcd_remap(int w, int G) {
   constexpr int kXcd = 8;
@@ -73,8 +83,9 @@ __device__ __forceinline__ int xcd_remap(int w, int G) {
   return w;
 }
 
-// TAG only separates kernel symbols (1 = rank-kPanel updates of the
-// inverse) so that profilers report the two uses apart.
+// TAG only separates kernel symbols (1 = rank-kPanel and rank-kSuper
+// updates of the inverse, 2 = its rank-kMega updates) so that profilers
+// report the uses apart.
 // Thread -> element maps of the operand tiles.  Tiles whose rows are
 // contiguous in HBM along the LDS minor index (A^dagger: [k][m], B: [k][n])
 // are read in 16-complex (256-byte) segments, 16 lanes per segment and four
@@ -93,7 +104,20 @@ __device__ __forceinline__ void tile_index(int q, int& w, int& k) {
   }
 }
 
-template <class P, class T, int OPA, int OPB, int TAG>
+// CM = 4: each complex product is four real products,
+//     Cr += ar br - ai bi,  Ci += ar bi + ai br;
+// CM = 3: three (the 3M form), accumulated separately and combined in the
+// epilogue,
+//     T1 += ar br,  T2 += ai bi,  T3 += (ar + ai)(br + bi),
+//     Cr = T1 - T2,  Ci = T3 - T1 - T2.
+// The 3M form does three quarters of the matrix-core work.  Its real part
+// is the conventional one; its imaginary part is bounded by a small multiple
+// of u (|Ar| + |Ai|)(|Br| + |Bi|) instead of u (|Ar||Bi| + |Ai||Br|), the
+// same order for operands whose real and imaginary parts are of similar
+// size (the stability analysis of the three-multiplication method).  Every
+// tile configuration uses the same form and the same k order, so the tile
+// still changes no bit of a result.
+template <class P, class T, int OPA, int OPB, int TAG, int CM>
 __global__ __launch_bounds__(T::kThreads)
 void zgemm_kernel(FlatLaunch L) {
   typedef typename P::lds_t Lt;
@@ -199,13 +223,16 @@ void zgemm_kernel(FlatLaunch L) {
     }
   };
 
+  constexpr int kS = CM == 3 ? 1 : 0;          // third accumulator set (3M)
   Acc accR[T::kTM][T::kTN], accI[T::kTM][T::kTN];
+  Acc accS[kS ? T::kTM : 1][kS ? T::kTN : 1];
 #pragma unroll
   for (int i = 0; i < T::kTM; ++i)
 #pragma unroll
     for (int j = 0; j < T::kTN; ++j) {
       accR[i][j] = Acc{0, 0, 0, 0};
       accI[i][j] = Acc{0, 0, 0, 0};
+      if (kS) accS[kS ? i : 0][kS ? j : 0] = Acc{0, 0, 0, 0};
     }
 
   // the inverse's update products (K = 16 or 64) read C before the k loop,
@@ -243,15 +270,31 @@ void zgemm_kernel(FlatLaunch L) {
       for (int i = 0; i < T::kTM; ++i) a[i] = As[buf][ia(kidx, wm * T::kWM + i * 16 + lrow)];
 #pragma unroll
       for (int j = 0; j < T::kTN; ++j) b[j] = Bs[buf][ib(kidx, wn * T::kWN + j * 16 + lrow)];
+      if (CM == 3) {
+        R as[T::kTM], bs[T::kTN];
 #pragma unroll
-      for (int i = 0; i < T::kTM; ++i) {
-        const R nai = -a[i].y;
+        for (int i = 0; i < T::kTM; ++i) as[i] = a[i].x + a[i].y;
 #pragma unroll
-        for (int j = 0; j < T::kTN; ++j) {
-          accR[i][j] = P::mfma(a[i].x, b[j].x, accR[i][j]);
-          accI[i][j] = P::mfma(a[i].x, b[j].y, accI[i][j]);
-          accR[i][j] = P::mfma(nai, b[j].y, accR[i][j]);
-          accI[i][j] = P::mfma(a[i].y, b[j].x, accI[i][j]);
+        for (int j = 0; j < T::kTN; ++j) bs[j] = b[j].x + b[j].y;
+#pragma unroll
+        for (int i = 0; i < T::kTM; ++i)
+#pragma unroll
+          for (int j = 0; j < T::kTN; ++j) {
+            accR[i][j] = P::mfma(a[i].x, b[j].x, accR[i][j]);
+            accI[i][j] = P::mfma(a[i].y, b[j].y, accI[i][j]);
+            accS[kS ? i : 0][kS ? j : 0] = P::mfma(as[i], bs[j], accS[kS ? i : 0][kS ? j : 0]);
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < T::kTM; ++i) {
+          const R nai = -a[i].y;
+#pragma unroll
+          for (int j = 0; j < T::kTN; ++j) {
+            accR[i][j] = P::mfma(a[i].x, b[j].x, accR[i][j]);
+            accI[i][j] = P::mfma(a[i].x, b[j].y, accI[i][j]);
+            accR[i][j] = P::mfma(nai, b[j].y, accR[i][j]);
+            accI[i][j] = P::mfma(a[i].y, b[j].x, accI[i][j]);
+          }
         }
       }
     }
@@ -274,30 +317,46 @@ void zgemm_kernel(FlatLaunch L) {
         const int gm = m0 + wm * T::kWM + i * 16 + P::row(r, lk);
         const int gn = n0 + wn * T::kWN + j * 16 + lrow;
         if (gm < M && gn < N) {
-          double2 v = cscale(alpha, make_double2((double)accR[i][j][r], (double)accI[i][j][r]));
+          double re, im;
+          if (CM == 3) {
+            const double t1 = (double)accR[i][j][r], t2 = (double)accI[i][j][r];
+            re = t1 - t2;
+            im = (double)accS[kS ? i : 0][kS ? j : 0][r] - t1 - t2;
+          } else {
+            re = (double)accR[i][j][r];
+            im = (double)accI[i][j][r];
+          }
+          double2 v = cscale(alpha, make_double2(re, im));
           if (useC) v = cadd(v, cscale(beta, kPreC ? cpre[i][j][r] : C[(long long)gm * ldc + gn]));
           D[(long long)gm * ldd + gn] = v;
         }
       }
 }
 
-template <class P, class T>
+template <class P, class T, int CM>
 hipError_t launch_ops(char opa, char opb, const FlatLaunch& l, hipStream_t s) {
   const int oa = (opa == 'C'), ob = (opb == 'C');
   dim3 grid(l.total), block(T::kThreads);
-  if (oa == 0 && ob == 0) hipLaunchKernelGGL((zgemm_kernel<P, T, 0, 0, 0>), grid, block, 0, s, l);
-  else if (oa == 0 && ob == 1) hipLaunchKernelGGL((zgemm_kernel<P, T, 0, 1, 0>), grid, block, 0, s, l);
-  else if (oa == 1 && ob == 0) hipLaunchKernelGGL((zgemm_kernel<P, T, 1, 0, 0>), grid, block, 0, s, l);
-  else hipLaunchKernelGGL((zgemm_kernel<P, T, 1, 1, 0>), grid, block, 0, s, l);
+  if (oa == 0 && ob == 0) hipLaunchKernelGGL((zgemm_kernel<P, T, 0, 0, 0, CM>), grid, block, 0, s, l);
+  else if (oa == 0 && ob == 1) hipLaunchKernelGGL((zgemm_kernel<P, T, 0, 1, 0, CM>), grid, block, 0, s, l);
+  else if (oa == 1 && ob == 0) hipLaunchKernelGGL((zgemm_kernel<P, T, 1, 0, 0, CM>), grid, block, 0, s, l);
+  else hipLaunchKernelGGL((zgemm_kernel<P, T, 1, 1, 0, CM>), grid, block, 0, s, l);
   return hipGetLastError();
 }
 
-template <class P>
-hipError_t launch_prec(int cfg, char opa, char opb, const FlatLaunch& l, hipStream_t s) {
+hipError_t launch_f64(int cfg, char opa, char opb, const FlatLaunch& l, hipStream_t s) {
   switch (cfg) {
-    case 1: return launch_ops<P, Cfg1>(opa, opb, l, s);
-    case 2: return launch_ops<P, Cfg2>(opa, opb, l, s);
-    default: return launch_ops<P, Cfg0>(opa, opb, l, s);
+    case 1: return launch_ops<MathF64, Cfg1, 3>(opa, opb, l, s);
+    case 2: return launch_ops<MathF64, Cfg2, 3>(opa, opb, l, s);
+    default: return launch_ops<MathF64, Cfg0, 3>(opa, opb, l, s);
+  }
+}
+
+hipError_t launch_f32(int cfg, char opa, char opb, const FlatLaunch& l, hipStream_t s) {
+  switch (cfg) {
+    case 1: return launch_ops<MathF32, Cfg1w, 4>(opa, opb, l, s);
+    case 2: return launch_ops<MathF32, Cfg2, 4>(opa, opb, l, s);
+    default: return launch_ops<MathF32, Cfg0, 4>(opa, opb, l, s);
   }
 }
 
@@ -309,18 +368,23 @@ int gemm_tile_m(int cfg) {
 int gemm_tile_n(int cfg) {
   return cfg == kGemmInvUpdate ? CfgU::BN : cfg == 1 ? Cfg1::BN : cfg == 2 ? Cfg2::BN : Cfg0::BN;
 }
+// kGemmMegaUpdate (and every other value) falls through to configuration 0
 // the inverse's update products use the small tile
 
 hipError_t launch_gemm(int cfg, bool fp32, char opa, char opb, const FlatLaunch& l,
                        hipStream_t s) {
   if (l.total <= 0 || l.nd <= 0) return hipSuccess;
   if (cfg == kGemmInvUpdate) {
-    hipLaunchKernelGGL((zgemm_kernel<MathF64, CfgU, 0, 0, 1>), dim3(l.total), dim3(CfgU::kThreads),
-                       0, s, l);
+    hipLaunchKernelGGL((zgemm_kernel<MathF64, CfgU, 0, 0, 1, 4>), dim3(l.total),
+                       dim3(CfgU::kThreads), 0, s, l);
     return hipGetLastError();
   }
-  return fp32 ? launch_prec<MathF32>(cfg, opa, opb, l, s)
-              : launch_prec<MathF64>(cfg, opa, opb, l, s);
+  if (cfg == kGemmMegaUpdate) {       // the inverse's rank-kMega updates (TAG 2)
+    hipLaunchKernelGGL((zgemm_kernel<MathF64, Cfg0, 0, 0, 2, 3>), dim3(l.total),
+                       dim3(Cfg0::kThreads), 0, s, l);
+    return hipGetLastError();
+  }
+  return fp32 ? launch_f32(cfg, opa, opb, l, s) : launch_f64(cfg, opa, opb, l, s);
 }
 
 }  // namespace qtx

@@ -305,27 +305,29 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
   }
 }
 
+// For the W-column panel at K0 (W = kSuper or kMega):
 // spanel[r][c] = A[r][K0 + c] - (r == p_{K0+c}),  sbrow[c][j] = A[p_{K0+c}][j]
-// outside [K0, K0 + kSuper) and 0 inside; c beyond the matrix are zero.
+// outside [K0, K0 + W) and 0 inside; c beyond the matrix are zero.
 __global__ __launch_bounds__(256)
-void gj_super_gather_kernel(FlatLaunch L, int K0) {
+void gj_super_gather_kernel(FlatLaunch L, int K0, int W) {
   const int di = find_desc(L.prefix, L.nd, blockIdx.x);
   const InvDesc& d = ((const InvDesc*)L.desc)[di];
   const int b = d.b;
-  const int chunks = super_gather_chunks(b);
+  const int chunks = super_gather_chunks(b, W);
   const int local = blockIdx.x - L.prefix[di];
   const long long e = local / chunks;
   const long long q0 = (long long)(local % chunks) * kGatherItems;
   const double2* A = (const double2*)d.S + e * d.sS;
   const int* pe = d.perm + e * b;
-  double2* sp = (double2*)d.spanel + e * (long long)b * kSuper;
-  double2* sb = (double2*)d.sbrow + e * (long long)kSuper * b;
-  const int spe = min(kSuper, b - K0);
-  const long long half = (long long)b * kSuper;
+  const int span = inv_span(b);
+  double2* sp = (double2*)d.spanel + e * (long long)b * span;
+  double2* sb = (double2*)d.sbrow + e * (long long)span * b;
+  const int spe = min(W, b - K0);
+  const long long half = (long long)b * W;
   const long long q1 = min(q0 + kGatherItems, 2 * half);
   for (long long q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
     if (q < half) {
-      const int r = (int)(q / kSuper), c = (int)(q % kSuper);
+      const int r = (int)(q / W), c = (int)(q % W);
       double2 v = make_double2(0.0, 0.0);
       if (c < spe) {
         v = A[(long long)r * b + K0 + c];
@@ -392,9 +394,10 @@ hipError_t launch_inv_panel(int R, int k0, const FlatLaunch& l, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_inv_super_gather(int K0, const FlatLaunch& l, hipStream_t s) {
+hipError_t launch_inv_super_gather(int K0, int W, const FlatLaunch& l, hipStream_t s) {
   if (l.total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gj_super_gather_kernel, dim3(l.total), dim3(256), 0, s, l, K0);
+  if (W != kSuper && W != kMega) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gj_super_gather_kernel, dim3(l.total), dim3(256), 0, s, l, K0, W);
   return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ QTX_KIND_W = 1
 QTX_FP64 = 0
 QTX_MIXED = 1
 QTX_FLAG_PROFILE = 1
+QTX_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 KERNEL_CLASSES = {"zgemm": 0, "cgemm": 1, "inverse": 2, "elementwise": 3}
 

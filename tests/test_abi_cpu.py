@@ -93,3 +93,10 @@ def test_occupation_arrays_are_checked_before_the_call():
     ctx = Q.Context.__new__(Q.Context)            # no device: the check comes first
     with pytest.raises(ValueError):
         Q.Context.obc_lesser_greater(ctx, 4, 3, None, 0, np.ones(2), np.ones(3), None, None)
+
+
+def test_noalloc_scratch_size_matches_header():
+    src = open(HEADER).read()
+    m = re.search(r"#define QTX_NOALLOC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", src)
+    assert m, "QTX_NOALLOC_SCRATCH_BYTES not found"
+    assert Q.QTX_NOALLOC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))

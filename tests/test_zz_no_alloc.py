@@ -61,9 +61,24 @@ def test_noalloc_equals_zinv_two_calls_second_smaller(ctx):
             assert err < 1e-12, (b, e, err)
 
 
+def _work_bytes(b, batch):
+    """Scratch bytes of one call, as the header states them."""
+    up = lambda x: (x + 255) // 256 * 256
+    w = 64 if b <= 256 else 256
+    return 2 * up(batch * b * 16 * 16) + 2 * up(batch * b * w * 16) + 2 * up(batch * b * 4)
+
+
+def _largest_batch(b):
+    n = 1
+    while _work_bytes(b, n + 1) <= Q.QTX_NOALLOC_SCRATCH_BYTES:
+        n += 1
+    return n
+
+
 def test_noalloc_largest_batch_that_fits(ctx):
-    # 51 matrices of 512 fill the 64 MiB scratch (1,314,816 bytes each)
-    b, batch = 512, 51
+    b = 512
+    batch = _largest_batch(b)                  # 15 matrices of 512 fill 64 MiB
+    assert batch == 15
     A = _batch(13, b, batch)
     x1, x2, i1, i2 = _both(ctx, A)
     assert np.all(i2 == 0)
@@ -71,7 +86,8 @@ def test_noalloc_largest_batch_that_fits(ctx):
 
 
 def test_noalloc_refuses_oversized_call(ctx):
-    b, batch = 512, 52
+    b = 512
+    batch = _largest_batch(b) + 1
     a = torch.zeros((batch, b, b), dtype=torch.complex128, device=DEV)
     x = torch.empty_like(a)
     info = torch.zeros(batch, dtype=torch.int32, device=DEV)
