@@ -50,10 +50,11 @@ HBM_PEAK_GBS = 8000.0
 # --pmc FETCH_SIZE and WRITE_SIZE runs of this default workload (the
 # recursion's real launch mix, 810 product launches), each scaled by the
 # same counter on a 1 GiB device copy in the same run (FETCH_SIZE reads 0.500
-# of the copied bytes, WRITE_SIZE 1.000): 1554326 KiB x 2 read + 968314 KiB
-# written per launch against 3.303e9 algorithmic bytes.  None once the
+# of the copied bytes, WRITE_SIZE 1.000): 1608419 KiB x 2 read + 968314 KiB
+# written per launch against 3.3445e9 algorithmic bytes (A, B, D, and C or
+# the assembled C's sources).  None once the
 # kernel changes.
-MEASURED_TRAFFIC_FACTOR = (1554326.0 * 2.0 + 968314.0) * 1024.0 / 3303413117.7876544
+MEASURED_TRAFFIC_FACTOR = (1608419.0 * 2.0 + 968314.0) * 1024.0 / 3344506940.68
 
 
 def parse():
@@ -334,7 +335,7 @@ def run_plain(args, mixed=False):
         out["symmetric_storage"] = {
             "lower_blocks_not_written": 2 * (n - 1) * n_e,
             "hbm_saved_bytes": 2 * (n - 1) * n_e * blk,
-            "output_bytes": (3 * (2 * n - 1) + n) * n_e * blk,
+            "output_bytes_written": ((3 * n - 2) + 2 * (2 * n - 1)) * n_e * blk,
             "energies_per_lane": n_e,
             "what": "X^< and X^> lower blocks left to the caller as -upper^dagger (Sec. 4.2)"}
     if mixed:

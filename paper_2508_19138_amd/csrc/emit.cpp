@@ -256,14 +256,13 @@ void build_lane(Lane& lane, const qtx_rgf_problem& p, const Plan& q, char* ws,
     }
     s.set_fp32(q.fp32);
     run_core(s, k, [&](int i) {
-      LinCombDesc a{};
+      LinCombDesc a{};          // Mt_ii = E S_ii - H_ii - Sigma^R_ii
       a.E = E;
       if (Sd.ok()) { a.src[0] = Sd.at(i); a.sSrc[0] = 0; a.d[0] = kOne; }
       else a.idc1 = kOne;
       a.src[1] = Hd.at(i); a.sSrc[1] = 0; a.c[1] = kMinus;
       a.src[2] = SRd.at(i); a.sSrc[2] = SRd.es; a.c[2] = kMinus;
-      a.D = k.tS.w(0); a.sD = k.tS.es;
-      s.lincomb(a);
+      return a;
     });
     s.set_fp32(false);
   } else {
@@ -289,7 +288,11 @@ void build_lane(Lane& lane, const qtx_rgf_problem& p, const Plan& q, char* ws,
     w_assemble(s, w, n, q.nr);
     k.U = w.Au; k.L = w.Al; k.su = 1.0; k.sl = 1.0;
     s.set_fp32(q.fp32);
-    run_core(s, k, [&](int i) { s.copy(k.tS, 0, w.Ad, i); });
+    run_core(s, k, [&](int i) {
+      LinCombDesc a{};          // Mt_ii as assembled by w_assemble
+      a.src[0] = w.Ad.at(i); a.sSrc[0] = w.Ad.es; a.c[0] = kOne;
+      return a;
+    });
     s.set_fp32(false);
     if (p.WR_diag) {
       // W^R_ii = X_ii V_ii + X_{i,i-1} V_{i-1,i} + X_{i,i+1} V_{i+1,i}

@@ -77,6 +77,41 @@ class Emitter {
     L_.ops.push_back(o);
   }
 
+  // D = alpha * op(A) op(B) + C with C assembled in the product's epilogue
+  // from the linear combination `c` (its D and batch fields are unused).
+  void gemm_asm(char opa, char opb, const Opnd& A, const Opnd& B, const View& D, long long id,
+                zc alpha, const LinCombDesc& c) {
+    Op o;
+    o.k = OpK::Gemm;
+    o.opa = opa; o.opb = opb; o.fp32 = fp32_;
+    o.cfg = T_.cfg(b_, b_, b_, fp32_, s_);
+    o.first = (int)L_.gd.size();
+    GemmDesc g{};
+    g.A = A.v.at(A.i); g.sA = A.v.es; g.tA = A.v.bs;
+    g.B = B.v.at(B.i); g.sB = B.v.es; g.tB = B.v.bs;
+    g.D = D.w(id); g.sD = D.es; g.tD = D.bs;
+    g.lda = g.ldb = g.ldc = g.ldd = b_;
+    g.alpha = alpha;
+    g.beta = kZero;
+    g.M = g.N = g.K = b_;
+    g.batch = ec_;
+    g.batch2 = 1;
+    g.asm_ = 1;
+    for (int t = 0; t < 3; ++t) {
+      g.X[t] = c.src[t]; g.sX[t] = c.sSrc[t];
+      g.xc[t] = c.c[t]; g.xd[t] = c.d[t];
+    }
+    g.i0 = c.idc0; g.i1 = c.idc1;
+    g.E = c.E;
+    L_.gd.push_back(g);
+    o.count = 1;
+    o.flops = 8.0 * blk_ * b_ * (double)ec_;
+    int nsrc = 0;
+    for (int t = 0; t < 3; ++t) nsrc += c.src[t] != nullptr;
+    o.bytes = 16.0 * blk_ * (3.0 + nsrc) * ec_;
+    L_.ops.push_back(o);
+  }
+
   void inverse(const View& S, long long is, const View& X, long long ix, void* panel,
                void* brow, void* spanel, void* sbrow, int* perm, int* used, int* info,
                int code, bool reset) {
@@ -224,7 +259,10 @@ inline void prods(Emitter& s, std::initializer_list<Prod> ps) {
   }
 }
 
-// Forward and backward passes, given a callback that writes Mt_ii into tS.
+// Forward and backward passes, given a callback that describes Mt_ii as a
+// linear combination (LinCombDesc without destination).  Mt_00 is written by
+// an elementwise pass; every later Mt_ii is assembled in the epilogue of the
+// Schur update Mt_ii - F U_{i-1} (no separate pass, no extra block in HBM).
 template <class PrepDiag>
 void run_core(Emitter& s, const Core& k, PrepDiag prep_diag) {
   const int n = k.n;
@@ -240,7 +278,11 @@ void run_core(Emitter& s, const Core& k, PrepDiag prep_diag) {
   const View* none = nullptr;
 
   // ---- forward pass ----------------------------------------------------
-  prep_diag(0);
+  {
+    LinCombDesc a = prep_diag(0);
+    a.D = k.tS.w(0); a.sD = k.tS.es;
+    s.lincomb(a);
+  }
   inv(0);
   if (nr >= 1) {
     // x^s_0 = x_0 B_00 x_0^dag
@@ -258,8 +300,10 @@ void run_core(Emitter& s, const Core& k, PrepDiag prep_diag) {
   for (int i = 1; i < n; ++i) {
     // F = L_{i-1} x_{i-1};  Mt_ii - F U_{i-1}  -> inverse -> x_i
     prods(s, {Prod{k.tF, 0, Lr(i - 1), SN(k.xR, i - 1), none, 0, 1.0, 0.0}});
-    prep_diag(i);
-    prods(s, {Prod{k.tS, 0, SN(k.tF, 0), Ur(i - 1), &k.tS, 0, -1.0, 1.0}});
+    {
+      const Src u = Ur(i - 1);
+      s.gemm_asm('N', u.op, Opnd{k.tF, 0}, Opnd{u.v, u.i}, k.tS, 0, rs(-u.sg), prep_diag(i));
+    }
     inv(i);
     if (nr == 0) continue;
     // W = B_ii + L x^s_{i-1} L^dag - y + y^dag;  x^s_i = x_i W x_i^dag

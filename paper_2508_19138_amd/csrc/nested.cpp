@@ -704,7 +704,11 @@ void nested_chunk(qtx_rgf_ctx* c, const qtx_rgf_problem& p, const qtx_rgf_nested
       k.rhs.push_back(h);
     }
     s.set_fp32(q.fp32);
-    run_core(s, k, [&](int i) { s.copy(k.tS, 0, L.Sd, i); });
+    run_core(s, k, [&](int i) {
+      LinCombDesc a{};          // the reduced system's diagonal block
+      a.src[0] = L.Sd.at(i); a.sSrc[0] = L.Sd.es; a.c[0] = kOne;
+      return a;
+    });
     s.set_fp32(false);
     run({l});
   }

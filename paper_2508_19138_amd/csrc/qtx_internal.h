@@ -41,6 +41,16 @@ struct GemmDesc {
   int M, N, K;
   int batch, batch2;
   int tiles;            // workgroups per matrix (set by the launcher's config)
+  // asm != 0 (C null, batch2 1, square blocks): the C term is assembled in
+  // the epilogue, C[e] = (i0 + i1 E[e]) I + sum_t (xc_t + xd_t E[e]) X_t[e],
+  // X_t[e] at X_t + e * sX_t (ld ldc; null terms skipped) -- the diagonal
+  // block E S - H - Sigma^R formed where the Schur update is written
+  int asm_;
+  const void* X[3];
+  long long sX[3];
+  zc xc[3], xd[3];
+  zc i0, i1;
+  const double* E;
 };
 
 // Tile configurations of the product kernel (see zgemm.hip); the extra

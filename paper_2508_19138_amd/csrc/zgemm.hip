@@ -67,12 +67,14 @@ struct Cfg {
 // wave); FP32 products and the inverse's thin update products the
 // four-product form (FP32's 3M form measured 4x less accurate in the
 // partitioned solve).
-typedef Cfg<64, 64, 16, 2, 2> Cfg0;     // general: 32 x 32 per wave
+typedef Cfg<64, 64, 8, 2, 2> Cfg0;      // general, 3M: 32 x 32 per wave, three waves per SIMD
+typedef Cfg<64, 64, 16, 2, 2> Cfg0w;    // general, four products
 typedef Cfg<128, 64, 8, 4, 2> Cfg1;    // large blocks, 3M: eight waves of 32 x 32
 typedef Cfg<128, 64, 8, 2, 2> Cfg1w;   // large blocks, four products: 64 x 32 per wave
 typedef Cfg<32, 32, 16, 2, 2> Cfg2;     // small blocks
 typedef Cfg<32, 32, 16, 2, 2> CfgU;     // the inverse's update products
 static_assert(Cfg1w::BM == Cfg1::BM && Cfg1w::BN == Cfg1::BN, "one tile shape per configuration");
+static_assert(Cfg0w::BM == Cfg0::BM && Cfg0w::BN == Cfg0::BN, "one tile shape per configuration");
 static_assert(CfgU::BM == kInvUpdTile && CfgU::BN == kInvUpdTile, "update tile");
 static_assert(Cfg0::BM == kMegaTile && Cfg0::BN == kMegaTile, "mega tile");
 
@@ -308,6 +310,19 @@ void zgemm_kernel(FlatLaunch L) {
   const bool useC = (g.beta.re != 0.0 || g.beta.im != 0.0) && C != nullptr;
   const zc alpha = g.alpha, beta = g.beta;
   const long long ldc = g.ldc, ldd = g.ldd;
+  // assembled C (same order of terms as the elementwise assembly pass)
+  const bool asmC = TAG == 0 && g.asm_ != 0;
+  zc aco[3] = {}, aid = {};
+  const double2* __restrict__ AX[3] = {nullptr, nullptr, nullptr};
+  if (asmC) {
+    const double Ee = g.E ? g.E[e] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      aco[t] = zc{g.xc[t].re + g.xd[t].re * Ee, g.xc[t].im + g.xd[t].im * Ee};
+      AX[t] = g.X[t] ? (const double2*)g.X[t] + e * g.sX[t] : nullptr;
+    }
+    aid = zc{g.i0.re + g.i1.re * Ee, g.i0.im + g.i1.im * Ee};
+  }
 #pragma unroll
   for (int i = 0; i < T::kTM; ++i)
 #pragma unroll
@@ -328,6 +343,14 @@ void zgemm_kernel(FlatLaunch L) {
           }
           double2 v = cscale(alpha, make_double2(re, im));
           if (useC) v = cadd(v, cscale(beta, kPreC ? cpre[i][j][r] : C[(long long)gm * ldc + gn]));
+          if (asmC) {
+            const long long q = (long long)gm * ldc + gn;
+            double2 cv = gm == gn ? make_double2(aid.re, aid.im) : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+              if (AX[t]) cv = cadd(cv, cscale(aco[t], AX[t][q]));
+            v = cadd(v, cv);
+          }
           D[(long long)gm * ldd + gn] = v;
         }
       }
@@ -356,7 +379,7 @@ hipError_t launch_f32(int cfg, char opa, char opb, const FlatLaunch& l, hipStrea
   switch (cfg) {
     case 1: return launch_ops<MathF32, Cfg1w, 4>(opa, opb, l, s);
     case 2: return launch_ops<MathF32, Cfg2, 4>(opa, opb, l, s);
-    default: return launch_ops<MathF32, Cfg0, 4>(opa, opb, l, s);
+    default: return launch_ops<MathF32, Cfg0w, 4>(opa, opb, l, s);
   }
 }
 
