@@ -33,9 +33,23 @@ COMMON = [
 ]
 
 
+# Per-source options.  zinv.hip: the panel kernel keeps R rows of the panel
+# in registers, which needs every loop over them fully unrolled (the
+# largest instance exceeds the default size limit of a requested unroll)
+# and no indexed access to them: the candidate row is copied out of one of
+# the R rows chosen at run time, written as one branch per row, and sinking
+# the branches' common stores into one block would turn that into an
+# indexed access and move the whole row array to scratch memory.
+PER_FILE = {
+    "zinv.hip": ["-mllvm", "-simplifycfg-sink-common=false",
+                 "-mllvm", "-pragma-unroll-threshold=200000"],
+}
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + ["-x", "hip", "-c", src, "-o", obj]
+    extra = PER_FILE.get(os.path.basename(src), [])
+    cmd = [HIPCC] + COMMON + extra + ["-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

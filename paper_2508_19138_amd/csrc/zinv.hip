@@ -27,56 +27,125 @@
 namespace qtx {
 namespace {
 
-// Pivot search key of a candidate row r with |z|^2 = v (finite, >= 0): the
-// bits of v with the low 10 mantissa bits replaced by 1023 - r.  Keys order
-// as v (to 42 mantissa bits) and then by lowest row, so the maximum key is
-// the partial-pivoting choice and names its row; non-candidates use -1.
-__device__ __forceinline__ double pivot_key(double v, int r) {
-  const unsigned long long u = ((unsigned long long)__double_as_longlong(v) & ~1023ull) |
-                               (unsigned long long)(1023 - r);
-  return __longlong_as_double((long long)u);
+// Pivot search key of a candidate row r (< 1024) with |z|^2 = v (finite,
+// >= 0): bits 62..42 of v (its exponent and top 10 mantissa bits) above the
+// 10 bits of 1023 - r, plus one; 0 means no candidate.  Keys order as v to
+// a relative 2^-10 and then by lowest row, so the largest key picks a pivot
+// whose |z|^2 is within 0.1% of the column's largest (partial pivoting: the
+// growth bound is that of the exact choice up to that factor) and names its
+// row.  32-bit keys make the wave reduction one DPP max per step.
+__device__ __forceinline__ unsigned pivot_key(double v, int r) {
+  const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(v) >> 42);
+  return ((hi << 10) | (unsigned)(1023 - r)) + 1u;
 }
-__device__ __forceinline__ int pivot_row(double key) {
-  return 1023 - (int)((unsigned long long)__double_as_longlong(key) & 1023ull);
+__device__ __forceinline__ int pivot_row(unsigned key) {
+  return 1023 - (int)((key - 1u) & 1023u);
 }
 
-// x moved across lanes by a DPP pattern (both 32-bit halves)
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double x) {
-  const long long v = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffff), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xf, 0xf, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+// x combined with its value in another lane moved by a DPP pattern (lanes
+// of rows outside row_mask see 0, the identity of the unsigned maximum)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned dpp_max(unsigned x) {
+  const unsigned y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xf, false);
+  return x > y ? x : y;
 }
 
 // Maximum over the 64 lanes of a wave, returned in every lane: within rows
-// of 16 lanes by DPP (quad xor 1, quad xor 2, half-row mirror, row mirror,
-// after which every lane holds its row's maximum), then across the four
-// rows through scalar reads of one lane per row.
-__device__ __forceinline__ double lane_read(double x, int l) {
-  const long long v = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), l);
-  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double wave_max(double x) {
-  x = fmax(x, dpp_move<0xB1>(x));     // quad_perm [1,0,3,2]
-  x = fmax(x, dpp_move<0x4E>(x));     // quad_perm [2,3,0,1]
-  x = fmax(x, dpp_move<0x141>(x));    // row_half_mirror
-  x = fmax(x, dpp_move<0x140>(x));    // row_mirror
-  return fmax(fmax(lane_read(x, 0), lane_read(x, 16)), fmax(lane_read(x, 32), lane_read(x, 48)));
+// of 16 lanes (quad xor 1, quad xor 2, half-row mirror, row mirror: every
+// lane then holds its row's maximum), then lane 15 into rows 1 and 3 and
+// lane 31 into rows 2 and 3, after which lane 63 holds the maximum.
+__device__ __forceinline__ unsigned wave_max(unsigned x) {
+  x = dpp_max<0xB1, 0xf>(x);     // quad_perm [1,0,3,2]
+  x = dpp_max<0x4E, 0xf>(x);     // quad_perm [2,3,0,1]
+  x = dpp_max<0x141, 0xf>(x);    // row_half_mirror
+  x = dpp_max<0x140, 0xf>(x);    // row_mirror
+  x = dpp_max<0x142, 0xa>(x);    // row_bcast:15
+  x = dpp_max<0x143, 0xc>(x);    // row_bcast:31
+  return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
 }
 
-// One division: z is scaled by an exact power of two so that |z'|^2 lies in
-// [1, 8), then 1/z = conj(z') / |z'|^2 scaled back.
+// 1/z without branches: z is scaled by an exact power of two so that
+// d = |z'|^2 lies in [1/4, 2), then 1/z = conj(z') / d scaled back, with 1/d
+// from the hardware reciprocal estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - d r), each of which squares the relative error (the
+// estimate's is far below 2^-20, so the result is within a few ulp).  z = 0
+// gives non-finite values; the caller flags that pivot.
 __device__ __forceinline__ double2 crecip_scaled(double2 z) {
   const double s = fmax(fabs(z.x), fabs(z.y));
-  if (s == 0.0) return make_double2(1.0 / s, 0.0);   // inf: caller flags it
   int ex;
   (void)frexp(s, &ex);
   const double xr = ldexp(z.x, -ex), xi = ldexp(z.y, -ex);
-  const double r = 1.0 / (xr * xr + xi * xi);
+  const double d = fma(xr, xr, xi * xi);
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
   return make_double2(ldexp(xr * r, -ex), ldexp(-xi * r, -ex));
+}
+
+// a -= g * x (complex), four fused multiply-adds
+__device__ __forceinline__ void axpy_neg(double2& a, double2 g, double2 x) {
+  a.x = fma(-g.x, x.x, fma(g.y, x.y, a.x));
+  a.y = fma(-g.x, x.y, fma(-g.y, x.x, a.y));
+}
+
+// This thread's best pivot key in panel column c over its unused rows
+// (0 if none); bad is set for a non-finite candidate.
+// Pins the computation of v where it stands: without it the compiler moves
+// the reciprocal into the one lane that stores it, after the update it is
+// meant to overlap.
+__device__ __forceinline__ void keep(double2 v) { asm volatile("" ::"v"(v.x), "v"(v.y)); }
+
+// A value written to LDS by one lane is read by the other lanes of its
+// wave: LDS operations of a wave are performed in order, so only the
+// compiler has to keep the read after the write.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int R>
+__device__ __forceinline__ unsigned col_key(const double2 (&a)[R][kPanel], const int (&u)[R],
+                                            int c, int t, int& bad) {
+  unsigned key = 0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    if (!u[q]) {
+      const double v = a[q][c].x * a[q][c].x + a[q][c].y * a[q][c].y;
+      if (!(v <= 1.7976931348623157e308)) bad = 1;     // NaN or Inf
+      else {
+        const unsigned k = pivot_key(v, t + q * kInvThreads);
+        key = k > key ? k : key;
+      }
+    }
+  }
+  return key;
+}
+
+// The lane holding its wave's best candidate (keys are distinct) stores
+// that row's element in column c, or the whole row.
+template <int R>
+__device__ __forceinline__ void publish_elem(const double2 (&a)[R][kPanel], unsigned key,
+                                             unsigned wk, int c, int t, double2* dst) {
+  if (wk != 0 && key == wk) {
+    const int qs = (pivot_row(wk) - t) / kInvThreads;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (q == qs) *dst = a[q][c];
+  }
+}
+template <int R>
+__device__ __forceinline__ void publish_row(const double2 (&a)[R][kPanel], unsigned key,
+                                            unsigned wk, int t, double2* dst) {
+  if (wk != 0 && key == wk) {
+    const int qs = (pivot_row(wk) - t) / kInvThreads;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (q == qs) {
+#pragma unroll
+        for (int cc = 0; cc < kPanel; ++cc) dst[cc] = a[q][cc];
+      }
+  }
 }
 
 template <int R>
@@ -84,11 +153,15 @@ __global__ __launch_bounds__(kInvThreads)
 void gj_panel_kernel(FlatLaunch L, int k0) {
   constexpr int NB = kPanel;
   constexpr int NW = kInvThreads / 64;
-  // per column: each wave publishes its best key and that candidate's row;
-  // double buffered by column parity so one barrier per column suffices
-  __shared__ double keyS[2][NW];
+  // per column: each wave publishes its best key, that candidate's row and
+  // the reciprocal of its pivot element; double buffered by column parity
+  // so one barrier per column suffices
+  __shared__ unsigned keyS[2][NW];
   __shared__ int badS[2][NW];
   __shared__ double2 rowS[2][NW][NB];
+  __shared__ double2 invS[2][NW];   // reciprocal of the candidate's pivot element
+  __shared__ double2 elemS[NW];     // the candidate's pivot element
+  __shared__ double2 pinvS[NB];     // reciprocal pivot of each panel column
   __shared__ int pivs[NB];
 
   const int di = find_desc(L.prefix, L.nd, blockIdx.x);
@@ -153,100 +226,131 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
   // candidates and their elimination leaves them zero: no bounds tests in
   // the column loop.  Values read back from LDS are uniform across the
   // workgroup, so the failure bookkeeping branches uniformly.
+  //
+  // Pivot rows are left unscaled while the panel is eliminated: the row
+  // chosen for column c keeps its values with 1 in column c, and the later
+  // eliminations (linear in the row) act on it unchanged, so scaling it by
+  // the reciprocal pivot once after the last column gives the same panel.
+  // Non-pivot rows take the multiplier g = a[r][c] / pivot.  Column c + 1 is
+  // updated first: its pivot search, and the reciprocal of each wave's
+  // candidate (read back through LDS by the whole wave), then overlap the
+  // update of the other columns.
   int first_bad = 0;
   int pv_reg[NB];
+  {
+    int bad = 0;
+    const unsigned key = col_key<R>(a, u, 0, t, bad);
+    const unsigned wk = wave_max(key);
+    publish_elem<R>(a, key, wk, 0, t, &elemS[wave]);
+    wave_sync();
+    const double2 inv0 = crecip_scaled(elemS[wave]);   // stale (unused) without a candidate
+    publish_row<R>(a, key, wk, t, rowS[0][wave]);
+    const int wbad = __any(bad);
+    if (lane == 0) { keyS[0][wave] = wk; badS[0][wave] = wbad; invS[0][wave] = inv0; }
+  }
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     if (c >= nbe) continue;      // uniform across the workgroup
     const int par = c & 1;
-    // ---- pivot search over unused rows -------------------------------
-    double key = -1.0;
-    int bad = 0;
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int r = t + q * kInvThreads;
-      if (!u[q]) {
-        const double v = a[q][c].x * a[q][c].x + a[q][c].y * a[q][c].y;
-        if (!(v <= 1.7976931348623157e308)) bad = 1;     // NaN or Inf
-        else key = fmax(key, pivot_key(v, r));
-      }
-    }
-    const double wk = wave_max(key);
-    // the lane holding the wave's best candidate (keys are distinct) stores
-    // that row for the other waves
-    if (wk >= 0.0 && key == wk) {
-      const int qs = (pivot_row(wk) - t) / kInvThreads;
-#pragma unroll
-      for (int q = 0; q < R; ++q)
-        if (q == qs) {
-#pragma unroll
-          for (int cc = 0; cc < NB; ++cc) rowS[par][wave][cc] = a[q][cc];
-        }
-    }
-    const int wbad = __any(bad);
-    if (lane == 0) { keyS[par][wave] = wk; badS[par][wave] = wbad; }
     __syncthreads();
-    double bk = keyS[par][0];
+    unsigned bk = keyS[par][0];
     int bw = 0, anybad = badS[par][0];
 #pragma unroll
     for (int w = 1; w < NW; ++w) {
-      const double ok = keyS[par][w];
+      const unsigned ok = keyS[par][w];
       if (ok > bk) { bk = ok; bw = w; }
       anybad |= badS[par][w];
     }
     // An unused row always remains (b - k0 - c > 0), so a candidate exists
     // unless every one was non-finite; then row 0 keeps indices in range
     // and the failure is reported through info.
-    int p = (bk >= 0.0) ? pivot_row(bk) : 0;
+    int p = bk ? pivot_row(bk) : 0;
     if (p >= b) p = 0;
+    // what the multipliers and column c + 1 need is read first
+    const double2 inv = invS[par][bw];
+    // (the winning wave as a scalar, so that the 16 reads share one
+    // address register and differ in their offsets)
+    const double2* src = &rowS[par][0][0] + __builtin_amdgcn_readfirstlane(bw) * NB;
     double2 prow[NB];
+    if (c + 1 < NB) prow[c + 1] = src[c + 1];
+    prow[c] = src[c];
 #pragma unroll
-    for (int cc = 0; cc < NB; ++cc) prow[cc] = rowS[par][bw][cc];
-    if (first_bad == 0) {
+    for (int cc = 0; cc < NB; ++cc)
+      if (cc != c && cc != c + 1) prow[cc] = src[cc];
+    {
       const int code = code0 > 0 ? code0 : 1 + k0 + c;
       const double pv = prow[c].x * prow[c].x + prow[c].y * prow[c].y;
-      if (anybad || bk < 0.0) first_bad = -code;
-      else if (pv <= 0.0) first_bad = code;
+      const int st = (anybad || bk == 0) ? -code : (pv <= 0.0 ? code : 0);
+      first_bad = first_bad != 0 ? first_bad : st;
     }
     pv_reg[c] = p;
+    // multipliers; the pivot row takes none (it stays as it is)
+    bool isp[R];
+    double2 g[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const bool isp = (t + q * kInvThreads == p);
-      u[q] |= isp;
-      pc[q] = isp ? c : pc[q];
+      isp[q] = (t + q * kInvThreads == p);
+      u[q] |= isp[q];
+      pc[q] = isp[q] ? c : pc[q];
+      const double2 m = cmul(a[q][c], inv);
+      g[q] = isp[q] ? make_double2(0.0, 0.0) : m;
     }
-    // ---- eliminate column k0 + c from every row ---------------------
-    // every row as a non-pivot row, then the pivot row is replaced by the
-    // scaled pivot row (its own update is discarded)
-    const double2 inv = crecip_scaled(prow[c]);
-    double2 ps[NB];
+    // ---- column c + 1 first, and the next pivot search
+    const bool nxt = c + 1 < nbe;  // uniform across the workgroup
+    unsigned key1 = 0, wk1 = 0;
+    int bad1 = 0;
+    if (c + 1 < NB) {
 #pragma unroll
-    for (int cc = 0; cc < NB; ++cc) ps[cc] = (cc == c) ? inv : cmul(prow[cc], inv);
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      // a -= f * ps as four fused multiply-adds per element; column c
-      // becomes -f * inv
-      const double fx = a[q][c].x, fy = a[q][c].y;
-#pragma unroll
-      for (int cc = 0; cc < NB; ++cc) {
-        const double2 z = (cc == c) ? make_double2(0.0, 0.0) : a[q][cc];
-        a[q][cc].x = fma(-fx, ps[cc].x, fma(fy, ps[cc].y, z.x));
-        a[q][cc].y = fma(-fx, ps[cc].y, fma(-fy, ps[cc].x, z.y));
+      for (int q = 0; q < R; ++q) axpy_neg(a[q][c + 1], g[q], prow[c + 1]);
+      if (nxt) {
+        key1 = col_key<R>(a, u, c + 1, t, bad1);
+        wk1 = wave_max(key1);
+        publish_elem<R>(a, key1, wk1, c + 1, t, &elemS[wave]);
       }
+    }
+    // outside the branch, so that it interleaves with the update below
+    // (without a next column it reads a stale element and is not used)
+    wave_sync();
+    const double2 inv1 = crecip_scaled(elemS[wave]);
+    keep(inv1);
+    // ---- the other columns
+#pragma unroll
+    for (int cc = 0; cc < NB; ++cc) {
+      if (cc == c || cc == c + 1) continue;
+#pragma unroll
+      for (int q = 0; q < R; ++q) axpy_neg(a[q][cc], g[q], prow[cc]);
     }
 #pragma unroll
     for (int q = 0; q < R; ++q)
-      if (t + q * kInvThreads == p) {
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc) a[q][cc] = ps[cc];
+      a[q][c] = isp[q] ? make_double2(1.0, 0.0) : make_double2(-g[q].x, -g[q].y);
+    if (c + 1 < NB && nxt) {
+      publish_row<R>(a, key1, wk1, t, rowS[par ^ 1][wave]);
+      const int wbad = __any(bad1);
+      if (lane == 0) {
+        keyS[par ^ 1][wave] = wk1;
+        badS[par ^ 1][wave] = wbad;
+        invS[par ^ 1][wave] = inv1;
       }
+    }
+    if (t == 0) pinvS[c] = inv;
   }
   if (t == 0) {
 #pragma unroll
     for (int c = 0; c < NB; ++c)
       if (c < nbe) pivs[c] = pv_reg[c];
   }
-  __syncthreads();                 // pivs[] complete before the write-back
+  __syncthreads();                 // pivs[], pinvS[] complete
+
+  // ---- scale the pivot rows by their reciprocal pivots
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    if (pc[q] >= 0) {
+      const double2 s = pinvS[pc[q]];
+#pragma unroll
+      for (int cc = 0; cc < NB; ++cc)
+        if (cc < nbe) a[q][cc] = cmul(a[q][cc], s);
+    }
+  }
 
   // ---- pivot rows within the super-panel (this panel's columns zeroed):
   // they lie outside the panel columns, so they are read before the panel
