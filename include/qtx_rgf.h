@@ -108,7 +108,7 @@ typedef struct {
   int32_t kind;        /* qtx_kind                                           */
   int32_t precision;   /* qtx_precision                                      */
   int32_t n_blocks;    /* n >= 1                                             */
-  int32_t block_size;  /* b >= 1                                             */
+  int32_t block_size;  /* 1 <= b <= 4096                                     */
   int32_t n_energies;  /* N_E >= 1                                           */
   int32_t flags;       /* reserved, must be 0                                */
   const double* energies; /* host, [N_E] real energies (G-type; W ignores)   */
@@ -307,11 +307,16 @@ qtx_status qtx_rgf_cgemm(qtx_rgf_ctx* ctx, char opa, char opb, int32_t m,
                          int64_t sD, int32_t batch);
 
 /* Batched inverse of b x b complex128 matrices by Gauss-Jordan elimination
- * with partial pivoting (largest |z| in the pivot column; ties to the lowest
- * row).  A [batch][b][b] is overwritten (used as workspace); the inverses
- * are written to X [batch][b][b].  info[batch] (device int32, may be NULL)
- * receives 0, or 1 + the column of the first exactly zero pivot, or
- * -(1 + column) for a non-finite pivot. */
+ * with partial pivoting (largest |z| in the pivot column to a relative 0.1%
+ * in |z|^2; ties to the lowest row), 1 <= b <= 4096.  Above b = 1024 the
+ * pivot rows of each 16-column panel are chosen by a tournament (each chunk
+ * of 768 rows proposes the rows its own elimination pivots on, and the
+ * elimination of the proposed rows picks among them), which is stable in
+ * practice though its worst-case growth bound is weaker.  A [batch][b][b]
+ * is overwritten (used as workspace); the inverses are written to X
+ * [batch][b][b].  info[batch] (device int32, may be NULL) receives 0, or
+ * 1 + the column of the first exactly zero pivot, or -(1 + column) for a
+ * non-finite pivot. */
 qtx_status qtx_rgf_zinv(qtx_rgf_ctx* ctx, int32_t b, void* A, void* X,
                         int32_t* info, int32_t batch);
 
@@ -331,7 +336,7 @@ qtx_status qtx_rgf_zinv(qtx_rgf_ctx* ctx, int32_t b, void* A, void* X,
  *     b <= 256, else 256) plus 8 * batch * b bytes of pivot bookkeeping (each
  *     part rounded up to 256 bytes) must fit QTX_NOALLOC_SCRATCH_BYTES; larger
  *     calls return QTX_ERR_INVALID_ARG with the sizes in qtx_rgf_last_error
- *     (e.g. at most 102 matrices of 256, 15 of 512, 7 of 1024).
+ *     (e.g. at most 102 matrices of 256, 15 of 512, 7 of 1024); b <= 1024.
  * All calls on one GPU share its array, which keeps the last call's contents
  * (nothing in it needs to start at zero): calls that overlap in time on one
  * GPU race on it and must be serialised by the caller (one stream, or

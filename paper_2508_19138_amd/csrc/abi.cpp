@@ -58,7 +58,7 @@ std::string qtx::validate_problem(const qtx_rgf_problem& p) {
   if (p.precision != QTX_FP64 && p.precision != QTX_MIXED) return "unknown precision";
   if (p.n_blocks < 1 || p.block_size < 1 || p.n_energies < 1)
     return "n_blocks, block_size and n_energies must be >= 1";
-  if (p.block_size > 1024) return "block_size above 1024 is not supported";
+  if (p.block_size > kMaxB) return "block_size above 4096 is not supported";
   if (p.flags != 0) return "flags must be 0";
   if (!p.XR.diag) return "XR.diag is required";
   if (p.n_blocks > 1 && (!p.XR.upper || !p.XR.lower))
@@ -474,7 +474,7 @@ qtx_status qtx_rgf_cgemm(qtx_rgf_ctx* c, char opa, char opb, int32_t m, int32_t 
 
 qtx_status qtx_rgf_zinv(qtx_rgf_ctx* c, int32_t b, void* A, void* X, int32_t* info,
                         int32_t batch) {
-  if (!c || b < 1 || b > 1024 || !A || !X || batch < 0 || A == X) return QTX_ERR_INVALID_ARG;
+  if (!c || b < 1 || b > kMaxB || !A || !X || batch < 0 || A == X) return QTX_ERR_INVALID_ARG;
   if (c->busy) return QTX_ERR_BUSY;
   if (batch == 0) return QTX_OK;
   BusyGuard g(c);

@@ -248,9 +248,12 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
       for (int q = 0; q < lo.second->count; ++q) all.push_back(lo.first->id[lo.second->first + q]);
       fl += lo.second->flops;
     }
-    int maxb = 0;
-    for (auto& v : all) maxb = std::max(maxb, v.b);
-    const int R = (maxb + kInvThreads - 1) / kInvThreads;
+    int maxb = 0, maxn = 0;            // largest b, largest b of the one-workgroup panels
+    for (auto& v : all) {
+      maxb = std::max(maxb, v.b);
+      if (v.b <= kTallB) maxn = std::max(maxn, v.b);
+    }
+    const int R = std::max(1, (maxn + kInvThreads - 1) / kInvThreads);
 
     bool first = true;
     auto gather_and_update = [&](int K0, int W, int cfg,
@@ -282,16 +285,26 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
     for (int M0 = 0; M0 < maxb; M0 += kMega) {
       for (int K0 = M0; K0 < std::min(M0 + kMega, maxb); K0 += kSuper) {
         for (int k0 = K0; k0 < std::min(K0 + kSuper, maxb); k0 += kPanel) {
-          std::vector<InvDesc> d;
-          std::vector<int> pre(1, 0);
+          // one-workgroup panels (b <= kTallB) and the tournament path's
+          // three steps for larger matrices, then one update launch for all
+          std::vector<InvDesc> d, dt;
+          std::vector<int> pre(1, 0), p1(1, 0), p2(1, 0), p3(1, 0);
           std::vector<GemmDesc> gd;
           std::vector<int> gpre(1, 0);
-          double by = 0, gby = 0;
+          double by = 0, byt = 0, gby = 0;
           for (const InvDesc& v : all) {
             if (v.b <= k0) continue;
-            d.push_back(v);
-            pre.push_back(pre.back() + v.batch);
-            by += 16.0 * 3.0 * v.b * kPanel * v.batch;
+            if (v.b <= kTallB) {
+              d.push_back(v);
+              pre.push_back(pre.back() + v.batch);
+              by += 16.0 * 3.0 * v.b * kPanel * v.batch;
+            } else {
+              dt.push_back(v);
+              p1.push_back(p1.back() + v.batch * tall_chunks(v.b));
+              p2.push_back(p2.back() + v.batch);
+              p3.push_back(p3.back() + v.batch * ((v.b + kInvThreads - 1) / kInvThreads));
+              byt += 16.0 * 4.0 * v.b * kPanel * v.batch;
+            }
             GemmDesc g;
             if (inv_panel_update(v, k0, &g)) {
               gd.push_back(g);
@@ -299,9 +312,24 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
               gby += 16.0 * 2.0 * g.M * (double)g.N * g.batch;
             }
           }
-          recs_.push_back(LaunchRec{LaunchRec::Panel, 'N', 'N', false, R, k0, put(d), put_prefix(pre),
-                                    (int)d.size(), pre.back(), kClassInv, (first ? fl : 0.0), by});
-          first = false;
+          if (!d.empty()) {
+            recs_.push_back(LaunchRec{LaunchRec::Panel, 'N', 'N', false, R, k0, put(d),
+                                      put_prefix(pre), (int)d.size(), pre.back(), kClassInv,
+                                      (first ? fl : 0.0), by});
+            first = false;
+          }
+          if (!dt.empty()) {
+            const size_t off = put(dt);
+            const LaunchRec::Kind kinds[3] = {LaunchRec::TallSelect, LaunchRec::TallFinal,
+                                              LaunchRec::TallApply};
+            const std::vector<int>* pres[3] = {&p1, &p2, &p3};
+            for (int st = 0; st < 3; ++st) {
+              recs_.push_back(LaunchRec{kinds[st], 'N', 'N', false, 0, k0, off, put_prefix(*pres[st]),
+                                        (int)dt.size(), pres[st]->back(), kClassInv,
+                                        (first ? fl : 0.0), st == 0 ? byt : 0.0});
+              first = false;
+            }
+          }
           if (!gd.empty())
             recs_.push_back(LaunchRec{LaunchRec::Gemm, 'N', 'N', false, kGemmInvUpdate, k0, put(gd),
                                       put_prefix(gpre), (int)gd.size(), gpre.back(), kClassInv, 0.0,
@@ -421,6 +449,9 @@ void Executor::issue(char* base, bool profile) {
     switch (r.kind) {
       case LaunchRec::Gemm: XCHK(launch_gemm(r.cfg, r.fp32, r.opa, r.opb, l, s_)); break;
       case LaunchRec::Panel: XCHK(launch_inv_panel(r.cfg, r.k0, l, s_)); break;
+      case LaunchRec::TallSelect: XCHK(launch_inv_tall(1, r.k0, l, s_)); break;
+      case LaunchRec::TallFinal: XCHK(launch_inv_tall(2, r.k0, l, s_)); break;
+      case LaunchRec::TallApply: XCHK(launch_inv_tall(3, r.k0, l, s_)); break;
       case LaunchRec::Permute: XCHK(launch_inv_permute(l, s_)); break;
       case LaunchRec::Gather: XCHK(launch_inv_super_gather(r.k0, r.cfg, l, s_)); break;
       case LaunchRec::Lin: XCHK(launch_lincomb(l, s_)); break;

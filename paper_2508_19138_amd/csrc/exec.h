@@ -80,7 +80,7 @@ class Tuner {
 
 // One kernel launch of a merged schedule.
 struct LaunchRec {
-  enum Kind : uint8_t { Gemm, Panel, Gather, Permute, Lin, Trans } kind;
+  enum Kind : uint8_t { Gemm, Panel, Gather, Permute, Lin, Trans, TallSelect, TallFinal, TallApply } kind;
   char opa, opb;
   bool fp32;
   int cfg;        // gemm tile config, rows-per-thread R (Panel) or width W (Gather)

@@ -102,6 +102,24 @@ struct InvDesc {
   int b;
   int batch;
 };
+// Largest block size of the inverse.  Above kInvThreads * 4 rows the panel
+// takes the tournament path (zinv.hip): chunks of kTallChunk rows propose
+// pivot rows, at most kTallCand of them.
+constexpr int kMaxB = 4096;
+constexpr int kTallB = 4 * kInvThreads;
+constexpr int kTallChunk = 3 * kInvThreads;
+constexpr int kTallCand = (kMaxB + kTallChunk - 1) / kTallChunk * kPanel;
+__host__ __device__ inline int tall_chunks(int b) { return (b + kTallChunk - 1) / kTallChunk; }
+// The tournament path's records of matrix e, kept in its spanel buffer
+// (which only the gather after a super-panel and the product reading it
+// use): the pivot block's inverse [kPanel][kPanel], then the proposed rows
+// [kTallCand] and each chunk's flags of non-finite columns [chunks].
+__host__ __device__ inline double2* tall_binv(const InvDesc& d, long long e, int b) {
+  return (double2*)d.spanel + e * (long long)b * inv_span(b);
+}
+__host__ __device__ inline int* tall_cand(const InvDesc& d, long long e, int b) {
+  return (int*)(tall_binv(d, e, b) + kPanel * kPanel);
+}
 // Bytes of inverse work buffers per matrix of size b.
 inline size_t inv_work_bytes(int b) {
   return (size_t)b * (2 * kPanel + 2 * inv_span(b)) * 16 + (size_t)b * 8;
@@ -111,6 +129,12 @@ inline size_t inv_work_bytes(int b) {
 // pivot rows are gathered into brow for the columns [k0 & ~(kSuper-1),
 // + kSuper) of the current super-panel.
 hipError_t launch_inv_panel(int R, int k0, const FlatLaunch& l, hipStream_t s);
+// The tournament path's three launches for the panel at k0 of matrices with
+// b > kTallB: step 1 one workgroup per chunk of kTallChunk rows (proposals),
+// step 2 one per matrix (pivot rows, pivot block inverse, status, gathered
+// pivot rows), step 3 one per kInvThreads rows (every row of the panel,
+// Panel'', used flags).
+hipError_t launch_inv_tall(int step, int k0, const FlatLaunch& l, hipStream_t s);
 // After the last panel of the W-column panel (W = kSuper or kMega) starting
 // at K0: spanel = its eliminated columns minus the identity at their pivot
 // rows [b][W], sbrow = its pivot rows outside it (zero inside) [W][b].

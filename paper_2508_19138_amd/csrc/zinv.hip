@@ -22,6 +22,17 @@
 // and its pivot rows outside it are gathered and one rank-kSuper product on
 // the matrix cores updates the whole matrix.  Gathered pivot rows carry
 // zeros in the columns being eliminated, so those pass through unchanged.
+//
+// Matrices above kInvThreads * 4 rows do not fit one workgroup's registers.
+// Their panels pick the pivot rows by a tournament: every chunk of
+// kTallChunk rows eliminates the panel columns on its own rows and proposes
+// the rows it pivoted on; one workgroup eliminates the proposed rows, which
+// fixes the panel's pivot rows p_0..p_15 and leaves on them the inverse of
+// the pivot block B = A[p_k][k0 + j] (Gauss-Jordan on B); every other row r
+// then becomes -A[r][panel] B^{-1}, the value the elimination would leave
+// there.  This is the selection of communication-avoiding LU: it keeps the
+// elimination stable in practice though its worst-case growth bound is
+// weaker than that of partial pivoting over the whole column.
 #include "qtx_internal.h"
 
 namespace qtx {
@@ -148,7 +159,14 @@ __device__ __forceinline__ void publish_row(const double2 (&a)[R][kPanel], unsig
   }
 }
 
-template <int R>
+// MODE 0: one workgroup per matrix factors the panel on all rows (b <= 4 *
+// kInvThreads).  MODE 1: one workgroup per chunk of kTallChunk rows
+// eliminates the panel on its rows and records the rows it pivoted on and
+// which columns met a non-finite candidate.  MODE 2: one workgroup per
+// matrix eliminates the recorded rows (the panel's pivot rows follow), and
+// writes the inverse of the pivot block, the pivot rows, the status and the
+// gathered pivot rows of the super-panel; gj_tall_apply_kernel does the rest.
+template <int R, int MODE>
 __global__ __launch_bounds__(kInvThreads)
 void gj_panel_kernel(FlatLaunch L, int k0) {
   constexpr int NB = kPanel;
@@ -164,10 +182,14 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
   __shared__ double2 pinvS[NB];     // reciprocal pivot of each panel column
   __shared__ int pivs[NB];
 
+  __shared__ int rowmap[kTallCand];  // MODE 2: the recorded rows
   const int di = find_desc(L.prefix, L.nd, blockIdx.x);
   const InvDesc& d = ((const InvDesc*)L.desc)[di];
-  const int e = blockIdx.x - L.prefix[di];
   const int b = d.b;
+  const int local = blockIdx.x - L.prefix[di];
+  const int nch = tall_chunks(b);
+  const int e = MODE == 1 ? local / nch : local;
+  const int ch = MODE == 1 ? local % nch : 0;
   if (k0 >= b) return;                       // this matrix has no such panel
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -180,6 +202,17 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
   const int lo = k0 - k0 % kSuper;                // current super-panel
   const int hi = min(b, lo + kSuper);
   const int code0 = d.code;
+  // the workgroup's rows: local row i is matrix row grow(i), i < nrows
+  int* tc = tall_cand(d, e, b);                    // MODE 1/2 records
+  const int base = ch * kTallChunk;
+  const int nrows = MODE == 0 ? b : MODE == 1 ? min(kTallChunk, b - base) : nch * NB;
+  unsigned tbad = 0;                               // MODE 2: columns flagged by a chunk
+  if (MODE == 2) {
+    for (int i = t; i < kTallCand; i += kInvThreads) rowmap[i] = i < nrows ? tc[i] : -1;
+    for (int j = 0; j < nch; ++j) tbad |= (unsigned)tc[kTallCand + j];
+    __syncthreads();
+  }
+  auto grow = [&](int i) { return MODE == 0 ? i : MODE == 1 ? base + i : rowmap[i]; };
 
   // Panel rows move between HBM and registers through LDS: 16 lanes per
   // row in HBM (256-byte segments), one row per thread in registers.
@@ -194,8 +227,11 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
     const int r = r0 + t;
     pc[q] = -1;
     u[q] = 1;
-    if (r < b) u[q] = (k0 == 0) ? 0 : ue[r];
-    if (r0 < b) {                           // uniform across the workgroup
+    if (r < nrows) {
+      if (MODE == 2) u[q] = grow(r) >= 0 ? 0 : 1;   // recorded rows are unused
+      else u[q] = (k0 == 0) ? 0 : ue[grow(r)];
+    }
+    if (r0 < nrows) {                       // uniform across the workgroup
       // unconditional loads (out-of-range entries read element 0 and are
       // replaced by zero) so that all of them are in flight together
       double2 v[NB];
@@ -203,8 +239,9 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
       for (int i = 0; i < NB; ++i) {
         const int idx = t + i * kInvThreads;
         const int rl = idx / NB, c = idx % NB;
-        const bool ok = (r0 + rl < b) && (c < nbe);
-        v[i] = A[ok ? (long long)(r0 + rl) * b + k0 + c : 0];
+        const int gr = (r0 + rl < nrows) ? grow(r0 + rl) : -1;
+        const bool ok = (gr >= 0) && (c < nbe);
+        v[i] = A[ok ? (long long)gr * b + k0 + c : 0];
         if (!ok) v[i] = make_double2(0.0, 0.0);
       }
 #pragma unroll
@@ -237,6 +274,7 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
   // update of the other columns.
   int first_bad = 0;
   int pv_reg[NB];
+  unsigned hcm = 0, hbm = 0;     // MODE 1: columns with a candidate / a non-finite one
   {
     int bad = 0;
     const unsigned key = col_key<R>(a, u, 0, t, bad);
@@ -265,7 +303,14 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
     // unless every one was non-finite; then row 0 keeps indices in range
     // and the failure is reported through info.
     int p = bk ? pivot_row(bk) : 0;
-    if (p >= b) p = 0;
+    if (p >= nrows) p = 0;
+    // A chunk (MODE 1) whose remaining rows are all zero in this column (or
+    // none is left) skips it: it proposes no row for it and eliminates
+    // nothing, so its proposals stay a basis of its rows' panel entries.
+    const bool skip = MODE == 1 && (bk == 0 || ((bk - 1u) >> 10) == 0);
+    if (MODE == 1 && !skip) hcm |= 1u << c;
+    if (MODE == 1 && anybad) hbm |= 1u << c;
+    if (MODE == 2) anybad |= (tbad >> c) & 1u;
     // what the multipliers and column c + 1 need is read first
     const double2 inv = invS[par][bw];
     // (the winning wave as a scalar, so that the 16 reads share one
@@ -289,11 +334,11 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
     double2 g[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      isp[q] = (t + q * kInvThreads == p);
+      isp[q] = !skip && (t + q * kInvThreads == p);
       u[q] |= isp[q];
       pc[q] = isp[q] ? c : pc[q];
       const double2 m = cmul(a[q][c], inv);
-      g[q] = isp[q] ? make_double2(0.0, 0.0) : m;
+      g[q] = (isp[q] || skip) ? make_double2(0.0, 0.0) : m;
     }
     // ---- column c + 1 first, and the next pivot search
     const bool nxt = c + 1 < nbe;  // uniform across the workgroup
@@ -334,10 +379,21 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
     }
     if (t == 0) pinvS[c] = inv;
   }
+  if (MODE == 1) {
+    // the rows this chunk pivoted on, and its flags of non-finite columns
+    if (t == 0) {
+      int* rec = tc + ch * NB;
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        rec[c] = (c < nbe && ((hcm >> c) & 1u)) ? base + pv_reg[c] : -1;
+      tc[kTallCand + ch] = (int)hbm;
+    }
+    return;
+  }
   if (t == 0) {
 #pragma unroll
     for (int c = 0; c < NB; ++c)
-      if (c < nbe) pivs[c] = pv_reg[c];
+      if (c < nbe) pivs[c] = grow(pv_reg[c]);
   }
   __syncthreads();                 // pivs[], pinvS[] complete
 
@@ -368,10 +424,23 @@ void gj_panel_kernel(FlatLaunch L, int k0) {
     if (!ok) gv[g] = make_double2(0.0, 0.0);
   }
 
+  if (MODE == 2) {
+    // row k of the pivot block's inverse is left on pivot row k (rows past
+    // the panel's width are zero)
+    double2* binv = tall_binv(d, e, b);
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (pc[q] >= 0) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) binv[pc[q] * NB + cc] = a[q][cc];
+      }
+    for (int i = nbe * NB + t; i < NB * NB; i += kInvThreads) binv[i] = make_double2(0.0, 0.0);
+  }
   // ---- write back the panel and Panel'' (panel minus I at the pivots) ----
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int r0 = q * kInvThreads;
+    if (MODE != 0) continue;
     if (r0 >= b) continue;                  // uniform across the workgroup
     if (r0 + t < b) ue[r0 + t] = u[q];
 #pragma unroll
@@ -451,11 +520,98 @@ void gj_super_gather_kernel(FlatLaunch L, int K0, int W) {
   }
 }
 
+// The tournament path's last step for the panel at k0: row r becomes row k
+// of the pivot block's inverse if it is pivot row p_k, else -A[r][panel]
+// times that inverse; Panel'' and the used flags follow.  Rows move through
+// LDS as in the panel kernel (16 lanes per row in HBM).
+__global__ __launch_bounds__(kInvThreads)
+void gj_tall_apply_kernel(FlatLaunch L, int k0) {
+  constexpr int NB = kPanel;
+  __shared__ double2 binvS[NB][NB];
+  __shared__ int pivS[NB];
+  __shared__ double2 stage[kInvThreads][NB + 1];
+  __shared__ int pcS[kInvThreads];
+  const int di = find_desc(L.prefix, L.nd, blockIdx.x);
+  const InvDesc& d = ((const InvDesc*)L.desc)[di];
+  const int b = d.b;
+  const int nblk = (b + kInvThreads - 1) / kInvThreads;
+  const int local = blockIdx.x - L.prefix[di];
+  const int e = local / nblk;
+  const int r0 = (local % nblk) * kInvThreads;
+  if (k0 >= b) return;
+  const int t = threadIdx.x;
+  const int nbe = min(NB, b - k0);
+  double2* A = (double2*)d.S + e * d.sS;
+  const int* pe = d.perm + (long long)e * b;
+  int* ue = d.used + (long long)e * b;
+  double2* pan = (double2*)d.panel + (long long)e * b * NB;
+  const double2* binv = tall_binv(d, e, b);
+  for (int i = t; i < NB * NB; i += kInvThreads) binvS[i / NB][i % NB] = binv[i];
+  if (t < NB) pivS[t] = t < nbe ? pe[k0 + t] : -1;
+  double2 v[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int idx = t + i * kInvThreads;
+    const int rl = idx / NB, c = idx % NB;
+    const bool ok = (r0 + rl < b) && (c < nbe);
+    v[i] = A[ok ? (long long)(r0 + rl) * b + k0 + c : 0];
+    if (!ok) v[i] = make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int idx = t + i * kInvThreads;
+    stage[idx / NB][idx % NB] = v[i];
+  }
+  __syncthreads();
+  double2 a[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) a[c] = stage[t][c];
+  const int r = r0 + t;
+  int k = -1;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) k = (pivS[j] == r) ? j : k;
+  double2 y[NB];
+  if (k >= 0) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) y[j] = binvS[k][j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) y[j] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const double2 m = binvS[i][j];
+        y[j].x = fma(-a[i].x, m.x, fma(a[i].y, m.y, y[j].x));
+        y[j].y = fma(-a[i].x, m.y, fma(-a[i].y, m.x, y[j].y));
+      }
+    }
+  }
+  if (r < b) ue[r] = ((k0 == 0) ? 0 : ue[r]) | (k >= 0 ? 1 : 0);
+  __syncthreads();                  // stage is reused
+#pragma unroll
+  for (int c = 0; c < NB; ++c) stage[t][c] = y[c];
+  pcS[t] = k;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int idx = t + i * kInvThreads;
+    const int rl = idx / NB, c = idx % NB;
+    const int rr = r0 + rl;
+    if (rr < b) {
+      double2 w = stage[rl][c];
+      if (c < nbe) A[(long long)rr * b + k0 + c] = w;
+      if (pcS[rl] == c) w.x -= 1.0;
+      pan[(long long)rr * NB + c] = w;
+    }
+  }
+}
+
 // X[k][c] = Y[p_k][pinv(c)] with pinv(p_j) = j; kPermRows rows per workgroup.
 __global__ __launch_bounds__(256)
 void gj_permute_kernel(FlatLaunch L) {
-  __shared__ int pinv[1024];
-  __shared__ int pk[1024];
+  __shared__ int pinv[kMaxB];
+  __shared__ int pk[kMaxB];
   const int di = find_desc(L.prefix, L.nd, blockIdx.x);
   const InvDesc& d = ((const InvDesc*)L.desc)[di];
   const int b = d.b;
@@ -489,10 +645,23 @@ void gj_permute_kernel(FlatLaunch L) {
 hipError_t launch_inv_panel(int R, int k0, const FlatLaunch& l, hipStream_t s) {
   if (l.total <= 0) return hipSuccess;
   switch (R) {
-    case 1: hipLaunchKernelGGL(gj_panel_kernel<1>, dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
-    case 2: hipLaunchKernelGGL(gj_panel_kernel<2>, dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
-    case 3: hipLaunchKernelGGL(gj_panel_kernel<3>, dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
-    case 4: hipLaunchKernelGGL(gj_panel_kernel<4>, dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
+    case 1: hipLaunchKernelGGL((gj_panel_kernel<1, 0>), dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
+    case 2: hipLaunchKernelGGL((gj_panel_kernel<2, 0>), dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
+    case 3: hipLaunchKernelGGL((gj_panel_kernel<3, 0>), dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
+    case 4: hipLaunchKernelGGL((gj_panel_kernel<4, 0>), dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_inv_tall(int step, int k0, const FlatLaunch& l, hipStream_t s) {
+  if (l.total <= 0) return hipSuccess;
+  static_assert(kTallChunk == 3 * kInvThreads, "chunk rows = 3 per thread");
+  static_assert(kTallCand <= kInvThreads, "one recorded row per thread");
+  switch (step) {
+    case 1: hipLaunchKernelGGL((gj_panel_kernel<3, 1>), dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
+    case 2: hipLaunchKernelGGL((gj_panel_kernel<1, 2>), dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
+    case 3: hipLaunchKernelGGL(gj_tall_apply_kernel, dim3(l.total), dim3(kInvThreads), 0, s, l, k0); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -106,7 +106,8 @@ def test_panel_kernel_rows_stay_in_registers(tmp_path):
     """The inverse's panel kernel holds R rows of the panel per thread in
     registers; compiled with the library's options (hipcc cross-compiles
     for gfx950 without a device), the instances for R = 1..3 must not place
-    that array in scratch memory."""
+    that array in scratch memory (nor the tall path's chunk and final
+    instances)."""
     from paper_2508_19138_amd import build as B
     src = os.path.join(B.CSRC, "zinv.hip")
     out = str(tmp_path / "zinv.s")
@@ -115,12 +116,13 @@ def test_panel_kernel_rows_stay_in_registers(tmp_path):
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
     meta = open(out).read()
-    for R in (1, 2, 3):
-        name = "_ZN3qtx12_GLOBAL__N_115gj_panel_kernelILi%dEEEvNS_10FlatLaunchEi" % R
+    # (R, mode): whole-matrix panels, and the tall path's chunk and final steps
+    for R, mode in ((1, 0), (2, 0), (3, 0), (3, 1), (1, 2)):
+        name = "_ZN3qtx12_GLOBAL__N_115gj_panel_kernelILi%dELi%dEEEvNS_10FlatLaunchEi" % (R, mode)
         # the kernel's entry in the code-object metadata
         i = meta.index(".name:           " + name)
         lo = meta.rindex("\n  - .", 0, i)
         hi = meta.find("\n  - .", i)
         block = meta[lo:hi if hi >= 0 else len(meta)]
         m = re.search(r"\.private_segment_fixed_size:\s+(\d+)", block)
-        assert m and int(m.group(1)) == 0, (R, m and m.group(1))
+        assert m and int(m.group(1)) == 0, (R, mode, m and m.group(1))
