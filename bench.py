@@ -93,6 +93,8 @@ def parse():
                     help="after the run, copy a 1 GiB device buffer three times "
                          "(reference kernel for HBM byte counters)")
     ap.add_argument("--solves", type=int, default=512, help="uneven: solve count")
+    ap.add_argument("--only-b", type=int, default=0,
+                    help="uneven: keep only the solves of this block size (0: all)")
     ap.add_argument("--skip-loop", action="store_true",
                     help="uneven: time the merged batches only")
     ap.add_argument("--repeat", type=int, default=1,
@@ -511,6 +513,10 @@ def run_uneven(args):
     from paper_2508_19138_amd import qtx_rgf as Q
     from paper_2508_19138_amd import synth
     specs = synth.uneven_specs(args.seed, args.solves)
+    if args.only_b:
+        specs = [sp for sp in specs if sp["b"] == args.only_b]
+        if not specs:
+            raise SystemExit("no solve of block size %d in the workload" % args.only_b)
     cap = int(args.wave_gib * 2 ** 30)
     waves = _waves(specs, cap)
     flops = {id(sp): _spec_flops(Q, sp) for sp in specs}
@@ -580,9 +586,11 @@ def run_uneven(args):
         "value": round(n_sol / t_merged, 3), "unit": "energy-points/s", "n_gpus": 1,
         "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "batched uneven solves: %d independent single-energy complex128 "
-                               "RGF solves, b from {64,128,256,384,512,768}, n from 8..128, "
+                               "RGF solves, b from %s, n from 8..128, "
                                "half G-type half W-type (W with W^< W^> outputs), merged "
-                               "batches in %d memory waves" % (n_sol, len(waves)),
+                               "batches in %d memory waves"
+                               % (n_sol, "{%d}" % args.only_b if args.only_b
+                                  else "{64,128,256,384,512,768}", len(waves)),
                    "solves": n_sol, "waves": len(waves), "seed": args.seed,
                    "timed_solve_of_each_wave": args.repeat},
         "merged": {"s": round(t_merged, 3), "energy_points_per_s": round(n_sol / t_merged, 3),

@@ -25,6 +25,12 @@ using namespace qtx;
 namespace {
 
 constexpr int kSplitMinEnergies = 64;          // energies before a problem is split
+// Lanes of at most this many energies (independent single-energy solves)
+// are spread over the pool's streams within their class: a class of many
+// such lanes is a chain of latency-bound launches (one matrix per
+// workgroup in the inverse's panels), and several shorter chains on
+// different streams overlap one another's gaps.
+constexpr int kSpreadMaxEnergies = 4;
 
 }  // namespace
 
@@ -172,6 +178,7 @@ qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
   Regions reg(std::max(cap, largest + 4096));
   Pool& P = *c->pool;
   P.fork();
+  std::map<uint64_t, int> spread;     // lanes admitted so far per spread class
   std::vector<std::unique_ptr<Lane>> active;
   std::vector<std::pair<Lane*, int>> fin;
   size_t next = 0;
@@ -190,7 +197,11 @@ qtx_status solve(qtx_rgf_ctx* c, qtx_rgf_problem* probs, int np) {
       // lanes of one class (operation structure and block size) start
       // together and share one stream in lockstep; classes spread over the
       // pool's streams and overlap one another's latency-bound inverses
-      const uint64_t cls = lane_class(plans[pd.prob], p, c->batch_size_key) * 8 + pd.part;
+      const uint64_t base = lane_class(plans[pd.prob], p, c->batch_size_key);
+      int part = pd.part;
+      if (pd.ec <= kSpreadMaxEnergies && P.size() > 1 && pd.part == 0)
+        part = spread[base]++ % std::min(P.size(), 8);
+      const uint64_t cls = base * 8 + part;
       const int xi = P.place(cls);
       build_lane(*L, p, plans[pd.prob], c->ws + off, pd.e0, pd.ec, d_E + e_off[pd.prob],
                  d_info + e_off[pd.prob], c->tuner, P.stream(xi));
