@@ -448,9 +448,10 @@ qtx_status qtx_rgf_obc_lesser_greater(qtx_rgf_ctx* ctx, int32_t b, int32_t batch
  *                     double[batch][n-1] or NULL (then XL_lower and H_upper
  *                     may be NULL).  XG_diag may be NULL if dos is.
  * Integration over energy is left to the caller.  1 <= b <= 1024, n >= 1,
- * batch >= 0; returns when written.  Scratch of (n-1) b*b complex128 from
- * the context's workspace.  Errors: QTX_ERR_INVALID_ARG, QTX_ERR_NOMEM, QTX_ERR_BUSY,
- * QTX_ERR_HIP. */
+ * batch >= 0; returns when written.  Scratch of (n-1) b*b complex128 (the
+ * couplings' adjoints) plus batch (n-1) ceil(b*b / 2048) doubles (the
+ * current's partial sums) from the context's workspace.  Errors:
+ * QTX_ERR_INVALID_ARG, QTX_ERR_NOMEM, QTX_ERR_BUSY, QTX_ERR_HIP. */
 /* The screened interaction's lesser/greater surface function (Sec.
  * "Lesser/Greater OBC"): the solution w of Eq. (lyapunov),
  *     w = q - a w a^dagger,

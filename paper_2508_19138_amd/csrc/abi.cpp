@@ -852,9 +852,13 @@ qtx_status qtx_rgf_observables(qtx_rgf_ctx* c, int32_t n_blocks, int32_t b, int3
     HIPCHK(c, hipSetDevice(c->device));
     const long long bb = (long long)b * b;
     const hipStream_t st = c->pool->exe(0).stream();
+    double* part = nullptr;
     if (want_cur) {
-      ensure(c, &c->ws, &c->ws_bytes, (size_t)(n_blocks - 1) * bb * 16);   // grow-only
+      // the couplings' adjoints, then the current's partial sums
+      const size_t hd_bytes = ((size_t)(n_blocks - 1) * bb * 16 + 255) & ~(size_t)255;
+      ensure(c, &c->ws, &c->ws_bytes, hd_bytes + observables_part_bytes(n_blocks, b, batch));
       hd = c->ws;
+      part = (double*)(c->ws + hd_bytes);
       Lane L;
       TransDesc t{};
       t.C = nullptr;
@@ -876,7 +880,7 @@ qtx_status qtx_rgf_observables(qtx_rgf_ctx* c, int32_t n_blocks, int32_t b, int3
     }
     HIPCHK(c, launch_observables(XL_diag, XG_diag, want_cur ? XL_lower : nullptr, hd, dos,
                                  density, want_cur ? current : nullptr, n_blocks, b, batch,
-                                 st));
+                                 part, st));
     c->pool->exe(0).sync_and_collect(c->stats);
   } catch (const Fail& fl) {
     if (c->err.empty()) c->err = fl.what;

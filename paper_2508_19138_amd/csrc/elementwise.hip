@@ -250,14 +250,74 @@ hipError_t launch_norms(const NormTerms& T, long long bb, int batch, int mode, d
   return hipGetLastError();
 }
 
+// The current through interface i, 2 Re Tr(H_{i,i+1} G^<_{i+1,i}) =
+// 2 sum_q Re(G[q] conj(Hd[q])) with Hd = H_{i,i+1}^dagger (both blocks read
+// contiguously), in partial sums: workgroup (i, tile) keeps its tile of Hd
+// in registers and streams the same tile of G^<_{i+1,i} of every energy,
+// kObsEnergies energies per pass, so each coupling block is read once per
+// call rather than once per energy.  part[(e (n-1) + i) tiles + tile].
+constexpr int kObsVec = 8;                      // elements per thread and tile
+constexpr int kObsTile = 256 * kObsVec;         // elements per workgroup
+constexpr int kObsEnergies = 8;                 // energies per pass
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) x += __shfl_xor(x, m, 64);
+  return x;
+}
+
+__global__ __launch_bounds__(256)
+void current_partial_kernel(const double2* __restrict__ gl_l, const double2* __restrict__ hd,
+                            double* __restrict__ part, int n, int b, int batch, int tiles) {
+  const int i = blockIdx.x / tiles, tl = blockIdx.x % tiles;
+  const long long bb = (long long)b * b;
+  const long long q0 = (long long)tl * kObsTile;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  double2 h[kObsVec];
+#pragma unroll
+  for (int v = 0; v < kObsVec; ++v) {
+    const long long q = q0 + t + 256 * v;
+    h[v] = q < bb ? hd[(long long)i * bb + q] : make_double2(0.0, 0.0);
+  }
+  __shared__ double red[kObsEnergies][4];
+  for (int e0 = 0; e0 < batch; e0 += kObsEnergies) {
+    double sum[kObsEnergies];
+#pragma unroll
+    for (int k = 0; k < kObsEnergies; ++k) {
+      sum[k] = 0.0;
+      const int e = e0 + k;
+      if (e < batch) {                          // uniform across the workgroup
+        const double2* G = gl_l + ((long long)e * (n - 1) + i) * bb;
+#pragma unroll
+        for (int v = 0; v < kObsVec; ++v) {
+          const long long q = q0 + t + 256 * v;
+          if (q < bb) {
+            const double2 g = G[q];
+            sum[k] = fma(g.x, h[v].x, fma(g.y, h[v].y, sum[k]));
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kObsEnergies; ++k) {
+      const double w = wave_sum(sum[k]);
+      if (lane == 0) red[k][wave] = w;
+    }
+    __syncthreads();
+    if (t < kObsEnergies && e0 + t < batch)
+      part[((long long)(e0 + t) * (n - 1) + i) * tiles + tl] =
+          (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]);
+    __syncthreads();
+  }
+}
+
 // Observables per energy e: workgroups k < n take block k's traces
 // (density of states from i(G^> - G^<), density from -i G^<, diagonal
 // elements only), workgroups k >= n the current through interface
-// i = k - n, 2 Re Tr(H_{i,i+1} G^<_{i+1,i}) = 2 sum_q Re(G[q] conj(Hd[q]))
-// with Hd = H_{i,i+1}^dagger, so both blocks are read contiguously.
+// i = k - n from its partial sums.
 __global__ __launch_bounds__(256)
 void observables_kernel(const double2* __restrict__ gl_d, const double2* __restrict__ gg_d,
-                        const double2* __restrict__ gl_l, const double2* __restrict__ hd,
+                        const double* __restrict__ part, int tiles,
                         double* __restrict__ dos, double* __restrict__ dens,
                         double* __restrict__ cur, int n, int b) {
   const int per = 2 * n - 1;
@@ -276,14 +336,10 @@ void observables_kernel(const double2* __restrict__ gl_d, const double2* __restr
       s0 += l.y - g.y;          // Re(i (g - l))
       s1 += l.y;                // Re(-i l)
     }
-  } else if (cur) {             // gl_l and hd are null when no current is asked for
+  } else if (cur) {             // part is null when no current is asked for
     const int i = k - n;
-    const double2* G = gl_l + (e * (n - 1) + i) * bb;
-    const double2* H = hd + (long long)i * bb;
-    for (long long q = t; q < bb; q += 256) {
-      const double2 g = G[q], h = H[q];
-      s0 += g.x * h.x + g.y * h.y;
-    }
+    const double* P = part + (e * (n - 1) + i) * tiles;
+    for (int q = t; q < tiles; q += 256) s0 += P[q];
   }
   __shared__ double r0[256], r1[256];
   r0[t] = s0;
@@ -309,14 +365,26 @@ void observables_kernel(const double2* __restrict__ gl_d, const double2* __restr
 
 }  // namespace
 
+size_t observables_part_bytes(int n, int b, int batch) {
+  if (n < 2) return 0;
+  const long long tiles = ((long long)b * b + kObsTile - 1) / kObsTile;
+  return (size_t)batch * (n - 1) * tiles * sizeof(double);
+}
+
 hipError_t launch_observables(const void* gl_d, const void* gg_d, const void* gl_l,
                               const void* hd, double* dos, double* dens, double* cur, int n,
-                              int b, int batch, hipStream_t s) {
+                              int b, int batch, double* part, hipStream_t s) {
   if (batch <= 0 || n <= 0) return hipSuccess;
+  const int tiles = (int)(((long long)b * b + kObsTile - 1) / kObsTile);
+  if (cur && n > 1) {
+    hipLaunchKernelGGL(current_partial_kernel, dim3((unsigned)((n - 1) * tiles)), dim3(256), 0,
+                       s, (const double2*)gl_l, (const double2*)hd, part, n, b, batch, tiles);
+  }
   const long long grid = (long long)batch * (2 * n - 1);
   hipLaunchKernelGGL(observables_kernel, dim3((unsigned)grid), dim3(256), 0, s,
-                     (const double2*)gl_d, (const double2*)gg_d, (const double2*)gl_l,
-                     (const double2*)hd, dos, dens, cur, n, b);
+                     (const double2*)gl_d, (const double2*)gg_d,
+                     (cur && n > 1) ? (const double*)part : nullptr, tiles, dos, dens,
+                     (cur && n > 1) ? cur : nullptr, n, b);
   return hipGetLastError();
 }
 

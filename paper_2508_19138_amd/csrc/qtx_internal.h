@@ -259,10 +259,12 @@ hipError_t launch_lincomb(const FlatLaunch& l, hipStream_t s);
 hipError_t launch_transcomb(const FlatLaunch& l, hipStream_t s);
 // Per energy: dos[n], density[n] from the diagonal blocks of G^< / G^>,
 // current[n-1] from the lower blocks of G^< and Hd = H_{i,i+1}^dagger
-// ([n-1][b][b], shared by all energies).  Null outputs are skipped.
+// ([n-1][b][b], shared by all energies) through partial sums in `part`
+// (observables_part_bytes).  Null outputs are skipped.
+size_t observables_part_bytes(int n, int b, int batch);
 hipError_t launch_observables(const void* gl_d, const void* gg_d, const void* gl_l,
                               const void* hd, double* dos, double* dens, double* cur, int n,
-                              int b, int batch, hipStream_t s);
+                              int b, int batch, double* part, hipStream_t s);
 // L_e = -f_e (S_e - S_e^dagger), G_e = (1 - f_e)(S_e - S_e^dagger) with
 // occ[2e] = f_e, occ[2e + 1] = 1 - f_e (device); S_e at stride sS (0 = shared),
 // L and G contiguous, either may be null.
