@@ -105,6 +105,16 @@ def parse():
                     help="uneven: device memory for the inputs/outputs of one wave")
     ap.add_argument("--requests", type=int, default=1000, help="serve: requests per rate")
     ap.add_argument("--rates", default="50,100,200,400", help="serve: arrivals per second")
+    ap.add_argument("--serve-sizes", default="scaled", choices=["scaled", "matched", "literal"],
+                    help="serve: request sizes: scaled (n 8..64, b in {128,192,256}, 1..16 "
+                         "energies), matched (n 8..32, b in {128,256}, 16..64 energies) or "
+                         "literal (n 8..64, b in {128,256,...,768}, 16..256 energies)")
+    ap.add_argument("--serve-cap-s", type=float, default=0.0,
+                    help="serve: stop each replay this many seconds after its first arrival "
+                         "(0: serve every request)")
+    ap.add_argument("--chunk-gib", type=float, default=16.0,
+                    help="serve: the client splits a request into energy chunks of at most "
+                         "this many GiB of self-energies and outputs, one problem each")
     ap.add_argument("--partitions", default="2,4,8,16",
                     help="nested: partition counts to time")
     ap.add_argument("--nested-blocks", type=int, default=128, help="nested: block count")
@@ -614,11 +624,30 @@ def _serve_trace(args, rate):
     gaps = rng.exponential(1.0 / rate, size=R)
     arr = np.cumsum(gaps) - gaps[0]
     reqs = []
+    n_lo, n_hi, bs, e_lo, e_hi = _SERVE_SIZES[args.serve_sizes]
     for i in range(R):
-        reqs.append({"n": int(rng.integers(8, 65)), "b": int(rng.choice([128, 192, 256])),
-                     "ne": int(rng.integers(1, 17)), "t": float(arr[i]),
+        reqs.append({"n": int(rng.integers(n_lo, n_hi + 1)), "b": int(rng.choice(bs)),
+                     "ne": int(rng.integers(e_lo, e_hi + 1)), "t": float(arr[i]),
                      "e0": float(rng.uniform(-2.0, 1.0))})
     return reqs
+
+
+# request sizes: (n min, n max, block sizes, energies min, energies max)
+_SERVE_SIZES = {
+    "scaled": (8, 64, (128, 192, 256), 1, 16),
+    "matched": (8, 32, (128, 256), 16, 64),
+    "literal": (8, 64, (128, 256, 384, 512, 640, 768), 16, 256),
+}
+
+
+def _chunks(r, i, cap_elems):
+    """The client's split of request i into energy chunks (one problem each)
+    of at most cap_elems complex128 elements of self-energies and outputs."""
+    per_e = _req_elems(dict(r, ne=1))
+    k = max(1, min(r["ne"], cap_elems // per_e))
+    E = np.linspace(r["e0"], r["e0"] + 1.0, r["ne"])
+    return [{"req": i, "n": r["n"], "b": r["b"], "ne": len(E[j:j + k]), "E": E[j:j + k]}
+            for j in range(0, r["ne"], k)]
 
 
 class _Arena:
@@ -674,14 +703,15 @@ class _ServeInputs:
     per-request self-energies and outputs are views of a region of the
     client's arena, filled when the client admits the request."""
 
-    def __init__(self, seed, arena):
+    def __init__(self, seed, arena, sizes="scaled"):
         import torch
         self.arena = arena
         self.H = {}
-        for b in (128, 192, 256):
+        n_hi, bs = _SERVE_SIZES[sizes][1], _SERVE_SIZES[sizes][2]
+        for b in bs:
             gen = torch.Generator(device="cuda:0")
             gen.manual_seed(seed + b)
-            self.H[b] = _herm_bt_dev(gen, 64, b)
+            self.H[b] = _herm_bt_dev(gen, n_hi, b)
 
     def make(self, r):
         """The request's problem, or None while the arena has no room."""
@@ -701,7 +731,7 @@ class _ServeInputs:
             pos[0] += ne * k * b * b
             return t
 
-        E = np.ascontiguousarray(np.linspace(r["e0"], r["e0"] + 1.0, ne))
+        E = np.ascontiguousarray(r["E"] if "E" in r else np.linspace(r["e0"], r["e0"] + 1.0, ne))
         sig = []
         for scal in synth.g_sigma_scalars(E, n):
             t = take(n)
@@ -722,74 +752,108 @@ class _ServeInputs:
 
 def _lat_summary(lat, n_e_tot, t_span):
     lat = np.asarray(lat)
-    return {"energy_points_per_s": round(n_e_tot / t_span, 2),
-            "requests_per_s": round(len(lat) / t_span, 2),
-            "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
-            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
-            "mean_latency_s": round(float(lat.mean()), 4), "span_s": round(t_span, 3)}
+    out = {"energy_points_per_s": round(n_e_tot / t_span, 2),
+           "requests_per_s": round(len(lat) / t_span, 2), "span_s": round(t_span, 3)}
+    if len(lat):
+        out.update({"p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                    "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+                    "mean_latency_s": round(float(lat.mean()), 4)})
+    return out
 
 
-def _serve_run(ctx, inputs, reqs, served):
-    """Replay the arrival trace; returns (latencies, span).  served: submit
-    to the request loop, admitting requests in arrival order while the
-    client's arena has room; otherwise solve each request alone, in arrival
-    order, as soon as the previous one is done."""
+def _serve_run(ctx, inputs, reqs, served, cap_elems, cap_s=0.0):
+    """Replay the arrival trace.  A request becomes its energy chunks when
+    it arrives (the client's split, one problem each) and completes with its
+    last chunk.  served: chunks are submitted to the request loop in arrival
+    order while the client's arena has room; otherwise each chunk is solved
+    alone, in arrival order, as soon as the previous one is done.  With
+    cap_s > 0 the replay stops cap_s seconds after the first arrival (work
+    then in flight is drained and not counted).  Returns the latencies of
+    the completed requests, the span, diagnostics, and the energy points,
+    flops and arrived-but-unfinished requests of the span."""
     import torch
+    from paper_2508_19138_amd import qtx_rgf as Q
     R = len(reqs)
     lat = [None] * R
+    left = [0] * R
     diag = {"client_wait": [], "lib_queue": [], "lib_latency": []}
-    queue, nxt, done = [], 0, 0
+    queue, nxt = [], 0
+    st = {"req": 0, "e": 0, "flops": 0.0, "last": 0.0}
     live = {}
     t0 = time.perf_counter()
-    last = t0
-    while done < R:
+    st["last"] = t0
+
+    def finish(ch, tn):
+        i = ch["req"]
+        left[i] -= 1
+        st["e"] += ch["ne"]
+        st["flops"] += ch["ne"] * Q.flops_per_energy(Q.QTX_KIND_G, ch["n"], ch["b"], 2, False)
+        st["last"] = tn
+        if left[i] == 0:
+            lat[i] = (tn - t0) - reqs[i]["t"]
+            st["req"] += 1
+            if st["req"] % 1000 == 0:
+                print("  %s %d/%d" % ("served" if served else "per-solve loop", st["req"], R),
+                      file=sys.stderr, flush=True)
+
+    def in_cap(tn):
+        return not cap_s or tn - t0 <= cap_s
+
+    while st["req"] < R:
         now = time.perf_counter() - t0
+        if cap_s and now >= cap_s:
+            break
         while nxt < R and reqs[nxt]["t"] <= now:
-            queue.append(nxt)
+            chs = _chunks(reqs[nxt], nxt, cap_elems)
+            left[nxt] = len(chs)
+            queue.extend(chs)
             nxt += 1
         if served:
             while queue:
-                k = inputs.make(reqs[queue[0]])
+                k = inputs.make(queue[0])
                 if k is None:
-                    assert live, "request larger than the client arena"
+                    assert live, "request chunk larger than the client arena"
                     break
-                i = queue.pop(0)
+                ch = queue.pop(0)
                 torch.cuda.current_stream().synchronize()     # inputs written
-                diag["client_wait"].append(time.perf_counter() - t0 - reqs[i]["t"])
-                live[ctx.submit(k["prob"])] = (i, k)
-            wait = 1 if (nxt < R or queue) else 50
+                diag["client_wait"].append(time.perf_counter() - t0 - reqs[ch["req"]]["t"])
+                live[ctx.submit(k["prob"])] = (ch, k)
+            wait = 1 if (cap_s or nxt < R or queue) else 50
             cs, _ = ctx.poll(cap=64, wait_ms=wait)
             tn = time.perf_counter()
             for c in cs:
-                i, k = live.pop(c["ticket"])
+                ch, k = live.pop(c["ticket"])
                 assert c["status"] == 0, c
-                lat[i] = (tn - t0) - reqs[i]["t"]
                 diag["lib_queue"].append(c["queue_s"])
                 diag["lib_latency"].append(c["latency_s"])
                 inputs.release(k)
-                done += 1
-                last = tn
-                if done % 1000 == 0:
-                    print("  served %d/%d" % (done, R), file=sys.stderr, flush=True)
+                if in_cap(tn):
+                    finish(ch, tn)
         else:
             if not queue:
                 dt = reqs[nxt]["t"] - (time.perf_counter() - t0)
+                if cap_s:
+                    dt = min(dt, cap_s - (time.perf_counter() - t0))
                 if dt > 0:
                     time.sleep(dt)
                 continue
-            i = queue.pop(0)
-            k = inputs.make(reqs[i])
+            ch = queue.pop(0)
+            k = inputs.make(ch)
             torch.cuda.current_stream().synchronize()         # inputs written
             ctx.solve_batch([k["prob"]])
             assert k["prob"].status == 0
             tn = time.perf_counter()
-            lat[i] = (tn - t0) - reqs[i]["t"]
             inputs.release(k)
-            done += 1
-            last = tn
-            if done % 1000 == 0:
-                print("  per-solve loop %d/%d" % (done, R), file=sys.stderr, flush=True)
-    return lat, last - t0, diag
+            if in_cap(tn):
+                finish(ch, tn)
+    while live:                                               # drain, not counted
+        cs, _ = ctx.poll(cap=64, wait_ms=50)
+        for c in cs:
+            ch, k = live.pop(c["ticket"])
+            inputs.release(k)
+    span = cap_s if cap_s else st["last"] - t0
+    done = [x for x in lat if x is not None]
+    return done, span, diag, st["e"], st["flops"], nxt - st["req"]
 
 
 def run_serve(args):
@@ -797,12 +861,13 @@ def run_serve(args):
     from paper_2508_19138_amd import qtx_rgf as Q
     rates = [float(x) for x in args.rates.split(",") if x]
     ws = int(args.ws_gib * 2 ** 30)
-    inputs = _ServeInputs(args.seed, _Arena(args.pool_gib))
+    inputs = _ServeInputs(args.seed, _Arena(args.pool_gib), args.serve_sizes)
+    cap_elems = int(args.chunk_gib * 2 ** 30) // 16
     results = []
     ctx_s = Q.Context(0, budget_bytes=ws)
     ctx_l = Q.Context(0, budget_bytes=ws)
     # warm-up (tile tuning, workspace, request-loop start): untimed
-    warm = [{"n": 8, "b": b, "ne": 2, "t": 0.0, "e0": -0.5} for b in (128, 192, 256)]
+    warm = [{"n": 8, "b": b, "ne": 2, "t": 0.0, "e0": -0.5} for b in _SERVE_SIZES[args.serve_sizes][2]]
     for r in warm:
         k = inputs.make(r)
         torch.cuda.synchronize()
@@ -821,8 +886,13 @@ def run_serve(args):
         row = {"rate_per_s": rate, "requests": len(reqs), "energy_points": n_e_tot,
                "mean_request_tflop": round(req_flops / 1e12, 4)}
         for name, ctx, served in (("served", ctx_s, True), ("per_solve_loop", ctx_l, False)):
-            lat, span, diag = _serve_run(ctx, inputs, reqs, served)
-            row[name] = _lat_summary(lat, n_e_tot, span)
+            lat, span, diag, e_done, fl_done, unfinished = _serve_run(
+                ctx, inputs, reqs, served, cap_elems, args.serve_cap_s)
+            row[name] = _lat_summary(lat, e_done, span)
+            row[name]["tflops"] = round(fl_done / span / 1e12, 3)
+            if args.serve_cap_s:
+                row[name]["requests_completed"] = len(lat)
+                row[name]["requests_arrived_not_completed"] = unfinished
             if served:
                 # where the time goes: arrival -> submit in the client (input
                 # set-up, memory admission), submit -> first lane admitted and
@@ -833,9 +903,7 @@ def run_serve(args):
             print("rate %g %s: %s" % (rate, name, row[name]), file=sys.stderr, flush=True)
             torch.cuda.synchronize()
         row["throughput_ratio_served_vs_loop"] = round(
-            row["served"]["energy_points_per_s"] / row["per_solve_loop"]["energy_points_per_s"], 3)
-        row["served"]["tflops"] = round(
-            row["requests"] * req_flops / row["served"]["span_s"] / 1e12, 3)
+            row["served"]["energy_points_per_s"] / max(row["per_solve_loop"]["energy_points_per_s"], 1e-9), 3)
         results.append(row)
     ctx_s.close()
     ctx_l.close()
@@ -852,12 +920,21 @@ def run_serve(args):
         "value": top["served"]["energy_points_per_s"], "unit": "energy-points/s",
         "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "serving stream: Poisson arrivals, %d G-type requests per rate, "
-                               "each n in 8..64 blocks of b in {128,192,256}, 1..16 energies "
-                               "in a window of width 1 in [-2,2]; client admits requests in "
-                               "arrival order into a %.0f GiB device arena allocated up front; "
-                               "latency = arrival to observed completion" % (args.requests, args.pool_gib),
-                   "rates_per_s": rates, "seed": args.seed},
+        "config": {"workload": "serving stream (%s sizes): Poisson arrivals, %d G-type requests "
+                               "per rate, each n in %d..%d blocks of b in {%s}, %d..%d energies "
+                               "in a window of width 1 in [-2,2], split by the client into energy "
+                               "chunks of at most %.0f GiB; chunks admitted in arrival order into "
+                               "a %.0f GiB device arena allocated up front; latency = arrival to "
+                               "observed completion of the last chunk%s"
+                               % ((args.serve_sizes, args.requests) + _SERVE_SIZES[args.serve_sizes][:2]
+                                  + (",".join(str(x) for x in _SERVE_SIZES[args.serve_sizes][2]),)
+                                  + _SERVE_SIZES[args.serve_sizes][3:]
+                                  + (args.chunk_gib, args.pool_gib,
+                                     "; each replay stopped %.0f s after its first arrival "
+                                     "(work then in flight not counted)" % args.serve_cap_s
+                                     if args.serve_cap_s else "")),
+                   "rates_per_s": rates, "seed": args.seed, "sizes": args.serve_sizes,
+                   "time_cap_s": args.serve_cap_s or None},
         "rates": results,
     }
     print(json.dumps(out), flush=True)
