@@ -20,6 +20,9 @@ paper (arXiv 2508.19138, "QuaTrEx"):
                  continuants (independent pin for block size 1).
 * ``observables`` - local density of states, charge density and current
                  from the selected blocks (Sec. "Observables").
+* ``convolution`` - the element-wise energy convolution of two descriptors
+                 that forms the scattering terms (Sec. "Energy
+                 Convolutions", Eq. interaction).
 * ``nested``   - nested-dissection selected inversion (the partitioned
                  solver of Sec. 4.4): per-partition elimination, the reduced
                  system on the separators, per-partition recovery.
@@ -41,6 +44,7 @@ from .flops import rgf_flops, w_assembly_flops
 from .obc import (obc_fixed_point, obc_sancho_rubio, obc_sancho_rubio_steps,
                   obc_lesser_greater, obc_lyapunov_fixed_point, obc_lyapunov_doubling)
 from .observables import observables
+from .convolution import energy_convolution
 
 __all__ = [
     "rgf_selected", "dense_from_bt", "dense_selected",
@@ -48,5 +52,5 @@ __all__ = [
     "chain_lead_self_energy", "tridiag_inverse_selected", "rgf_flops",
     "w_assembly_flops", "obc_fixed_point", "obc_sancho_rubio",
     "obc_sancho_rubio_steps", "obc_lesser_greater", "observables",
-    "obc_lyapunov_fixed_point", "obc_lyapunov_doubling",
+    "obc_lyapunov_fixed_point", "obc_lyapunov_doubling", "energy_convolution",
 ]

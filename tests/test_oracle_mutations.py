@@ -156,6 +156,39 @@ def _check_nested_blocks(m):
     return worst
 
 
+def _check_convolution(m):
+    """Worst deviation of the energy convolution from its pins: the
+    geometric closed form (scaled, shifted window), a shifted delta through
+    the reversed X1, and numpy's convolution."""
+    rng = np.random.default_rng(4)
+    a = 0.6 * np.exp(1j * rng.uniform(0, 2 * np.pi, 3)) + 0.2
+    c = 0.9 * np.exp(1j * rng.uniform(0, 2 * np.pi, 3)) - 0.1
+    n1, n2, n_out, shift, s = 9, 7, 10, 3, 0.4 + 0.9j
+    X1 = a[None, :] ** np.arange(n1)[:, None]
+    X2 = c[None, :] ** np.arange(n2)[:, None]
+    got = m.energy_convolution(X1, X2, n_out, shift, s)
+    r = c / a
+    worst = 0.0
+    for k in range(n_out):
+        mm = k + shift
+        lo, hi = max(0, mm - n1 + 1), min(mm, n2 - 1)
+        ref = s * a ** mm * (r ** lo - r ** (hi + 1)) / (1.0 - r) if lo <= hi else 0.0 * a
+        worst = max(worst, float(np.max(np.abs(got[k] - ref))))
+    D = np.zeros((n2, 3), np.complex128)
+    D[2] = 1.0
+    Y = synth.cn(rng, (n1, 3), 1.0)
+    gotd = m.energy_convolution(Y, D, n_out, shift, 1.0, True)
+    for k in range(n_out):
+        j = k + shift - 2
+        ref = Y[::-1][j] if 0 <= j < n1 else 0.0 * Y[0]
+        worst = max(worst, float(np.max(np.abs(gotd[k] - ref))))
+    Z = synth.cn(rng, (n2, 3), 1.0)
+    full = m.energy_convolution(Y, Z, n1 + n2 - 1, 0, 1.0)
+    for i in range(3):
+        worst = max(worst, float(np.max(np.abs(full[:, i] - np.convolve(Y[:, i], Z[:, i])))))
+    return worst
+
+
 # --------------------------------------------------------------- mutations
 
 _CASES = [
@@ -198,6 +231,16 @@ _CASES = [
      "gl_d, gl_l, _ = (np.asarray(t) for t in GL)", _check_observables),
     ("observables", "sign in the spectral function", "1j * (gg_d[i] - gl_d[i])",
      "1j * (gl_d[i] - gg_d[i])", _check_observables),
+    # Sec. "Energy Convolutions" (Eq. interaction)
+    ("convolution", "energy index of X2 with the wrong sign", "j = k + shift - kp",
+     "j = k + shift + kp", _check_convolution),
+    ("convolution", "difference grid shift dropped", "j = k + shift - kp", "j = k - kp",
+     _check_convolution),
+    ("convolution", "prefactor dropped", "B[k] = scale * acc", "B[k] = acc", _check_convolution),
+    ("convolution", "reversal ignored", "X1p = X1[::-1] if reverse1 else X1", "X1p = X1",
+     _check_convolution),
+    ("convolution", "last X1 sample left out", "if 0 <= j < n1:", "if 0 <= j < n1 - 1:",
+     _check_convolution),
     # Sec. 4.4 (nested dissection)
     ("nested", "sign of X_IS", "X_IS = -a @ A_IS @ X_SS", "X_IS = a @ A_IS @ X_SS", _check_nested),
     ("nested", "sign of the Schur complement", "S = A_SS - A_SI @ a @ A_IS",
