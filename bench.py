@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--mode", default="plain",
                     choices=["plain", "mixed", "uneven", "serve", "gemm", "obc",
-                             "observables", "nested"])
+                             "observables", "nested", "convolution"])
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-blocks", type=int, default=32)
@@ -118,6 +118,8 @@ def parse():
     ap.add_argument("--partitions", default="2,4,8,16",
                     help="nested: partition counts to time")
     ap.add_argument("--nested-blocks", type=int, default=128, help="nested: block count")
+    ap.add_argument("--conv-blocks", type=int, default=16,
+                    help="convolution: blocks of b x b entries convolved over energy")
     ap.add_argument("--nested-energies", type=int, default=1, help="nested: energies")
     ap.add_argument("--pool-gib", type=float, default=150.0,
                     help="serve: device memory for requests admitted by the client")
@@ -1182,6 +1184,64 @@ def run_observables(args):
     print(json.dumps(out), flush=True)
 
 
+def run_convolution(args):
+    """Element-wise energy convolution (Eq. interaction) of the diagonal
+    blocks of a device: X2 = a descriptor on N energies, X1 = the other on
+    the 2N - 1 energy differences, B on the N energies (every term inside
+    X1's range).  Random contents; FP64 vector arithmetic."""
+    import torch
+    from paper_2508_19138_amd import qtx_rgf as Q
+    nb, b, N = args.conv_blocks, args.block_size, args.energies
+    n_elem = nb * b * b
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(args.seed)
+    X1 = torch.randn((2 * N - 1, n_elem), dtype=torch.complex128, device="cuda:0", generator=g)
+    X2 = torch.randn((N, n_elem), dtype=torch.complex128, device="cuda:0", generator=g)
+    B = torch.empty((N, n_elem), dtype=torch.complex128, device="cuda:0")
+    s = 1j / (2 * np.pi)
+    with Q.Context(0) as ctx:
+        torch.cuda.synchronize()
+        for _ in range(max(1, args.warmup)):
+            ctx.energy_convolution(n_elem, X1, 2 * N - 1, X2, N, B, N, N - 1, s)
+        ts = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            ctx.energy_convolution(n_elem, X1, 2 * N - 1, X2, N, B, N, N - 1, s)
+            ts.append(time.perf_counter() - t0)
+    dt = float(np.median(ts))
+    flops = 8.0 * n_elem * N * N
+    by = 16.0 * n_elem * (3 * N - 1 + N)
+    # CPU baseline: the oracle on a bounded sample of the elements
+    from oracle import energy_convolution
+    m = 4096
+    x1 = X1[:, :m].cpu().numpy()
+    x2 = X2[:, :m].cpu().numpy()
+    t0 = time.perf_counter()
+    energy_convolution(x1, x2, N, N - 1, s)
+    tc = time.perf_counter() - t0
+    out = {"mode": "convolution",
+           "metric": "element-wise energy convolutions: energy-points/s + % of FP64 vector peak",
+           "value": round(N / dt, 2), "unit": "energy-points/s", "n_gpus": 1,
+           "steps": args.steps, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "B(E_k) = s sum_k' X1(E_k - E_k') X2(E_k') element by element "
+                                  "over %d blocks of %dx%d entries, %d energies, X1 on the %d "
+                                  "energy differences" % (nb, b, b, N, 2 * N - 1),
+                      "n_elem": n_elem, "n_energies": N},
+           "roofline": {"bound": "alu", "achieved": round(flops / dt / 1e12, 3),
+                        "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(flops / dt / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
+                        "traffic": None, "algorithmic_flops_per_call": flops,
+                        "algorithmic_bytes_per_call": by,
+                        "note": "host-timed call; peak = the FP64 vector rate (equal to the "
+                                "FP64 matrix rate on MI355X)"},
+           "cpu_baseline": {"value": round(N * m / n_elem / tc, 4), "unit": "energy-points/s",
+                            "cores": 1, "kind": "oracle",
+                            "sample": "%d of the %d elements (all energies), scaled to the whole "
+                                      "workload; NumPy, %.1f s" % (m, n_elem, tc)}}
+    print(json.dumps(out), flush=True)
+
+
 def run_nested(args):
     """Partitioned solve (qtx_rgf_solve_nested) of one long device at few
     energies, for several partition counts, against the plain solve of the
@@ -1300,6 +1360,8 @@ def main():
         run_plain(args, mixed=True)
     elif args.mode == "uneven":
         run_uneven(args)
+    elif args.mode == "convolution":
+        run_convolution(args)
     elif args.mode == "gemm":
         run_gemm(args)
     elif args.mode == "obc" and args.obc_method.startswith("lyap"):

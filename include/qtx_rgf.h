@@ -452,6 +452,32 @@ qtx_status qtx_rgf_obc_lesser_greater(qtx_rgf_ctx* ctx, int32_t b, int32_t batch
  * couplings' adjoints) plus batch (n-1) ceil(b*b / 2048) doubles (the
  * current's partial sums) from the context's workspace.  Errors:
  * QTX_ERR_INVALID_ARG, QTX_ERR_NOMEM, QTX_ERR_BUSY, QTX_ERR_HIP. */
+/* Element-wise energy convolution of two energy-resolved quantities, the
+ * form of the scattering terms P and Sigma (Sec. "Energy Convolutions",
+ * Eq. interaction: B_scatt(E) is proportional to the integral over E' of
+ * X1(E - E') X2(E'), the products taken entry by entry).  On uniform energy
+ * grids of one spacing, with the prefactor (sign, i / 2 pi, the spacing)
+ * folded into s = scale_re + i scale_im:
+ *     B[k][i] = s * sum_{k'=0}^{n2-1} X1'[k + shift - k'][i] * X2[k'][i],
+ *     0 <= k < n_out, 0 <= i < n_elem,
+ * X1' = X1, or X1 with its energy order reversed (X1'[j] = X1[n1-1-j]) when
+ * reverse1 = 1, which gives the correlation form G(E') G(E' - E); terms
+ * whose X1' index lies outside [0, n1) are left out, and shift places the
+ * difference grid of X1 against the output grid.
+ *   X1  [n1][n_elem], X2 [n2][n_elem], B [n_out][n_elem]: complex128 device
+ *       arrays, energy-major (the layout of the solve's outputs: the
+ *       selected blocks of one energy, [n][b][b] or a block range of them,
+ *       are n_elem consecutive entries).  B must not overlap X1 or X2.
+ * Summation over k' in increasing order, in FP64.  n_elem >= 0, n1, n2 >= 1,
+ * n_out >= 0, reverse1 in {0, 1}; returns when written.  Errors:
+ * QTX_ERR_INVALID_ARG, QTX_ERR_BUSY, QTX_ERR_HIP. */
+qtx_status qtx_rgf_energy_convolution(qtx_rgf_ctx* ctx, int64_t n_elem,
+                                      const void* X1, int32_t n1,
+                                      int32_t reverse1, const void* X2,
+                                      int32_t n2, void* B, int32_t n_out,
+                                      int32_t shift, double scale_re,
+                                      double scale_im);
+
 /* The screened interaction's lesser/greater surface function (Sec.
  * "Lesser/Greater OBC"): the solution w of Eq. (lyapunov),
  *     w = q - a w a^dagger,

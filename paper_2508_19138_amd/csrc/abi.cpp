@@ -889,6 +889,36 @@ qtx_status qtx_rgf_observables(qtx_rgf_ctx* c, int32_t n_blocks, int32_t b, int3
   return QTX_OK;
 }
 
+// Eq. (interaction): the element-wise energy convolution, one launch.
+qtx_status qtx_rgf_energy_convolution(qtx_rgf_ctx* c, int64_t n_elem, const void* X1,
+                                      int32_t n1, int32_t reverse1, const void* X2, int32_t n2,
+                                      void* B, int32_t n_out, int32_t shift, double scale_re,
+                                      double scale_im) {
+  if (!c || n_elem < 0 || n1 < 1 || n2 < 1 || n_out < 0 || !X1 || !X2 || !B)
+    return QTX_ERR_INVALID_ARG;
+  if (reverse1 != 0 && reverse1 != 1) return QTX_ERR_INVALID_ARG;
+  {
+    const Span sb = span_of(B, n_elem, n_elem, n_out);
+    if (overlap(sb, span_of(X1, n_elem, n_elem, n1)) || overlap(sb, span_of(X2, n_elem, n_elem, n2)))
+      return QTX_ERR_INVALID_ARG;
+  }
+  if (c->busy) return QTX_ERR_BUSY;
+  if (n_elem == 0 || n_out == 0) return QTX_OK;
+  BusyGuard g(c);
+  c->err.clear();
+  try {
+    HIPCHK(c, hipSetDevice(c->device));
+    const hipStream_t st = c->pool->exe(0).stream();
+    HIPCHK(c, launch_energy_convolution(X1, n1, reverse1, X2, n2, B, n_out, shift, scale_re,
+                                        scale_im, n_elem, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+  } catch (const Fail& fl) {
+    if (c->err.empty()) c->err = fl.what;
+    return (qtx_status)fl.st;
+  }
+  return QTX_OK;
+}
+
 // Eq. (lyapunov) by the plain iteration, all energies at once: two
 // products per iteration (T = w a^dagger, w' = q - a T), ping-pong buffers.
 qtx_status qtx_rgf_obc_lyapunov_fixed_point(qtx_rgf_ctx* c, int32_t b, int32_t batch,

@@ -265,6 +265,12 @@ size_t observables_part_bytes(int n, int b, int batch);
 hipError_t launch_observables(const void* gl_d, const void* gg_d, const void* gl_l,
                               const void* hd, double* dos, double* dens, double* cur, int n,
                               int b, int batch, double* part, hipStream_t s);
+// B[k][i] = s * sum_{k'} X1'[k + shift - k'][i] X2[k'][i] (X1' = X1, or X1
+// reversed in energy when rev), [energy][n_elem] complex128, terms outside
+// [0, n1) left out (convolution.hip).
+hipError_t launch_energy_convolution(const void* X1, int n1, int rev, const void* X2, int n2,
+                                     void* B, int n_out, int shift, double s_re, double s_im,
+                                     long long n_elem, hipStream_t st);
 // L_e = -f_e (S_e - S_e^dagger), G_e = (1 - f_e)(S_e - S_e^dagger) with
 // occ[2e] = f_e, occ[2e + 1] = 1 - f_e (device); S_e at stride sS (0 = shared),
 // L and G contiguous, either may be null.

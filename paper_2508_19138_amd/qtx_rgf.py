@@ -146,6 +146,11 @@ def lib():
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_void_p]
     L.qtx_rgf_observables.restype = ctypes.c_int
+    L.qtx_rgf_energy_convolution.argtypes = [
+        c_ctx, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+        ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+        ctypes.c_double, ctypes.c_double]
+    L.qtx_rgf_energy_convolution.restype = ctypes.c_int
     lyap = [c_ctx, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
             ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
     L.qtx_rgf_obc_lyapunov_fixed_point.argtypes = lyap
@@ -172,7 +177,8 @@ def exported_symbols():
             "qtx_rgf_solve_nested",
             "qtx_rgf_obc_fixed_point", "qtx_rgf_obc_sancho_rubio",
             "qtx_rgf_obc_lesser_greater", "qtx_rgf_observables",
-            "qtx_rgf_obc_lyapunov_fixed_point", "qtx_rgf_obc_lyapunov_doubling"]
+            "qtx_rgf_obc_lyapunov_fixed_point", "qtx_rgf_obc_lyapunov_doubling",
+            "qtx_rgf_energy_convolution"]
 
 
 def status_string(st):
@@ -349,6 +355,15 @@ class Context:
                                        _ptr(XL_lower), _ptr(H_upper), _ptr(dos),
                                        _ptr(density), _ptr(current))
         return self._check(st, "qtx_rgf_observables")
+
+    def energy_convolution(self, n_elem, X1, n1, X2, n2, B, n_out, shift=0, scale=1.0,
+                           reverse1=False):
+        """B[k][i] = scale * sum_k' X1'[k + shift - k'][i] X2[k'][i]; see the C header."""
+        s = complex(scale)
+        st = lib().qtx_rgf_energy_convolution(self._h, n_elem, _ptr(X1), n1, int(bool(reverse1)),
+                                              _ptr(X2), n2, _ptr(B), n_out, shift, s.real,
+                                              s.imag)
+        return self._check(st, "qtx_rgf_energy_convolution")
 
     def obc_lyapunov_fixed_point(self, b, batch, a, s_a, q, s_q, w, update, n_iter):
         """n_iter iterations of w <- q - a w a^dagger; see the C header."""
