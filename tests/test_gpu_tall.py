@@ -3,9 +3,10 @@ rows proposes the rows its own elimination pivots on, one workgroup picks
 the panel's pivot rows among them, every row then follows from the pivot
 block's inverse).  The batched inverse against numpy for random, structured
 and graded matrices, singular and non-finite columns past the first 1024,
-and RGF solves at b = 1100 and at the NW-2 block size 2016 (Table
-tab:structure_param) against the oracle, every output block at the FP64
-bound (Sec. 3.2.3 recursion; Eq. system-solve definition)."""
+and against the oracle at the FP64 bound (Sec. 3.2.3 recursion; Eq.
+system-solve definition): G-type solves at b = 1100 and at the NW-2 block
+size 2016 (Table tab:structure_param), a W-type solve with W^R at b = 1040,
+and the partitioned solve (Sec. 4.4) at b = 1100."""
 
 import numpy as np
 import pytest
@@ -141,3 +142,56 @@ def test_tall_block_solve_matches_oracle(ctx, n, b, bt):
     assert triple_err(_sel(XR, 0), OR) < TOL
     assert triple_err(_sel(XL, 0), OL) < TOL
     assert triple_err(_sel(XG, 0), OG) < TOL
+
+
+def test_tall_block_w_type_solve(ctx):
+    """W-type (I - V P^R) at b = 1040: the assembly products, the solve and
+    W^R_ii on the tournament path."""
+    from oracle import assemble_w, w_retarded_diag
+    gh = _gh()
+    n, b = 2, 1040
+    E = np.array([0.7])
+    p = synth.w_problem(17, n, b, E)
+    V = (gh.dev(p["V"][0]), gh.dev(p["V"][1]), None)
+    Pr = tuple(gh.dev(t) for t in p["P_r"])
+    Pl = (gh.dev(p["P_l"][0]), gh.dev(p["P_l"][1]), None)
+    Pg = (gh.dev(p["P_g"][0]), gh.dev(p["P_g"][1]), None)
+    XR, XL, XG = gh.outputs(1, n, b), gh.outputs(1, n, b), gh.outputs(1, n, b)
+    WR = gh.empty((1, n, b, b))
+    prob = Q.make_w_problem(V, Pr, Pl, Pg, XR, XL, XG, WR)
+    torch.cuda.synchronize()
+    print("W solve n %d b %d" % (n, b), flush=True)
+    ctx.solve_batch([prob])
+    torch.cuda.synchronize()
+    assert prob.status == 0
+    A, Bs = assemble_w(p["V"], tuple(t[0] for t in p["P_r"]),
+                       [tuple(t[0] for t in p["P_l"]), tuple(t[0] for t in p["P_g"])])
+    OR, (OL, OG) = rgf_selected(A, Bs)
+    for got, ref in ((gh.host(XR), OR), (gh.host(XL), OL), (gh.host(XG), OG)):
+        assert triple_err(_sel(got, 0), ref) < TOL
+    from blockcmp import max_rel_err
+    assert max_rel_err(WR.cpu().numpy()[0], w_retarded_diag(OR, p["V"])) < TOL
+
+
+def test_tall_block_partitioned_solve(ctx):
+    """The partitioned solve (Sec. 4.4) at b = 1100: 5 blocks in 2
+    partitions, one energy, against the oracle."""
+    gh = _gh()
+    n, b, P = 5, 1100, 2
+    p = synth.g_problem(5, n, b, n_e=1)
+    E = np.ascontiguousarray(p["energies"], dtype=np.float64)
+    H = tuple(gh.dev(t) for t in p["H"])
+    sr = tuple(gh.dev(t) for t in p["sigma_r"])
+    sl = (gh.dev(p["sigma_l"][0]), gh.dev(p["sigma_l"][1]), None)
+    sg = (gh.dev(p["sigma_g"][0]), gh.dev(p["sigma_g"][1]), None)
+    XR, XL, XG = gh.outputs(1, n, b), gh.outputs(1, n, b), gh.outputs(1, n, b)
+    prob = Q.make_g_problem(E, H, sr, sl, sg, XR, XL, XG)
+    torch.cuda.synchronize()
+    print("nested solve n %d b %d P %d" % (n, b, P), flush=True)
+    ctx.solve_nested(prob, P)
+    torch.cuda.synchronize()
+    assert prob.status == 0
+    OR, (OL, OG) = _oracle_g(p, 0)
+    assert triple_err(_sel(gh.host(XR), 0), OR) < TOL
+    assert triple_err(_sel(gh.host(XL), 0), OL) < TOL
+    assert triple_err(_sel(gh.host(XG), 0), OG) < TOL
