@@ -237,16 +237,36 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
     return;
   }
   if (f.k == OpK::Inv) {
-    // three-level blocked Gauss-Jordan (see zinv.hip): per mega-panel, per
+    // Matrices of b <= kSmallB: one launch of the one-workgroup inverse.
+    // The others: three-level blocked Gauss-Jordan (see zinv.hip): per mega-panel, per
     // super-panel, its panels each followed by a rank-kPanel update of the
     // super-panel, then the super-panel's gather and rank-kSuper update of
     // the mega-panel's columns; after the mega-panel its gather and the
     // rank-kMega update of the columns outside it; one permutation at the end
-    std::vector<InvDesc> all;
+    std::vector<InvDesc> all, small;
     double fl = 0;
     for (auto& lo : ops) {
-      for (int q = 0; q < lo.second->count; ++q) all.push_back(lo.first->id[lo.second->first + q]);
+      for (int q = 0; q < lo.second->count; ++q) {
+        const InvDesc& v = lo.first->id[lo.second->first + q];
+        (v.b <= kSmallB ? small : all).push_back(v);
+      }
       fl += lo.second->flops;
+    }
+    bool first = true;
+    if (!small.empty()) {
+      // matrices of one workgroup's registers: the whole inverse in one launch
+      std::vector<int> pre(1, 0);
+      int rpl = 1;
+      double by = 0;
+      for (const InvDesc& v : small) {
+        pre.push_back(pre.back() + v.batch);
+        rpl = std::max(rpl, small_rpl(v.b));
+        by += 32.0 * v.b * (double)v.b * v.batch;
+      }
+      recs_.push_back(LaunchRec{LaunchRec::Small, 'N', 'N', false, rpl, 0, put(small),
+                                put_prefix(pre), (int)small.size(), pre.back(), kClassInv, fl, by});
+      first = false;
+      if (all.empty()) return;
     }
     int maxb = 0, maxn = 0;            // largest b, largest b of the one-workgroup panels
     for (auto& v : all) {
@@ -255,7 +275,6 @@ void Executor::emit_group(std::vector<std::pair<Lane*, Op*>>& ops) {
     }
     const int R = std::max(1, (maxn + kInvThreads - 1) / kInvThreads);
 
-    bool first = true;
     auto gather_and_update = [&](int K0, int W, int cfg,
                                  const std::function<int(const InvDesc&, GemmDesc*)>& upd) {
       std::vector<InvDesc> d;
@@ -453,6 +472,7 @@ void Executor::issue(char* base, bool profile) {
       case LaunchRec::TallFinal: XCHK(launch_inv_tall(2, r.k0, l, s_)); break;
       case LaunchRec::TallApply: XCHK(launch_inv_tall(3, r.k0, l, s_)); break;
       case LaunchRec::Permute: XCHK(launch_inv_permute(l, s_)); break;
+      case LaunchRec::Small: XCHK(launch_inv_small(r.cfg, l, s_)); break;
       case LaunchRec::Gather: XCHK(launch_inv_super_gather(r.k0, r.cfg, l, s_)); break;
       case LaunchRec::Lin: XCHK(launch_lincomb(l, s_)); break;
       case LaunchRec::Trans: XCHK(launch_transcomb(l, s_)); break;

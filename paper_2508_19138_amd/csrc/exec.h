@@ -80,10 +80,11 @@ class Tuner {
 
 // One kernel launch of a merged schedule.
 struct LaunchRec {
-  enum Kind : uint8_t { Gemm, Panel, Gather, Permute, Lin, Trans, TallSelect, TallFinal, TallApply } kind;
+  enum Kind : uint8_t { Gemm, Panel, Gather, Permute, Lin, Trans, TallSelect, TallFinal, TallApply,
+                        Small } kind;
   char opa, opb;
   bool fp32;
-  int cfg;        // gemm tile config, rows-per-thread R (Panel) or width W (Gather)
+  int cfg;        // gemm tile config, rows per thread R (Panel, Small) or width W (Gather)
   int k0;         // Panel
   size_t desc_off, prefix_off;
   int nd, total;

@@ -15,7 +15,8 @@
 // Calls on one GPU share the array: two calls that overlap in time on that
 // GPU (different streams or contexts) race on it.  Nothing in the array
 // needs to start at zero: every buffer is written before it is read, and
-// the per-matrix status words are cleared by the first panel kernel.
+// the per-matrix status words are cleared by the first panel kernel (or by
+// the one-workgroup inverse, for b <= kSmallB).
 #include <mutex>
 #include <string>
 
@@ -43,7 +44,7 @@ char* g_ptr[kMaxDevices] = {};
 // at k0, `count` update products from upd[first] (tile configuration cfg),
 // or the final permutation.
 struct Step {
-  int kind;                  // 0 panel, 1 products, 2 gather, 3 permutation
+  int kind;                  // 0 panel, 1 products, 2 gather, 3 permutation, 4 whole (b <= kSmallB)
   int k0, W, cfg;
   int first, count;
 };
@@ -57,13 +58,18 @@ struct DescArea {
 };
 static_assert(sizeof(DescArea) <= kDescBytes, "descriptor area");
 
-// The executor's launch sequence for one inverse operation, in order:
-// per mega-panel, per super-panel, each panel and its rank-kPanel update,
-// then the super-panel's gather and rank-kSuper update of the mega-panel's
-// columns; after the mega-panel its gather and rank-kMega update of the
-// other columns; the permutation last.  Returns the number of steps.
+// The executor's launch sequence for one inverse operation, in order: for
+// b <= kSmallB the one-workgroup inverse alone; else per mega-panel, per
+// super-panel, each panel and its rank-kPanel update, then the
+// super-panel's gather and rank-kSuper update of the mega-panel's columns;
+// after the mega-panel its gather and rank-kMega update of the other
+// columns; the permutation last.  Returns the number of steps.
 __host__ __device__ inline int inv_steps(const InvDesc& v, Step* st, GemmDesc* upd) {
   int ns = 0, nu = 0;
+  if (v.b <= kSmallB) {
+    st[ns++] = Step{4, 0, 0, 0, 0, 0};
+    return ns;
+  }
   for (int M0 = 0; M0 < v.b; M0 += kMega) {
     const int mend = v.b < M0 + kMega ? v.b : M0 + kMega;
     for (int K0 = M0; K0 < mend; K0 += kSuper) {
@@ -97,7 +103,8 @@ __host__ __device__ inline int inv_steps(const InvDesc& v, Step* st, GemmDesc* u
 // workgroups of a step
 __host__ __device__ inline int step_total(const InvDesc& v, const Step& t, const GemmDesc* upd) {
   switch (t.kind) {
-    case 0: return v.batch;
+    case 0:
+    case 4: return v.batch;
     case 2: return v.batch * super_gather_chunks(v.b, t.W);
     case 3: return v.batch * ((v.b + kPermRows - 1) / kPermRows);
     default: {
@@ -217,6 +224,7 @@ extern "C" qtx_status qtx_rgf_zinv_noalloc(qtx_rgf_ctx* c, int32_t b, void* A, v
     } else {
       const FlatLaunch l{&dev->inv, dev->pre[i], 1, total};
       if (t.kind == 0) e = launch_inv_panel(R, t.k0, l, s);
+      else if (t.kind == 4) e = launch_inv_small(small_rpl(b), l, s);
       else if (t.kind == 2) e = launch_inv_super_gather(t.k0, t.W, l, s);
       else e = launch_inv_permute(l, s);
     }

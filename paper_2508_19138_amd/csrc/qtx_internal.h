@@ -226,6 +226,14 @@ __host__ __device__ inline bool inv_mega_update(const InvDesc& v, int M0, int si
   return true;
 }
 
+// Matrices of b <= kSmallB are inverted whole by one workgroup each, in one
+// launch (registers hold the matrix: rpl = 1 for b <= 64, 2 for b <= 128;
+// 256 rpl threads).  The result is written permuted to X; S is only read,
+// and the work buffers are not used.
+constexpr int kSmallB = 128;
+inline int small_rpl(int b) { return b <= 64 ? 1 : 2; }
+hipError_t launch_inv_small(int rpl, const FlatLaunch& l, hipStream_t s);
+
 // Final permutation X[k][p_j] = S[p_k][j]; 8 rows per workgroup.
 constexpr int kPermRows = 8;
 hipError_t launch_inv_permute(const FlatLaunch& l, hipStream_t s);

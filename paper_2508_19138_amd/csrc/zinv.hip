@@ -23,6 +23,10 @@
 // the matrix cores updates the whole matrix.  Gathered pivot rows carry
 // zeros in the columns being eliminated, so those pass through unchanged.
 //
+// Matrices of at most kSmallB rows skip the blocking: one workgroup holds
+// the whole matrix in registers and eliminates it column by column in a
+// single launch (gj_small_kernel).
+//
 // Matrices above kInvThreads * 4 rows do not fit one workgroup's registers.
 // Their panels pick the pivot rows by a tournament: every chunk of
 // kTallChunk rows eliminates the panel columns on its own rows and proposes
@@ -640,7 +644,273 @@ void gj_permute_kernel(FlatLaunch L) {
   }
 }
 
+// ---- the whole inverse in one workgroup (b <= kSmallB) ----------------------
+//
+// A matrix of up to 16 TR rows fits the registers of one workgroup of TR
+// waves.  Wave w holds columns [16 w, 16 w + 16); lane 16 ct + rt of it
+// holds a tile of rows rt + 16 i (i < TR) by columns 16 w + 4 ct + j
+// (j < 4).  The columns are eliminated one at a time in one launch, so the
+// inverse is one launch instead of a chain of panels and updates.  Per
+// column k, with one barrier: every wave reads the pivot row p_k and the
+// reciprocal pivot published for it, takes the pivot row's entries in its
+// columns from the four lanes that hold them (through LDS, within the
+// wave), forms the multipliers g_r = A[r][k] / pivot of its rows from the
+// published column and applies the rank-1 update to its tile.  The wave
+// holding column k + 1 updates that column first, searches it for the next
+// pivot row (a maximum over the column's 16 lanes) and publishes the
+// column and the reciprocal of its pivot, which overlaps the other waves'
+// updates.  The tile shape keeps
+// what each lane reads per column to 4 pivot-row entries and TR column
+// entries.  (Measured slower: a 16-column panel eliminated inside one wave
+// with the other columns updated once per panel, where the other waves
+// idle while the panel's columns go one after the other; and the winner's
+// reciprocal taken by readlane from every lane's own candidate, which
+// lengthens the search.)
+//
+// Pivot rows are left unscaled until all columns are done (as in the panel
+// kernel), and each eliminated column holds +g_r with -1 on its pivot row,
+// the negative of the Gauss-Jordan column (-g_r, and 1 before the
+// deferred scaling).  Later updates are linear in every eliminated column,
+// so the whole result comes out negated, and the final scaling of pivot
+// row p_k by -1/pivot_k undoes that; negation is exact, so the result has
+// the bits of the unnegated elimination.  The published column carries a
+// zero on the pivot row, which therefore takes no multiplier.  The result
+// is written permuted, X[k][p_j] = Y[p_k][j], through LDS in passes of 64
+// rows so that the stores are coalesced.
+template <int TR>
+__global__ __launch_bounds__(64 * TR)
+void gj_small_kernel(FlatLaunch L) {
+  constexpr int SB = 16 * TR;           // largest b: rows and columns
+  constexpr int NW = SB / 16;           // waves, 16 columns each
+  constexpr int NT = 64 * NW;           // threads
+  __shared__ uint2 hdrS[2];             // by column parity: pivot key, flags (1 non-finite, 2 zero pivot)
+  __shared__ double2 invS[2];           // reciprocal of the pivot
+  __shared__ double2 colS[2][4][SB];    // the column at each lane column offset of the searching wave
+  __shared__ double2 rowW[NW][16];      // the pivot row's entries in each wave's columns
+  __shared__ int permS[SB];             // pivot row of each column
+  __shared__ int posS[SB];              // column that row r pivots
+  __shared__ double2 pinvS[SB];         // reciprocal pivot of each column
+  __shared__ double2 stage[64][SB + 1]; // 64 rows on their way to or from HBM
+
+  const int di = find_desc(L.prefix, L.nd, blockIdx.x);
+  const InvDesc& d = ((const InvDesc*)L.desc)[di];
+  const int b = d.b;
+  const long long e = blockIdx.x - L.prefix[di];
+  const double2* A = (const double2*)d.S + e * d.sS;
+  double2* X = (double2*)d.X + e * d.sX;
+  const int code0 = d.code;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int rt = lane & 15, ct = lane >> 4;
+  const int cb = 16 * wave + 4 * ct;    // this lane's first column
+
+  double2 a[TR][4];
+  for (int i = t; i < SB; i += NT) posS[i] = i;
+#pragma unroll
+  for (int q = 0; q < TR / 4; ++q) {
+    // rows [64 q, 64 q + 64), i.e. rows rt + 16 i for i in [4 q, 4 q + 4):
+    // coalesced into LDS, then each lane takes its tile (zero past b)
+#pragma unroll
+    for (int s = 0; s < 64 * SB / NT; ++s) {
+      const int idx = t + s * NT;
+      const int rl = idx / SB, c = idx % SB;
+      const int r = 64 * q + rl;
+      const bool ok = r < b && c < b;
+      double2 v = A[ok ? (long long)r * b + c : 0];
+      if (!ok) v = make_double2(0.0, 0.0);
+      stage[rl][c] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[4 * q + ii][j] = stage[rt + 16 * ii][cb + j];
+    __syncthreads();
+  }
+  unsigned um = 0;                      // bit i: row rt + 16 i already a pivot row (rows past b count as used)
+#pragma unroll
+  for (int i = 0; i < TR; ++i) um |= (rt + 16 * i >= b ? 1u : 0u) << i;
+
+  // Search of column 16 w + 4 nct + nj (register column nj of the lanes
+  // with ct == nct) over the unused rows; all lanes' register column nj goes
+  // to colS[buf][ct], and the winner's key, the non-finite flag, the pivot
+  // row and the pivot element come back uniform.
+  auto search = [&](int nj, int nct, int buf, unsigned& wk, int& wbad, int& pn,
+                    double2& pe) __attribute__((always_inline)) {
+    unsigned key = 0;
+    int bad = 0;
+#pragma unroll
+    for (int i = 0; i < TR; ++i) {
+      const double v = a[i][nj].x * a[i][nj].x + a[i][nj].y * a[i][nj].y;
+      const bool fin = v <= 1.7976931348623157e308;     // not NaN or Inf
+      const bool un = ((um >> i) & 1u) == 0;
+      bad |= (un && !fin) ? 1 : 0;
+      const unsigned kv = (un && fin) ? pivot_key(v, rt + 16 * i) : 0u;
+      key = kv > key ? kv : key;
+    }
+    // maximum over each row of 16 lanes (the first four steps of wave_max)
+    key = dpp_max<0xB1, 0xf>(key);
+    key = dpp_max<0x4E, 0xf>(key);
+    key = dpp_max<0x141, 0xf>(key);
+    key = dpp_max<0x140, 0xf>(key);
+    wk = (unsigned)__builtin_amdgcn_readlane((int)key, 16 * nct);
+    wbad = __any(bad != 0 && ct == nct);
+#pragma unroll
+    for (int i = 0; i < TR; ++i) colS[buf][ct][rt + 16 * i] = a[i][nj];
+    wave_sync();
+    pn = wk ? pivot_row(wk) : 0;
+    pn = pn < SB ? pn : 0;
+    pe = colS[buf][nct][pn];
+  };
+  // After the search's wave has done its update: the header, the
+  // reciprocal pivot and a zero on the pivot row of the published column.
+  auto publish = [&](int nct, int buf, unsigned wk, int wbad, int pn, double2 pe,
+                     double2 inv1) __attribute__((always_inline)) {
+    if (lane == 0) {
+      const double pv = pe.x * pe.x + pe.y * pe.y;
+      hdrS[buf] = make_uint2(wk, (wbad ? 1u : 0u) | (pv <= 0.0 ? 2u : 0u));
+      invS[buf] = inv1;
+      colS[buf][nct][pn] = make_double2(0.0, 0.0);
+    }
+  };
+  if (wave == 0) {
+    unsigned wk;
+    int wbad, pn;
+    double2 pe;
+    search(0, 0, 0, wk, wbad, pn, pe);
+    publish(0, 0, wk, wbad, pn, pe, crecip_scaled(pe));
+  }
+
+  int first_bad = 0;
+  for (int kk = 0; kk < b; kk += 16) {
+    const int G = kk >> 4;              // the wave holding columns kk .. kk + 15
+#pragma unroll
+    for (int cl = 0; cl < 16; ++cl) {
+      const int k = kk + cl;
+      if (k >= b) continue;             // uniform across the workgroup
+      const int par = cl & 1;
+      const int ctk = cl >> 2, jk = cl & 3;   // lanes and register column of column k in wave G
+      __syncthreads();
+      const uint2 hd = hdrS[par];
+      const double2 inv = invS[par];
+      // A candidate exists unless every unused row was non-finite in this
+      // column; then row 0 keeps indices in range and info reports it.
+      int p = hd.x ? pivot_row(hd.x) : 0;
+      if (p >= b) p = 0;
+      const int ip = __builtin_amdgcn_readfirstlane(p >> 4), rtp = p & 15;
+      if (rt == rtp) {
+#pragma unroll
+        for (int i = 0; i < TR; ++i)
+          if (i == ip) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) rowW[wave][4 * ct + j] = a[i][j];
+          }
+      }
+      wave_sync();
+      double2 prow[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) prow[j] = rowW[wave][4 * ct + j];
+      {
+        const int code = code0 > 0 ? code0 : 1 + k;
+        const int st = ((hd.y & 1u) || hd.x == 0) ? -code : ((hd.y & 2u) ? code : 0);
+        first_bad = first_bad != 0 ? first_bad : st;
+      }
+      if (t == 0) { permS[k] = p; pinvS[k] = inv; }
+      double2 g[TR];
+#pragma unroll
+      for (int i = 0; i < TR; ++i) {
+        g[i] = cmul(colS[par][ctk][rt + 16 * i], inv);
+        um |= (rt + 16 * i == p ? 1u : 0u) << i;
+      }
+      // column k in the lanes holding it: +g, and -1 on the pivot row (where g is 0)
+      const bool ownk = wave == G && ct == ctk;
+      const int nj = (cl + 1) & 3, nct = ((cl + 1) & 15) >> 2;
+      const int nwave = cl + 1 < 16 ? G : G + 1;
+      if (wave == nwave && k + 1 < b) {   // uniform across the wave
+#pragma unroll
+        for (int i = 0; i < TR; ++i) axpy_neg(a[i][nj], g[i], prow[nj]);
+        unsigned wk;
+        int wbad, pn;
+        double2 pe;
+        search(nj, nct, par ^ 1, wk, wbad, pn, pe);
+        const double2 inv1 = crecip_scaled(pe);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (j == nj) continue;
+#pragma unroll
+          for (int i = 0; i < TR; ++i) axpy_neg(a[i][j], g[i], prow[j]);
+        }
+#pragma unroll
+        for (int i = 0; i < TR; ++i) {
+          const double2 h = make_double2(g[i].x + (rt + 16 * i == p ? -1.0 : 0.0), g[i].y);
+          if (ownk) a[i][jk] = h;      // (a store, not a select of two lvalues: that would take their addresses)
+        }
+        publish(nct, par ^ 1, wk, wbad, pn, pe, inv1);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < TR; ++i) axpy_neg(a[i][j], g[i], prow[j]);
+#pragma unroll
+        for (int i = 0; i < TR; ++i) {
+          const double2 h = make_double2(g[i].x + (rt + 16 * i == p ? -1.0 : 0.0), g[i].y);
+          if (ownk) a[i][jk] = h;      // (a store, not a select of two lvalues: that would take their addresses)
+        }
+      }
+    }
+  }
+  __syncthreads();                      // permS, pinvS complete
+  // Pivots are distinct rows unless a non-finite column was met (flagged
+  // through info); rows named twice keep every index in range.
+  for (int k = t; k < b; k += NT) posS[permS[k]] = k;
+  __syncthreads();
+  int pc[4];                            // destination column of each register column
+#pragma unroll
+  for (int j = 0; j < 4; ++j) pc[j] = cb + j < b ? permS[cb + j] : -1;
+#pragma unroll
+  for (int q2 = 0; q2 < TR / 4; ++q2) {
+    // destination rows [64 q2, 64 q2 + 64); row r goes to row posS[r],
+    // scaled by minus its reciprocal pivot
+#pragma unroll
+    for (int i = 0; i < TR; ++i) {
+      const int r = rt + 16 * i;
+      const int pr = r < b ? posS[r] : -1;
+      if (pr >= 0 && pr >> 6 == q2) {
+        const double2 s = pinvS[pr];
+        const double2 ns = make_double2(-s.x, -s.y);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (pc[j] >= 0) stage[pr & 63][pc[j]] = cmul(a[i][j], ns);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 64 * SB / NT; ++s) {
+      const int idx = t + s * NT;
+      const int rl = idx / SB, c = idx % SB;
+      const int r = 64 * q2 + rl;
+      if (r < b && c < b) X[(long long)r * b + c] = stage[rl][c];
+    }
+    __syncthreads();
+  }
+  if (t == 0 && d.info) {
+    int* inf = d.info + e;
+    if (d.reset_info) *inf = first_bad;
+    else if (first_bad != 0 && *inf == 0) *inf = first_bad;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_inv_small(int rpl, const FlatLaunch& l, hipStream_t s) {
+  if (l.total <= 0) return hipSuccess;
+  switch (rpl) {
+    case 1: hipLaunchKernelGGL((gj_small_kernel<4>), dim3(l.total), dim3(256), 0, s, l); break;
+    case 2: hipLaunchKernelGGL((gj_small_kernel<8>), dim3(l.total), dim3(512), 0, s, l); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_inv_panel(int R, int k0, const FlatLaunch& l, hipStream_t s) {
   if (l.total <= 0) return hipSuccess;

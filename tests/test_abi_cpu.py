@@ -107,7 +107,7 @@ def test_panel_kernel_rows_stay_in_registers(tmp_path):
     registers; compiled with the library's options (hipcc cross-compiles
     for gfx950 without a device), the instances for R = 1..3 must not place
     that array in scratch memory (nor the tall path's chunk and final
-    instances)."""
+    instances, nor the one-workgroup inverse its tile)."""
     from paper_2508_19138_amd import build as B
     src = os.path.join(B.CSRC, "zinv.hip")
     out = str(tmp_path / "zinv.s")
@@ -126,3 +126,14 @@ def test_panel_kernel_rows_stay_in_registers(tmp_path):
         block = meta[lo:hi if hi >= 0 else len(meta)]
         m = re.search(r"\.private_segment_fixed_size:\s+(\d+)", block)
         assert m and int(m.group(1)) == 0, (R, mode, m and m.group(1))
+    # the one-workgroup inverse: its tile of TR x 4 complex entries per lane
+    # (256 or 512 bytes) stays in registers; a few spilled words of the
+    # set-up are allowed
+    for TR in (4, 8):
+        name = "_ZN3qtx12_GLOBAL__N_115gj_small_kernelILi%dEEEvNS_10FlatLaunchE" % TR
+        i = meta.index(".name:           " + name)
+        lo = meta.rindex("\n  - .", 0, i)
+        hi = meta.find("\n  - .", i)
+        block = meta[lo:hi if hi >= 0 else len(meta)]
+        m = re.search(r"\.private_segment_fixed_size:\s+(\d+)", block)
+        assert m and int(m.group(1)) <= 32, (TR, m and m.group(1))
