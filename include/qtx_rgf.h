@@ -312,8 +312,10 @@ qtx_status qtx_rgf_cgemm(qtx_rgf_ctx* ctx, char opa, char opb, int32_t m,
  * pivot rows of each 16-column panel are chosen by a tournament (each chunk
  * of 768 rows proposes the rows its own elimination pivots on, and the
  * elimination of the proposed rows picks among them), which is stable in
- * practice though its worst-case growth bound is weaker.  A [batch][b][b]
- * is overwritten (used as workspace); the inverses are written to X
+ * practice though its worst-case growth bound is weaker.  Up to b = 128 one
+ * workgroup per matrix does the whole inverse in one launch.  A [batch][b][b]
+ * is used as workspace (its contents afterwards are unspecified); the
+ * inverses are written to X
  * [batch][b][b].  info[batch] (device int32, may be NULL) receives 0, or
  * 1 + the column of the first exactly zero pivot, or -(1 + column) for a
  * non-finite pivot. */
