@@ -4,8 +4,8 @@
 // X1' = X1 or X1 reversed in energy, terms outside [0, n1) left out.  Data
 // are energy-major, [energy][element] (the layout of the solver's outputs).
 //
-// One thread per element, so that every energy row is read coalesced, and
-// kConvT consecutive outputs k per thread.  For one k' those outputs need
+// Long sequences: one thread per element, so that every energy row is read
+// coalesced, and kConvT consecutive outputs k per thread.  For one k' those outputs need
 // kConvT consecutive samples of X1', a window that moves down by one sample
 // per k': it is kept in registers as a ring whose slot indices are fixed by
 // unrolling kConvT steps, so a step reads one sample of X1' and one of X2
@@ -84,12 +84,133 @@ void energy_conv_kernel(const double2* __restrict__ X1, int n1, int rev,
   }
 }
 
+// Short sequences (n1 + n2 <= kLdsSamples): a workgroup stages the whole
+// X1' and X2 sequences of kLdsE consecutive entries in LDS once (X1 stored
+// reversed when asked, so that it is X1'), and all output tiles of those
+// entries are computed from there, so every input is read from HBM once
+// (the kernel above re-reads an entry's inputs for each of its output
+// tiles).  Thread (slot, e): entry e, outputs k0 .. k0 + kLdsT - 1 with
+// k0 = kLdsT slot + 16 kLdsT m; the same register ring and the same order of
+// the sums as above.  8 entries x 400 samples take 50 KB, so three
+// workgroups share a CU.
+constexpr int kLdsT = 8;                 // outputs per thread
+constexpr int kLdsE = 8;                 // entries per workgroup
+constexpr int kLdsThreads = kLdsE * 16;  // 16 output tiles per pass
+constexpr int kLdsSamples = 400;         // largest n1 + n2
+
+__global__ __launch_bounds__(kLdsThreads)
+void energy_conv_lds_kernel(const double2* __restrict__ X1, int n1, int rev,
+                            const double2* __restrict__ X2, int n2, double2* __restrict__ B,
+                            int n_out, int shift, double2 s, long long n_elem) {
+  __shared__ double2 S[kLdsSamples * kLdsE];   // [sample][entry]: X1' then X2
+  const long long i0 = (long long)blockIdx.x * kLdsE;
+  const int t = threadIdx.x;
+  const int ns = n1 + n2;
+  // consecutive threads take consecutive entries of one sample row; a
+  // compile-time trip count keeps all of a thread's loads in flight at once
+  constexpr int kPer = (kLdsSamples * kLdsE + kLdsThreads - 1) / kLdsThreads;
+  double2 v[kPer];
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const int idx = t + m * kLdsThreads;
+    const int sr = idx / kLdsE, e = idx % kLdsE;
+    const long long i = i0 + e;
+    v[m] = make_double2(0.0, 0.0);
+    if (idx < ns * kLdsE && i < n_elem)
+      v[m] = sr < n1 ? X1[(long long)(rev ? n1 - 1 - sr : sr) * n_elem + i]
+                     : X2[(long long)(sr - n1) * n_elem + i];
+  }
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const int idx = t + m * kLdsThreads;
+    if (idx < ns * kLdsE) S[idx] = v[m];
+  }
+  __syncthreads();
+  const int e = t % kLdsE, slot = t / kLdsE;
+  const long long i = i0 + e;
+  const double2* S2 = S + n1 * kLdsE;
+  // sample j of X1' at this entry (zero outside [0, n1))
+  auto x1 = [&](int j) {
+    const bool in = j >= 0 && j < n1;
+    double2 v = S[(in ? j : 0) * kLdsE + e];
+    if (!in) v = make_double2(0.0, 0.0);
+    return v;
+  };
+  for (int k0 = slot * kLdsT; k0 < n_out; k0 += 16 * kLdsT) {
+    double2 acc[kLdsT];
+#pragma unroll
+    for (int u = 0; u < kLdsT; ++u) acc[u] = make_double2(0.0, 0.0);
+    const int lo = max(0, k0 + shift - n1 + 1);
+    const int hi = min(n2 - 1, k0 + shift + kLdsT - 1);
+    if (lo <= hi) {
+      double2 ring[kLdsT];
+#pragma unroll
+      for (int u = 0; u < kLdsT; ++u) ring[u] = x1(k0 + shift - lo + u);
+      const int count = hi - lo + 1;
+      const int full = count / kLdsT * kLdsT;
+      // whole blocks of kLdsT steps: no guards, so all of a block's LDS
+      // reads are issued ahead of its multiply-adds
+      for (int r0 = 0; r0 < full; r0 += kLdsT) {
+        double2 bq[kLdsT], xq[kLdsT];
+#pragma unroll
+        for (int q = 0; q < kLdsT; ++q) {
+          const int kp = lo + r0 + q;
+          bq[q] = S2[kp * kLdsE + e];
+          xq[q] = x1(k0 + shift - kp - 1);
+        }
+#pragma unroll
+        for (int q = 0; q < kLdsT; ++q) {
+#pragma unroll
+          for (int u = 0; u < kLdsT; ++u) {
+            const double2 a = ring[(u - q + kLdsT) % kLdsT];
+            acc[u].x = fma(a.x, bq[q].x, fma(-a.y, bq[q].y, acc[u].x));
+            acc[u].y = fma(a.x, bq[q].y, fma(a.y, bq[q].x, acc[u].y));
+          }
+          ring[(kLdsT - 1 - q + kLdsT) % kLdsT] = xq[q];
+        }
+      }
+      // the last, partial block
+#pragma unroll
+      for (int q = 0; q < kLdsT; ++q) {
+        if (full + q < count) {
+          const int kp = lo + full + q;
+          const double2 b = S2[kp * kLdsE + e];
+#pragma unroll
+          for (int u = 0; u < kLdsT; ++u) {
+            const double2 a = ring[(u - q + kLdsT) % kLdsT];
+            acc[u].x = fma(a.x, b.x, fma(-a.y, b.y, acc[u].x));
+            acc[u].y = fma(a.x, b.y, fma(a.y, b.x, acc[u].y));
+          }
+          ring[(kLdsT - 1 - q + kLdsT) % kLdsT] = x1(k0 + shift - kp - 1);
+        }
+      }
+    }
+    if (i < n_elem) {
+#pragma unroll
+      for (int u = 0; u < kLdsT; ++u) {
+        const int k = k0 + u;
+        if (k < n_out)
+          B[(long long)k * n_elem + i] =
+              make_double2(s.x * acc[u].x - s.y * acc[u].y, s.x * acc[u].y + s.y * acc[u].x);
+      }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_energy_convolution(const void* X1, int n1, int rev, const void* X2, int n2,
                                      void* B, int n_out, int shift, double s_re, double s_im,
                                      long long n_elem, hipStream_t st) {
   if (n_elem <= 0 || n_out <= 0) return hipSuccess;
+  if (n1 + n2 <= kLdsSamples) {
+    const long long nb = (n_elem + kLdsE - 1) / kLdsE;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(energy_conv_lds_kernel, dim3((unsigned)nb), dim3(kLdsThreads), 0, st,
+                       (const double2*)X1, n1, rev, (const double2*)X2, n2, (double2*)B, n_out,
+                       shift, make_double2(s_re, s_im), n_elem);
+    return hipGetLastError();
+  }
   const long long groups = (n_elem + kConvThreads - 1) / kConvThreads;
   const int tiles_k = (n_out + kConvT - 1) / kConvT;
   const long long nb = groups * tiles_k;

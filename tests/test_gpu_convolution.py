@@ -1,9 +1,10 @@
 """GPU parity of the element-wise energy convolution (Sec. "Energy
 Convolutions", Eq. interaction) against the oracle (oracle.convolution,
 pinned by closed forms and library routines): random inputs over ragged
-element counts, output ranges off the 16-output tile, shifts that leave
-part or all of the window outside X1, the reversed (correlation) form, and
-the solver's own lesser/greater outputs convolved over energy.
+element counts, output ranges off the 8- and 16-output tiles, shifts that
+leave part or all of the window outside X1, the reversed (correlation)
+form, sequences short enough to be staged in LDS and longer ones, and the
+solver's own lesser/greater outputs convolved over energy.
 
 Bound: each output is a sum of n2 products computed in FP64 with fused
 multiply-adds (the oracle rounds each product first), so the difference is
@@ -59,6 +60,10 @@ def _close(got, ref, X1, X2, s):
     (300, 17, 17, 33, -5, 1),
     (513, 9, 40, 20, 60, 0),         # the window leaves X1 for the later outputs
     (77, 6, 6, 12, 40, 0),           # every output outside: zeros
+    # sequences longer than 400 samples in total: the kernel without LDS staging
+    (300, 260, 150, 170, 100, 0),
+    (129, 301, 120, 64, -7, 1),
+    (1000, 255, 128, 128, 127, 0),   # the shape of the benchmark on 1000 entries (staged in LDS)
 ])
 def test_random_inputs_match_oracle(ctx, n_elem, n1, n2, n_out, shift, rev):
     rng = np.random.default_rng(n_elem + 3 * n1 + 7 * n2 + shift)
