@@ -5,8 +5,7 @@
 // they are read from HBM (see zgemm_kernel) and double buffered.  Complex
 // numbers stay interleaved (re, im): each lane reads one complex per
 // fragment.  FP64 products take three real MFMAs per complex product (the
-// 3M form, see zgemm_kernel); FP32 products and the inverse's thin update
-// products four,
+// 3M form, see zgemm_kernel); FP32 products four,
 //     Cr += ar*br - ai*bi,   Ci += ar*bi + ai*br.
 // MFMA operand layout (measured on gfx950, both 16x16x4 f64 and f32): lane l
 // supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register r of lane l
@@ -64,7 +63,8 @@ struct Cfg {
 };
 
 // FP64 products use the 3M form (three accumulator sets, so 32 x 32 per
-// wave); FP32 products and the inverse's thin update products the
+// wave), the inverse's thin update products included (measured 4-7% faster
+// inverses at 128 matrices than with four products); FP32 products the
 // four-product form (FP32's 3M form measured 4x less accurate in the
 // partitioned solve).
 typedef Cfg<64, 64, 8, 2, 2> Cfg0;      // general, 3M: 32 x 32 per wave, three waves per SIMD
@@ -398,7 +398,7 @@ hipError_t launch_gemm(int cfg, bool fp32, char opa, char opb, const FlatLaunch&
                        hipStream_t s) {
   if (l.total <= 0 || l.nd <= 0) return hipSuccess;
   if (cfg == kGemmInvUpdate) {
-    hipLaunchKernelGGL((zgemm_kernel<MathF64, CfgU, 0, 0, 1, 4>), dim3(l.total),
+    hipLaunchKernelGGL((zgemm_kernel<MathF64, CfgU, 0, 0, 1, 3>), dim3(l.total),
                        dim3(CfgU::kThreads), 0, s, l);
     return hipGetLastError();
   }
