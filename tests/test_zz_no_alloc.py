@@ -61,6 +61,21 @@ def test_noalloc_equals_zinv_two_calls_second_smaller(ctx):
             assert err < 1e-12, (b, e, err)
 
 
+def test_noalloc_equals_zinv_one_launch_sizes(ctx):
+    """Up to 128 rows both entry points take the one-launch inverse (no
+    scratch at all); two calls in a row, the second smaller."""
+    for seed, b, batch in ((21, 128, 5), (22, 100, 7), (23, 64, 3), (24, 17, 2)):
+        print("zinv_noalloc case: seed %d b %d batch %d" % (seed, b, batch), flush=True)
+        A = _batch(seed, b, batch)
+        x1, x2, i1, i2 = _both(ctx, A)
+        assert np.all(i1 == 0) and np.all(i2 == 0)
+        assert np.array_equal(x1.view(np.float64), x2.view(np.float64)), (b, batch)
+        ref = np.linalg.inv(A)
+        for e in range(batch):
+            err = np.linalg.norm(x2[e] - ref[e]) / np.linalg.norm(ref[e])
+            assert err < 1e-12, (b, e, err)
+
+
 def _work_bytes(b, batch):
     """Scratch bytes of one call, as the header states them."""
     up = lambda x: (x + 255) // 256 * 256
