@@ -334,11 +334,13 @@ qtx_status qtx_rgf_zinv(qtx_rgf_ctx* ctx, int32_t b, void* A, void* X,
  *   - the call is asynchronous: it returns once the kernels are queued on
  *     the context's stream, and the results are ready when that stream's
  *     work is complete (no wait inside, so it can be captured);
- *   - batch * (2*16 + 2*w) * 16 * b bytes of panel buffers (w = 64 for
- *     b <= 256, else 256) plus 8 * batch * b bytes of pivot bookkeeping (each
- *     part rounded up to 256 bytes) must fit QTX_NOALLOC_SCRATCH_BYTES; larger
- *     calls return QTX_ERR_INVALID_ARG with the sizes in qtx_rgf_last_error
- *     (e.g. at most 102 matrices of 256, 15 of 512, 7 of 1024); b <= 1024.
+ *   - for b > 128, batch * (2*16 + 2*w) * 16 * b bytes of panel buffers
+ *     (w = 64 for b <= 256, else 256) plus 8 * batch * b bytes of pivot
+ *     bookkeeping (each part rounded up to 256 bytes) must fit
+ *     QTX_NOALLOC_SCRATCH_BYTES; larger calls return QTX_ERR_INVALID_ARG with
+ *     the sizes in qtx_rgf_last_error (e.g. at most 102 matrices of 256, 15
+ *     of 512, 7 of 1024); b <= 1024.  Up to b = 128 the inverse is one launch
+ *     that uses no work buffers, so any batch is accepted.
  * All calls on one GPU share its array, which keeps the last call's contents
  * (nothing in it needs to start at zero): calls that overlap in time on one
  * GPU race on it and must be serialised by the caller (one stream, or

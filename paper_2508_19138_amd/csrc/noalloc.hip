@@ -138,6 +138,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 }  // namespace
 
 size_t noalloc_work_bytes(int b, int batch) {
+  if (b <= kSmallB) return 0;          // the one-launch inverse uses no work buffers
   const size_t pan = align256((size_t)batch * b * kPanel * 16);
   const size_t span = align256((size_t)batch * b * inv_span(b) * 16);
   const size_t ints = align256((size_t)batch * b * 4);

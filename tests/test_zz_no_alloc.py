@@ -63,8 +63,9 @@ def test_noalloc_equals_zinv_two_calls_second_smaller(ctx):
 
 def test_noalloc_equals_zinv_one_launch_sizes(ctx):
     """Up to 128 rows both entry points take the one-launch inverse (no
-    scratch at all); two calls in a row, the second smaller."""
-    for seed, b, batch in ((21, 128, 5), (22, 100, 7), (23, 64, 3), (24, 17, 2)):
+    scratch at all, so a batch far beyond what the panel buffers would allow
+    is accepted); calls in a row, each smaller than the one before."""
+    for seed, b, batch in ((21, 128, 700), (22, 100, 7), (23, 64, 3), (24, 17, 2)):
         print("zinv_noalloc case: seed %d b %d batch %d" % (seed, b, batch), flush=True)
         A = _batch(seed, b, batch)
         x1, x2, i1, i2 = _both(ctx, A)
@@ -72,8 +73,10 @@ def test_noalloc_equals_zinv_one_launch_sizes(ctx):
         assert np.array_equal(x1.view(np.float64), x2.view(np.float64)), (b, batch)
         ref = np.linalg.inv(A)
         for e in range(batch):
+            # the rounding bound of every inverse test: 1e-15 * cond_1 * b
+            cond = np.linalg.norm(A[e], 1) * np.linalg.norm(ref[e], 1)
             err = np.linalg.norm(x2[e] - ref[e]) / np.linalg.norm(ref[e])
-            assert err < 1e-12, (b, e, err)
+            assert err < 1e-15 * cond * b + 1e-13, (b, e, err, cond)
 
 
 def _work_bytes(b, batch):
