@@ -659,13 +659,12 @@ void gj_permute_kernel(FlatLaunch L) {
 // holding column k + 1 updates that column first, searches it for the next
 // pivot row (a maximum over the column's 16 lanes) and publishes the
 // column and the reciprocal of its pivot, which overlaps the other waves'
-// updates.  The tile shape keeps
-// what each lane reads per column to 4 pivot-row entries and TR column
-// entries.  (Measured slower: a 16-column panel eliminated inside one wave
-// with the other columns updated once per panel, where the other waves
-// idle while the panel's columns go one after the other; and the winner's
-// reciprocal taken by readlane from every lane's own candidate, which
-// lengthens the search.)
+// updates.  The tile shape keeps what each lane reads per column to 4
+// pivot-row entries and TR column entries.  (Measured slower: a 16-column
+// panel eliminated inside one wave with the other columns updated once per
+// panel, where the other waves idle while the panel's columns go one after
+// the other; and the winner's reciprocal taken by readlane from every
+// lane's own candidate, which lengthens the search.)
 //
 // Pivot rows are left unscaled until all columns are done (as in the panel
 // kernel), and each eliminated column holds +g_r with -1 on its pivot row,
