@@ -493,9 +493,11 @@ qtx_status qtx_rgf_zinv(qtx_rgf_ctx* c, int32_t b, void* A, void* X, int32_t* in
   void* work = nullptr;
   try {
     HIPCHK(c, hipSetDevice(c->device));
-    const size_t pan = (size_t)batch * b * kPanel * 16;
-    const size_t span = (size_t)batch * b * inv_span(b) * 16;
-    const size_t ints = (size_t)batch * b * 4;
+    // (the one-launch inverse for b <= kSmallB uses no work buffers)
+    const bool small = b <= kSmallB;
+    const size_t pan = small ? 0 : (size_t)batch * b * kPanel * 16;
+    const size_t span = small ? 0 : (size_t)batch * b * inv_span(b) * 16;
+    const size_t ints = small ? 0 : (size_t)batch * b * 4;
     HIPCHK(c, hipMalloc(&work, 2 * pan + 2 * span + 2 * ints + 4096));
     Lane L;
     InvDesc d{};
