@@ -101,6 +101,11 @@ def parse():
                     help="uneven: solve each wave this many times and time the last "
                          "(repeated batches replay captured graphs, as in a "
                          "self-consistent loop that re-solves the same shapes)")
+    ap.add_argument("--order", default="cost", choices=["given", "length", "cost"],
+                    help="uneven: order of the solves before they are cut into memory waves: "
+                         "as drawn, by block count (longest chains first) or by flops "
+                         "(most expensive first, the default: waves of similar solves end "
+                         "with shorter tails)")
     ap.add_argument("--wave-gib", type=float, default=140.0,
                     help="uneven: device memory for the inputs/outputs of one wave")
     ap.add_argument("--requests", type=int, default=1000, help="serve: requests per rate")
@@ -530,8 +535,12 @@ def run_uneven(args):
         if not specs:
             raise SystemExit("no solve of block size %d in the workload" % args.only_b)
     cap = int(args.wave_gib * 2 ** 30)
-    waves = _waves(specs, cap)
     flops = {id(sp): _spec_flops(Q, sp) for sp in specs}
+    if args.order == "length":
+        specs = sorted(specs, key=lambda sp: -sp["n"])
+    elif args.order == "cost":
+        specs = sorted(specs, key=lambda sp: -flops[id(sp)])
+    waves = _waves(specs, cap)
     ws = int(args.ws_gib * 2 ** 30)
     # without --repeat every wave is a different batch: no launch segment
     # repeats, so graph capture (done on a segment's second sight) would only
@@ -603,7 +612,7 @@ def run_uneven(args):
                                "batches in %d memory waves"
                                % (n_sol, "{%d}" % args.only_b if args.only_b
                                   else "{64,128,256,384,512,768}", len(waves)),
-                   "solves": n_sol, "waves": len(waves), "seed": args.seed,
+                   "solves": n_sol, "waves": len(waves), "order": args.order, "seed": args.seed,
                    "timed_solve_of_each_wave": args.repeat},
         "merged": {"s": round(t_merged, 3), "energy_points_per_s": round(n_sol / t_merged, 3),
                    "tflops": round(tf_total / t_merged / 1e12, 3),
