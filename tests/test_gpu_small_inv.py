@@ -4,7 +4,8 @@ matrix held in registers).  The batched inverse against numpy at sizes on
 either side of its 64- and 128-row forms (and 129, the first size of the
 blocked path), the exact status of a zero and of a non-finite column, bits
 that do not depend on the batch, and RGF solves at b = 128 against the
-oracle (Sec. 3.2.3 recursion; Eq. system-solve definition)."""
+oracle, G-type and W-type with W^R (Sec. 3.2.3 recursion; Eq. system-solve
+definition)."""
 
 import numpy as np
 import pytest
@@ -150,3 +151,36 @@ def test_small_block_solve_matches_oracle(ctx, n, b, n_e, bt):
             sel = tuple(None if t is None else t[e] for t in got)
             err = triple_err(sel, ref)
             assert err < TOL, (e, err)
+
+
+def test_small_block_w_type_solve(ctx):
+    """W-type (I - V P^R) at b = 128, with W^R_ii: the assembly products, the
+    solve on the one-launch inverse and the retarded screened interaction."""
+    from oracle import assemble_w, w_retarded_diag
+    from blockcmp import max_rel_err
+    gh = _gh()
+    n, b = 4, 128
+    E = np.array([0.4, -0.9])
+    p = synth.w_problem(31, n, b, E)
+    V = (gh.dev(p["V"][0]), gh.dev(p["V"][1]), None)
+    Pr = tuple(gh.dev(t) for t in p["P_r"])
+    Pl = (gh.dev(p["P_l"][0]), gh.dev(p["P_l"][1]), None)
+    Pg = (gh.dev(p["P_g"][0]), gh.dev(p["P_g"][1]), None)
+    n_e = E.shape[0]
+    XR, XL, XG = gh.outputs(n_e, n, b), gh.outputs(n_e, n, b), gh.outputs(n_e, n, b)
+    WR = gh.empty((n_e, n, b, b))
+    prob = Q.make_w_problem(V, Pr, Pl, Pg, XR, XL, XG, WR)
+    torch.cuda.synchronize()
+    print("W solve n %d b %d energies %d" % (n, b, n_e), flush=True)
+    ctx.solve_batch([prob])
+    torch.cuda.synchronize()
+    assert prob.status == 0
+    hR, hL, hG = gh.host(XR), gh.host(XL), gh.host(XG)
+    for e in range(n_e):
+        A, Bs = assemble_w(p["V"], tuple(t[e] for t in p["P_r"]),
+                           [tuple(t[e] for t in p["P_l"]), tuple(t[e] for t in p["P_g"])])
+        OR, (OL, OG) = rgf_selected(A, Bs)
+        for got, ref in ((hR, OR), (hL, OL), (hG, OG)):
+            sel = tuple(None if t is None else t[e] for t in got)
+            assert triple_err(sel, ref) < TOL, e
+        assert max_rel_err(WR.cpu().numpy()[e], w_retarded_diag(OR, p["V"])) < TOL
