@@ -22,6 +22,7 @@ namespace {
 // complex64 on the way into LDS and accumulates in FP32, while the epilogue
 // (alpha, beta, C) stays FP64.
 struct MathF64 {
+  static constexpr bool kDirect = true;
   typedef double2 lds_t;
   typedef d4v acc_t;
   typedef double real_t;
@@ -32,6 +33,7 @@ struct MathF64 {
   static __device__ __forceinline__ int row(int r, int lk) { return 4 * r + lk; }
 };
 struct MathF32 {
+  static constexpr bool kDirect = false;
   typedef float2 lds_t;
   typedef f4v acc_t;
   typedef float real_t;
@@ -106,6 +108,45 @@ __device__ __forceinline__ void tile_index(int q, int& w, int& k) {
   }
 }
 
+// Direct layout of an FP64 operand tile (the slot of each element in LDS).
+// A k-major tile (BK rows k of BW consecutive elements) is stored as read.
+// A row-major tile (BW rows w of BK consecutive k) permutes the k slots of
+// row w by XOR with (w / rows per 256 bytes) % BK, so that the 16 lanes that
+// read 16 consecutive rows at one k hit distinct banks; the lanes that fill
+// a row still read its contiguous segment of HBM.  swz_slot gives the slot
+// of (w, k), slot_elem the element of slot s (the XOR is its own inverse).
+template <int BK>
+__device__ __forceinline__ int swz_slot(int w, int k) {
+  static_assert((BK & (BK - 1)) == 0, "the XOR permutation needs a power-of-two BK");
+  constexpr int kRPB = 16 * BK >= 256 ? 1 : 256 / (16 * BK);
+  return w * BK + (k ^ ((w / kRPB) % BK));
+}
+template <int BK, int BW, int TRANS>
+__device__ __forceinline__ void slot_elem(int s, int& w, int& k) {
+  if (TRANS) {
+    constexpr int kRPB = 16 * BK >= 256 ? 1 : 256 / (16 * BK);
+    w = s / BK;
+    k = (s % BK) ^ ((w / kRPB) % BK);
+  } else {
+    k = s / BW;
+    w = s % BW;
+  }
+}
+template <bool DL, int BK, int BW, int TRANS>
+__device__ __forceinline__ void tile_elem(int q, int& w, int& k) {
+  if (DL) slot_elem<BK, BW, TRANS>(q, w, k);
+  else tile_index<BK, BW, TRANS>(q, w, k);
+}
+
+// One complex from HBM into LDS without registers (global_load_lds_dwordx4):
+// the lane's 16 bytes land at lds_wave + 16 * (lane index), lds_wave being
+// the same for the whole wave.  Completion is counted by vmcnt.
+__device__ __forceinline__ void lds_dma16(const double2* src, double2* lds_wave) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                   (__attribute__((address_space(3))) void*)lds_wave, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_dma_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // CM = 4: each complex product is four real products,
 //     Cr += ar br - ai bi,  Ci += ar bi + ai br;
 // CM = 3: three (the 3M form), accumulated separately and combined in the
@@ -126,14 +167,32 @@ void zgemm_kernel(FlatLaunch L) {
   typedef typename P::acc_t Acc;
   typedef typename P::real_t R;
   constexpr int BM = T::BM, BN = T::BN, BK = T::BK, WGN = T::WGN;
-  // Each operand tile keeps the layout in which it arrives from HBM, so the
-  // LDS stores are contiguous: A (row = m) and B^dagger (row = n) are stored
-  // row-major with pitch BK+1, A^dagger and B (row = k) k-major with pitch
-  // BM+1 / BN+1.  The pitches make the 16-lane fragment reads conflict-free.
-  __shared__ Lt As[2][T::kSzA];
-  __shared__ Lt Bs[2][T::kSzB];
-  auto ia = [](int k, int m) { return OPA == 0 ? m * (BK + 1) + k : k * (BM + 1) + m; };
-  auto ib = [](int k, int n) { return OPB == 1 ? n * (BK + 1) + k : k * (BN + 1) + n; };
+  // Each operand tile keeps the layout in which it arrives from HBM: A
+  // (row = m) and B^dagger (row = n) row-major, A^dagger and B (row = k)
+  // k-major.
+  // FP64 (kDL): whole tiles go from HBM straight into LDS, one complex per
+  // lane, without passing through registers (see slot_elem); the layout is
+  // unpadded and the row-major tiles permute the k slots of each row.  The
+  // adjoint operands are conjugated as their fragments are read.  Tiles
+  // that cross the edge of a matrix load through registers into the same
+  // layout, with zeros outside.
+  // FP32: values are rounded on the way through registers, conjugated there,
+  // and stored with pitches BK+1 / BM+1 / BN+1, which make the 16-lane
+  // fragment reads conflict-free.
+  constexpr bool kDL = P::kDirect;
+  // The two buffers of each operand are separate arrays: the compiler can
+  // then tell a read of one buffer from the direct loads into the other and
+  // does not make the read wait for them.
+  __shared__ Lt As0[kDL ? BM * BK : T::kSzA], As1[kDL ? BM * BK : T::kSzA];
+  __shared__ Lt Bs0[kDL ? BN * BK : T::kSzB], Bs1[kDL ? BN * BK : T::kSzB];
+  auto ia = [](int k, int m) {
+    if (kDL) return OPA == 0 ? swz_slot<BK>(m, k) : k * BM + m;
+    return OPA == 0 ? m * (BK + 1) + k : k * (BM + 1) + m;
+  };
+  auto ib = [](int k, int n) {
+    if (kDL) return OPB == 1 ? swz_slot<BK>(n, k) : k * BN + n;
+    return OPB == 1 ? n * (BK + 1) + k : k * (BN + 1) + n;
+  };
 
   const int w = xcd_remap(blockIdx.x, gridDim.x);
   const int di = find_desc(L.prefix, L.nd, w);
@@ -167,7 +226,7 @@ void zgemm_kernel(FlatLaunch L) {
       for (int r = 0; r < T::kALoads; ++r) {
         const int q = tid + r * T::kThreads;
         int m, k;
-        tile_index<BK, BM, OPA == 0>(q, m, k);
+        tile_elem<kDL, BK, BM, OPA == 0>(q, m, k);
         const int gm = m0 + m, gk = k0 + k;
         ra[r] = (OPA == 0) ? A[(long long)gm * lda + gk] : A[(long long)gk * lda + gm];
       }
@@ -175,7 +234,7 @@ void zgemm_kernel(FlatLaunch L) {
       for (int r = 0; r < T::kBLoads; ++r) {
         const int q = tid + r * T::kThreads;
         int n, k;
-        tile_index<BK, BN, OPB == 1>(q, n, k);
+        tile_elem<kDL, BK, BN, OPB == 1>(q, n, k);
         const int gn = n0 + n, gk = k0 + k;
         rb[r] = (OPB == 0) ? B[(long long)gk * ldb + gn] : B[(long long)gn * ldb + gk];
       }
@@ -185,7 +244,7 @@ void zgemm_kernel(FlatLaunch L) {
     for (int r = 0; r < T::kALoads; ++r) {
       const int q = tid + r * T::kThreads;
       int m, k;
-      tile_index<BK, BM, OPA == 0>(q, m, k);
+      tile_elem<kDL, BK, BM, OPA == 0>(q, m, k);
       const int gm = m0 + m, gk = k0 + k;
       double2 v = make_double2(0.0, 0.0);
       if (gm < M && gk < K)
@@ -196,7 +255,7 @@ void zgemm_kernel(FlatLaunch L) {
     for (int r = 0; r < T::kBLoads; ++r) {
       const int q = tid + r * T::kThreads;
       int n, k;
-      tile_index<BK, BN, OPB == 1>(q, n, k);
+      tile_elem<kDL, BK, BN, OPB == 1>(q, n, k);
       const int gn = n0 + n, gk = k0 + k;
       double2 v = make_double2(0.0, 0.0);
       if (gn < N && gk < K)
@@ -209,19 +268,19 @@ void zgemm_kernel(FlatLaunch L) {
     for (int r = 0; r < T::kALoads; ++r) {
       const int q = tid + r * T::kThreads;
       int m, k;
-      tile_index<BK, BM, OPA == 0>(q, m, k);
+      tile_elem<kDL, BK, BM, OPA == 0>(q, m, k);
       Lt v = P::cvt(ra[r]);
-      if (OPA == 1) v.y = -v.y;
-      As[buf][ia(k, m)] = v;
+      if (!kDL && OPA == 1) v.y = -v.y;
+      (buf ? As1 : As0)[kDL ? q : ia(k, m)] = v;
     }
 #pragma unroll
     for (int r = 0; r < T::kBLoads; ++r) {
       const int q = tid + r * T::kThreads;
       int n, k;
-      tile_index<BK, BN, OPB == 1>(q, n, k);
+      tile_elem<kDL, BK, BN, OPB == 1>(q, n, k);
       Lt v = P::cvt(rb[r]);
-      if (OPB == 1) v.y = -v.y;
-      Bs[buf][ib(k, n)] = v;
+      if (!kDL && OPB == 1) v.y = -v.y;
+      (buf ? Bs1 : Bs0)[kDL ? q : ib(k, n)] = v;
     }
   };
 
@@ -256,22 +315,46 @@ void zgemm_kernel(FlatLaunch L) {
                                                    : make_double2(0.0, 0.0);
         }
   }
-  const int nk = (K + BK - 1) / BK;
-  load_tiles(0);
-  store_tiles(0);
-  __syncthreads();
+  // whole FP64 tiles: every lane of a wave instruction reads one complex
+  // from HBM into the next 16-byte slot after the wave's base in LDS
+  auto dma_tiles = [&](int k0, Lt* as, Lt* bs) __attribute__((always_inline)) {
+    if constexpr (kDL) {
+#pragma unroll
+    for (int r = 0; r < T::kALoads; ++r) {
+      const int q = tid + r * T::kThreads;
+      int m, k;
+      slot_elem<BK, BM, OPA == 0>(q, m, k);
+      const double2* src = (OPA == 0) ? A + ((long long)(m0 + m) * lda + k0 + k)
+                                      : A + ((long long)(k0 + k) * lda + m0 + m);
+      lds_dma16(src, as + r * T::kThreads + wave * 64);
+    }
+#pragma unroll
+    for (int r = 0; r < T::kBLoads; ++r) {
+      const int q = tid + r * T::kThreads;
+      int n, k;
+      slot_elem<BK, BN, OPB == 1>(q, n, k);
+      const double2* src = (OPB == 0) ? B + ((long long)(k0 + k) * ldb + n0 + n)
+                                      : B + ((long long)(n0 + n) * ldb + k0 + k);
+      lds_dma16(src, bs + r * T::kThreads + wave * 64);
+    }
+    }
+  };
   const int lrow = lane & 15, lk = lane >> 4;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+  auto compute = [&](const Lt* as, const Lt* bs) __attribute__((always_inline)) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kidx = kk * 4 + lk;
       Lt a[T::kTM], b[T::kTN];
 #pragma unroll
-      for (int i = 0; i < T::kTM; ++i) a[i] = As[buf][ia(kidx, wm * T::kWM + i * 16 + lrow)];
+      for (int i = 0; i < T::kTM; ++i) {
+        a[i] = as[ia(kidx, wm * T::kWM + i * 16 + lrow)];
+        if (kDL && OPA == 1) a[i].y = -a[i].y;
+      }
 #pragma unroll
-      for (int j = 0; j < T::kTN; ++j) b[j] = Bs[buf][ib(kidx, wn * T::kWN + j * 16 + lrow)];
+      for (int j = 0; j < T::kTN; ++j) {
+        b[j] = bs[ib(kidx, wn * T::kWN + j * 16 + lrow)];
+        if (kDL && OPB == 1) b[j].y = -b[j].y;
+      }
       if (CM == 3) {
         R as[T::kTM], bs[T::kTN];
 #pragma unroll
@@ -300,8 +383,38 @@ void zgemm_kernel(FlatLaunch L) {
         }
       }
     }
-    if (kt + 1 < nk) store_tiles(buf ^ 1);
+  };
+  const int nk = (K + BK - 1) / BK;
+  // separate loops: in the direct one nothing waits for the next tile's
+  // loads before the products of this one
+  if (kDL && full) {
+    // two k tiles per trip, so that every access names its buffer statically
+    dma_tiles(0, As0, Bs0);
+    lds_dma_wait();
     __syncthreads();
+    int kt = 0;
+    for (; kt + 1 < nk; kt += 2) {           // tile kt is in buffer 0
+      dma_tiles((kt + 1) * BK, As1, Bs1);
+      compute(As0, Bs0);
+      lds_dma_wait();
+      __syncthreads();
+      if (kt + 2 < nk) dma_tiles((kt + 2) * BK, As0, Bs0);
+      compute(As1, Bs1);
+      lds_dma_wait();
+      __syncthreads();
+    }
+    if (kt < nk) compute(As0, Bs0);          // an odd last tile
+  } else {
+    load_tiles(0);
+    store_tiles(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+      compute(buf ? As1 : As0, buf ? Bs1 : Bs0);
+      if (kt + 1 < nk) store_tiles(buf ^ 1);
+      __syncthreads();
+    }
   }
 
   // epilogue: D = alpha * acc + beta * C
