@@ -50,11 +50,11 @@ HBM_PEAK_GBS = 8000.0
 # --pmc FETCH_SIZE and WRITE_SIZE runs of this default workload (the
 # recursion's real launch mix, 810 product launches), each scaled by the
 # same counter on a 1 GiB device copy in the same run (FETCH_SIZE reads 0.500
-# of the copied bytes, WRITE_SIZE 1.000): 1608419 KiB x 2 read + 968314 KiB
+# of the copied bytes, WRITE_SIZE 1.000): 1618018 KiB x 2 read + 968317 KiB
 # written per launch against 3.3445e9 algorithmic bytes (A, B, D, and C or
-# the assembled C's sources).  None once the
-# kernel changes.
-MEASURED_TRAFFIC_FACTOR = None   # the kernel's operand staging changed after the last counter runs
+# the assembled C's sources).  Taken on the kernel whose operand tiles go
+# from HBM straight into LDS; None once the kernel changes.
+MEASURED_TRAFFIC_FACTOR = (1618018.0 * 2.0 + 968317.0) * 1024.0 / 3344506940.68
 
 
 def parse():

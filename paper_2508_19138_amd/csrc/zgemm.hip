@@ -2,7 +2,8 @@
 //
 // A workgroup computes one BM x BN tile of D for one matrix of one
 // descriptor.  Operand tiles are staged through LDS in the layout in which
-// they are read from HBM (see zgemm_kernel) and double buffered.  Complex
+// they are read from HBM, double buffered; FP64 tiles go from HBM straight
+// into LDS without passing through registers (see zgemm_kernel).  Complex
 // numbers stay interleaved (re, im): each lane reads one complex per
 // fragment.  FP64 products take three real MFMAs per complex product (the
 // 3M form, see zgemm_kernel); FP32 products four,
@@ -11,7 +12,8 @@
 // supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register r of lane l
 // holds D[4r + l/16][l%16] for f64 and D[4(l/16) + r][l%16] for f32.
 // Conjugate-transposed operands are read with the transposed global index
-// and conjugated on the way into LDS.  Workgroup ids are remapped so that
+// and conjugated as their fragments are read from LDS (FP64) or on the way
+// into LDS (FP32).  Workgroup ids are remapped so that
 // the tiles of one matrix land on the same XCD (shared L2).
 #include "qtx_internal.h"
 
