@@ -11,7 +11,9 @@ size so the wide tile runs in every operand orientation, and check:
   back to the 32x32 tile) give identical bits: the tile does not change the
   result;
 * the product kernel alone at 512^3 x 16 in all four orientations, with the
-  128x64 tile and the two smaller ones, against NumPy.
+  128x64 tile and the two smaller ones, against NumPy;
+* the same products with edge tiles in m, n and k (loaded through registers)
+  give the bits of whole tiles (loaded straight into LDS).
 """
 
 import numpy as np
@@ -120,6 +122,53 @@ def test_zgemm_512_batch16_matches_numpy(ctx, monkeypatch, cfg, opa, opb):
               dD, b, b * b, batch)
     monkeypatch.delenv("QTX_GEMM_CFG")
     D = dD.cpu().numpy()
+    opA = A if opa == "N" else np.conj(np.swapaxes(A, 1, 2))
+    opB = B if opb == "N" else np.conj(np.swapaxes(B, 1, 2))
+    ref = alpha * (opA @ opB) + beta * C
+    err = np.linalg.norm(D - ref, axis=(1, 2)) / np.linalg.norm(ref, axis=(1, 2))
+    assert err.max() < 1e-14, err.max()
+
+
+@pytest.mark.parametrize("cfg", ["1", "0", "2"])
+@pytest.mark.parametrize("opa,opb", [("N", "N"), ("N", "C"), ("C", "N"), ("C", "C")])
+def test_zgemm_edge_tiles_give_the_bits_of_whole_tiles(ctx, monkeypatch, cfg, opa, opb):
+    """Tiles inside the matrices load their operands from HBM straight into
+    LDS; tiles that cross an edge (in m, n or k) load through registers with
+    zeros outside.  Both fill the same layout and sum over k in the same
+    order, so a product whose operands are zero past k = 509 gives the same
+    bits computed as 512^3 (every tile whole), as 500 x 497 x 512 (edge tiles
+    in m and n) and as 512 x 512 x 509 (every tile ragged in k)."""
+    b, batch, kk, mm, nn = 512, 16, 509, 500, 497
+    rng = np.random.default_rng(3 + ord(opa) + 5 * ord(opb))
+    A = synth.cn(rng, (batch, b, b), 1.0)
+    B = synth.cn(rng, (batch, b, b), 1.0)
+    C = synth.cn(rng, (batch, b, b), 1.0)
+    # zero the operands past k = kk (A is m x k stored, or k x m for "C")
+    if opa == "N":
+        A[:, :, kk:] = 0
+    else:
+        A[:, kk:, :] = 0
+    if opb == "N":
+        B[:, kk:, :] = 0
+    else:
+        B[:, :, kk:] = 0
+    dA, dB, dC = (torch.from_numpy(x).to(DEV) for x in (A, B, C))
+    alpha, beta = 0.6 + 0.3j, -1.0 + 0.5j
+    monkeypatch.setenv("QTX_GEMM_CFG", cfg)
+    outs = []
+    for m, n, k in ((b, b, b), (mm, nn, b), (b, b, kk)):
+        dD = torch.zeros((batch, b, b), dtype=torch.complex128, device=DEV)
+        print("zgemm %s%s cfg %s %d x %d x %d" % (opa, opb, cfg, m, n, k), flush=True)
+        ctx.zgemm(opa, opb, m, n, k, alpha, dA, b, b * b, dB, b, b * b, beta, dC, b, b * b,
+                  dD, b, b * b, batch)
+        outs.append(dD)
+    monkeypatch.delenv("QTX_GEMM_CFG")
+    torch.cuda.synchronize()
+    whole, edge, ragk = outs
+    assert torch.equal(edge[:, :mm, :nn], whole[:, :mm, :nn])
+    assert torch.count_nonzero(edge[:, mm:, :]) == 0 and torch.count_nonzero(edge[:, :, nn:]) == 0
+    assert torch.equal(ragk, whole)
+    D = whole.cpu().numpy()
     opA = A if opa == "N" else np.conj(np.swapaxes(A, 1, 2))
     opB = B if opb == "N" else np.conj(np.swapaxes(B, 1, 2))
     ref = alpha * (opA @ opB) + beta * C
