@@ -295,7 +295,8 @@ qtx_status qtx_rgf_zgemm(qtx_rgf_ctx* ctx, char opa, char opb, int32_t m,
                          int64_t sD, int32_t batch);
 
 /* The same product computed on the FP32 matrix cores, as QTX_MIXED uses it:
- * the complex128 operands are rounded to complex64 when staged, products
+ * the complex128 operands are rounded to complex64 as they are read from
+ * on-chip memory into the matrix cores, products
  * accumulate in FP32, and the epilogue (alpha, beta, C, D) is complex128.
  * Arguments as for qtx_rgf_zgemm. */
 qtx_status qtx_rgf_cgemm(qtx_rgf_ctx* ctx, char opa, char opb, int32_t m,

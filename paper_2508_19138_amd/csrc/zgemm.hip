@@ -2,7 +2,7 @@
 //
 // A workgroup computes one BM x BN tile of D for one matrix of one
 // descriptor.  Operand tiles are staged through LDS in the layout in which
-// they are read from HBM, double buffered; FP64 tiles go from HBM straight
+// they are read from HBM, double buffered; whole tiles go from HBM straight
 // into LDS without passing through registers (see zgemm_kernel).  Complex
 // numbers stay interleaved (re, im): each lane reads one complex per
 // fragment.  FP64 products take three real MFMAs per complex product (the
@@ -12,17 +12,16 @@
 // supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register r of lane l
 // holds D[4r + l/16][l%16] for f64 and D[4(l/16) + r][l%16] for f32.
 // Conjugate-transposed operands are read with the transposed global index
-// and conjugated as their fragments are read from LDS (FP64) or on the way
-// into LDS (FP32).  Workgroup ids are remapped so that
-// the tiles of one matrix land on the same XCD (shared L2).
+// and conjugated as their fragments are read from LDS.  Workgroup ids are
+// remapped so that the tiles of one matrix land on the same XCD (shared L2).
 #include "qtx_internal.h"
 
 namespace qtx {
 namespace {
 
-// Operands live in HBM as complex128; the FP32 variant rounds them to
-// complex64 on the way into LDS and accumulates in FP32, while the epilogue
-// (alpha, beta, C) stays FP64.
+// Operands live in HBM (and LDS) as complex128; the FP32 variant rounds them
+// to complex64 as the fragments are read and accumulates in FP32, while the
+// epilogue (alpha, beta, C) stays FP64.
 struct MathF64 {
   static constexpr bool kDirect = true;
   typedef double2 lds_t;
@@ -35,7 +34,7 @@ struct MathF64 {
   static __device__ __forceinline__ int row(int r, int lk) { return 4 * r + lk; }
 };
 struct MathF32 {
-  static constexpr bool kDirect = false;
+  static constexpr bool kDirect = true;
   typedef float2 lds_t;
   typedef f4v acc_t;
   typedef float real_t;
@@ -72,7 +71,7 @@ struct Cfg {
 // four-product form (FP32's 3M form measured 4x less accurate in the
 // partitioned solve).
 typedef Cfg<64, 64, 8, 2, 2> Cfg0;      // general, 3M: 32 x 32 per wave, three waves per SIMD
-typedef Cfg<64, 64, 16, 2, 2> Cfg0w;    // general, four products
+typedef Cfg<64, 64, 8, 2, 2> Cfg0w;     // general, four products
 typedef Cfg<128, 64, 8, 4, 2> Cfg1;    // large blocks, 3M: eight waves of 32 x 32
 typedef Cfg<128, 64, 8, 2, 2> Cfg1w;   // large blocks, four products: 64 x 32 per wave
 typedef Cfg<32, 32, 16, 2, 2> Cfg2;     // small blocks
@@ -110,7 +109,7 @@ __device__ __forceinline__ void tile_index(int q, int& w, int& k) {
   }
 }
 
-// Direct layout of an FP64 operand tile (the slot of each element in LDS).
+// Direct layout of an operand tile (the slot of each element in LDS).
 // A k-major tile (BK rows k of BW consecutive elements) is stored as read.
 // A row-major tile (BW rows w of BK consecutive k) permutes the k slots of
 // row w by XOR with (w / rows per 256 bytes) % BK, so that the 16 lanes that
@@ -172,21 +171,22 @@ void zgemm_kernel(FlatLaunch L) {
   // Each operand tile keeps the layout in which it arrives from HBM: A
   // (row = m) and B^dagger (row = n) row-major, A^dagger and B (row = k)
   // k-major.
-  // FP64 (kDL): whole tiles go from HBM straight into LDS, one complex per
-  // lane, without passing through registers (see slot_elem); the layout is
+  // Whole tiles go from HBM straight into LDS, one complex128 per lane,
+  // without passing through registers (see slot_elem); the layout is
   // unpadded and the row-major tiles permute the k slots of each row.  The
-  // adjoint operands are conjugated as their fragments are read.  Tiles
-  // that cross the edge of a matrix load through registers into the same
-  // layout, with zeros outside.
-  // FP32: values are rounded on the way through registers, conjugated there,
-  // and stored with pitches BK+1 / BM+1 / BN+1, which make the 16-lane
-  // fragment reads conflict-free.
+  // adjoint operands are conjugated, and FP32 operands rounded to complex64,
+  // as their fragments are read.  Tiles that cross the edge of a matrix load
+  // through registers into the same layout, with zeros outside.
+  // (kDL = false keeps a register-staged form: values rounded and
+  // conjugated on the way into LDS, stored with pitches BK+1 / BM+1 / BN+1,
+  // which make the 16-lane fragment reads conflict-free.)
   constexpr bool kDL = P::kDirect;
+  typedef typename std::conditional<kDL, double2, Lt>::type St;   // LDS element
   // The two buffers of each operand are separate arrays: the compiler can
   // then tell a read of one buffer from the direct loads into the other and
   // does not make the read wait for them.
-  __shared__ Lt As0[kDL ? BM * BK : T::kSzA], As1[kDL ? BM * BK : T::kSzA];
-  __shared__ Lt Bs0[kDL ? BN * BK : T::kSzB], Bs1[kDL ? BN * BK : T::kSzB];
+  __shared__ St As0[kDL ? BM * BK : T::kSzA], As1[kDL ? BM * BK : T::kSzA];
+  __shared__ St Bs0[kDL ? BN * BK : T::kSzB], Bs1[kDL ? BN * BK : T::kSzB];
   auto ia = [](int k, int m) {
     if (kDL) return OPA == 0 ? swz_slot<BK>(m, k) : k * BM + m;
     return OPA == 0 ? m * (BK + 1) + k : k * (BM + 1) + m;
@@ -271,18 +271,26 @@ void zgemm_kernel(FlatLaunch L) {
       const int q = tid + r * T::kThreads;
       int m, k;
       tile_elem<kDL, BK, BM, OPA == 0>(q, m, k);
-      Lt v = P::cvt(ra[r]);
-      if (!kDL && OPA == 1) v.y = -v.y;
-      (buf ? As1 : As0)[kDL ? q : ia(k, m)] = v;
+      if constexpr (kDL) {
+        (buf ? As1 : As0)[q] = ra[r];
+      } else {
+        Lt v = P::cvt(ra[r]);
+        if (OPA == 1) v.y = -v.y;
+        (buf ? As1 : As0)[ia(k, m)] = v;
+      }
     }
 #pragma unroll
     for (int r = 0; r < T::kBLoads; ++r) {
       const int q = tid + r * T::kThreads;
       int n, k;
       tile_elem<kDL, BK, BN, OPB == 1>(q, n, k);
-      Lt v = P::cvt(rb[r]);
-      if (!kDL && OPB == 1) v.y = -v.y;
-      (buf ? Bs1 : Bs0)[kDL ? q : ib(k, n)] = v;
+      if constexpr (kDL) {
+        (buf ? Bs1 : Bs0)[q] = rb[r];
+      } else {
+        Lt v = P::cvt(rb[r]);
+        if (OPB == 1) v.y = -v.y;
+        (buf ? Bs1 : Bs0)[ib(k, n)] = v;
+      }
     }
   };
 
@@ -319,7 +327,7 @@ void zgemm_kernel(FlatLaunch L) {
   }
   // whole FP64 tiles: every lane of a wave instruction reads one complex
   // from HBM into the next 16-byte slot after the wave's base in LDS
-  auto dma_tiles = [&](int k0, Lt* as, Lt* bs) __attribute__((always_inline)) {
+  auto dma_tiles = [&](int k0, St* as, St* bs) __attribute__((always_inline)) {
     if constexpr (kDL) {
 #pragma unroll
     for (int r = 0; r < T::kALoads; ++r) {
@@ -342,19 +350,21 @@ void zgemm_kernel(FlatLaunch L) {
     }
   };
   const int lrow = lane & 15, lk = lane >> 4;
-  auto compute = [&](const Lt* as, const Lt* bs) __attribute__((always_inline)) {
+  auto compute = [&](const St* as, const St* bs) __attribute__((always_inline)) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kidx = kk * 4 + lk;
       Lt a[T::kTM], b[T::kTN];
 #pragma unroll
       for (int i = 0; i < T::kTM; ++i) {
-        a[i] = as[ia(kidx, wm * T::kWM + i * 16 + lrow)];
+        if constexpr (kDL) a[i] = P::cvt(as[ia(kidx, wm * T::kWM + i * 16 + lrow)]);
+        else a[i] = as[ia(kidx, wm * T::kWM + i * 16 + lrow)];
         if (kDL && OPA == 1) a[i].y = -a[i].y;
       }
 #pragma unroll
       for (int j = 0; j < T::kTN; ++j) {
-        b[j] = bs[ib(kidx, wn * T::kWN + j * 16 + lrow)];
+        if constexpr (kDL) b[j] = P::cvt(bs[ib(kidx, wn * T::kWN + j * 16 + lrow)]);
+        else b[j] = bs[ib(kidx, wn * T::kWN + j * 16 + lrow)];
         if (kDL && OPB == 1) b[j].y = -b[j].y;
       }
       if (CM == 3) {
