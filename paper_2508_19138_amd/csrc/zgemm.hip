@@ -23,7 +23,6 @@ namespace {
 // to complex64 as the fragments are read and accumulates in FP32, while the
 // epilogue (alpha, beta, C) stays FP64.
 struct MathF64 {
-  static constexpr bool kDirect = true;
   typedef double2 lds_t;
   typedef d4v acc_t;
   typedef double real_t;
@@ -34,7 +33,6 @@ struct MathF64 {
   static __device__ __forceinline__ int row(int r, int lk) { return 4 * r + lk; }
 };
 struct MathF32 {
-  static constexpr bool kDirect = true;
   typedef float2 lds_t;
   typedef f4v acc_t;
   typedef float real_t;
@@ -55,10 +53,6 @@ struct Cfg {
   static constexpr int kWN = BN / WGN;
   static constexpr int kTM = kWM / 16;
   static constexpr int kTN = kWN / 16;
-  // LDS elements per buffer: a k-major tile [BK][BM+1] or a row-major tile
-  // [BM][BK+1], whichever the operand uses (one element of row padding)
-  static constexpr int kSzA = (BK * (BM + 1) > BM * (BK + 1)) ? BK * (BM + 1) : BM * (BK + 1);
-  static constexpr int kSzB = (BK * (BN + 1) > BN * (BK + 1)) ? BK * (BN + 1) : BN * (BK + 1);
   static constexpr int kALoads = BM * BK / kThreads;
   static constexpr int kBLoads = BN * BK / kThreads;
   static_assert(BM * BK % kThreads == 0 && BN * BK % kThreads == 0, "tile");
@@ -91,24 +85,6 @@ __device__ __forceinline__ int xcd_remap(int w, int G) {
 // TAG only separates kernel symbols (1 = rank-kPanel and rank-kSuper
 // updates of the inverse, 2 = its rank-kMega updates) so that profilers
 // report the uses apart.
-// Thread -> element maps of the operand tiles.  Tiles whose rows are
-// contiguous in HBM along the LDS minor index (A^dagger: [k][m], B: [k][n])
-// are read in 16-complex (256-byte) segments, 16 lanes per segment and four
-// rows per wave instruction; the transposed cases (A: [m][k], B^dagger:
-// [n][k]) read 16 consecutive k of one row.
-template <int BK, int BW, int TRANS>
-__device__ __forceinline__ void tile_index(int q, int& w, int& k) {
-  if (TRANS) {            // global row = w (BW of them), contiguous along k
-    w = q / BK;
-    k = q % BK;
-  } else {                // global row = k, contiguous along w
-    constexpr int SEG = BW < 16 ? BW : 16;
-    const int off = q % SEG;
-    k = (q / SEG) % BK;
-    w = (q / (SEG * BK)) * SEG + off;
-  }
-}
-
 // Direct layout of an operand tile (the slot of each element in LDS).
 // A k-major tile (BK rows k of BW consecutive elements) is stored as read.
 // A row-major tile (BW rows w of BK consecutive k) permutes the k slots of
@@ -133,12 +109,6 @@ __device__ __forceinline__ void slot_elem(int s, int& w, int& k) {
     w = s % BW;
   }
 }
-template <bool DL, int BK, int BW, int TRANS>
-__device__ __forceinline__ void tile_elem(int q, int& w, int& k) {
-  if (DL) slot_elem<BK, BW, TRANS>(q, w, k);
-  else tile_index<BK, BW, TRANS>(q, w, k);
-}
-
 // One complex from HBM into LDS without registers (global_load_lds_dwordx4):
 // the lane's 16 bytes land at lds_wave + 16 * (lane index), lds_wave being
 // the same for the whole wave.  Completion is counted by vmcnt.
@@ -177,24 +147,13 @@ void zgemm_kernel(FlatLaunch L) {
   // adjoint operands are conjugated, and FP32 operands rounded to complex64,
   // as their fragments are read.  Tiles that cross the edge of a matrix load
   // through registers into the same layout, with zeros outside.
-  // (kDL = false keeps a register-staged form: values rounded and
-  // conjugated on the way into LDS, stored with pitches BK+1 / BM+1 / BN+1,
-  // which make the 16-lane fragment reads conflict-free.)
-  constexpr bool kDL = P::kDirect;
-  typedef typename std::conditional<kDL, double2, Lt>::type St;   // LDS element
   // The two buffers of each operand are separate arrays: the compiler can
   // then tell a read of one buffer from the direct loads into the other and
   // does not make the read wait for them.
-  __shared__ St As0[kDL ? BM * BK : T::kSzA], As1[kDL ? BM * BK : T::kSzA];
-  __shared__ St Bs0[kDL ? BN * BK : T::kSzB], Bs1[kDL ? BN * BK : T::kSzB];
-  auto ia = [](int k, int m) {
-    if (kDL) return OPA == 0 ? swz_slot<BK>(m, k) : k * BM + m;
-    return OPA == 0 ? m * (BK + 1) + k : k * (BM + 1) + m;
-  };
-  auto ib = [](int k, int n) {
-    if (kDL) return OPB == 1 ? swz_slot<BK>(n, k) : k * BN + n;
-    return OPB == 1 ? n * (BK + 1) + k : k * (BN + 1) + n;
-  };
+  __shared__ double2 As0[BM * BK], As1[BM * BK];
+  __shared__ double2 Bs0[BN * BK], Bs1[BN * BK];
+  auto ia = [](int k, int m) { return OPA == 0 ? swz_slot<BK>(m, k) : k * BM + m; };
+  auto ib = [](int k, int n) { return OPB == 1 ? swz_slot<BK>(n, k) : k * BN + n; };
 
   const int w = xcd_remap(blockIdx.x, gridDim.x);
   const int di = find_desc(L.prefix, L.nd, w);
@@ -222,31 +181,13 @@ void zgemm_kernel(FlatLaunch L) {
 
   // whole tile inside the matrices: loads need no bounds checks
   const bool full = (m0 + BM <= M) && (n0 + BN <= N) && (K % BK == 0);
+  // tiles that cross an edge: through registers, zeros outside the matrices
   auto load_tiles = [&](int k0) {
-    if (full) {
-#pragma unroll
-      for (int r = 0; r < T::kALoads; ++r) {
-        const int q = tid + r * T::kThreads;
-        int m, k;
-        tile_elem<kDL, BK, BM, OPA == 0>(q, m, k);
-        const int gm = m0 + m, gk = k0 + k;
-        ra[r] = (OPA == 0) ? A[(long long)gm * lda + gk] : A[(long long)gk * lda + gm];
-      }
-#pragma unroll
-      for (int r = 0; r < T::kBLoads; ++r) {
-        const int q = tid + r * T::kThreads;
-        int n, k;
-        tile_elem<kDL, BK, BN, OPB == 1>(q, n, k);
-        const int gn = n0 + n, gk = k0 + k;
-        rb[r] = (OPB == 0) ? B[(long long)gk * ldb + gn] : B[(long long)gn * ldb + gk];
-      }
-      return;
-    }
 #pragma unroll
     for (int r = 0; r < T::kALoads; ++r) {
       const int q = tid + r * T::kThreads;
       int m, k;
-      tile_elem<kDL, BK, BM, OPA == 0>(q, m, k);
+      slot_elem<BK, BM, OPA == 0>(q, m, k);
       const int gm = m0 + m, gk = k0 + k;
       double2 v = make_double2(0.0, 0.0);
       if (gm < M && gk < K)
@@ -257,7 +198,7 @@ void zgemm_kernel(FlatLaunch L) {
     for (int r = 0; r < T::kBLoads; ++r) {
       const int q = tid + r * T::kThreads;
       int n, k;
-      tile_elem<kDL, BK, BN, OPB == 1>(q, n, k);
+      slot_elem<BK, BN, OPB == 1>(q, n, k);
       const int gn = n0 + n, gk = k0 + k;
       double2 v = make_double2(0.0, 0.0);
       if (gn < N && gk < K)
@@ -267,31 +208,9 @@ void zgemm_kernel(FlatLaunch L) {
   };
   auto store_tiles = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < T::kALoads; ++r) {
-      const int q = tid + r * T::kThreads;
-      int m, k;
-      tile_elem<kDL, BK, BM, OPA == 0>(q, m, k);
-      if constexpr (kDL) {
-        (buf ? As1 : As0)[q] = ra[r];
-      } else {
-        Lt v = P::cvt(ra[r]);
-        if (OPA == 1) v.y = -v.y;
-        (buf ? As1 : As0)[ia(k, m)] = v;
-      }
-    }
+    for (int r = 0; r < T::kALoads; ++r) (buf ? As1 : As0)[tid + r * T::kThreads] = ra[r];
 #pragma unroll
-    for (int r = 0; r < T::kBLoads; ++r) {
-      const int q = tid + r * T::kThreads;
-      int n, k;
-      tile_elem<kDL, BK, BN, OPB == 1>(q, n, k);
-      if constexpr (kDL) {
-        (buf ? Bs1 : Bs0)[q] = rb[r];
-      } else {
-        Lt v = P::cvt(rb[r]);
-        if (OPB == 1) v.y = -v.y;
-        (buf ? Bs1 : Bs0)[ib(k, n)] = v;
-      }
-    }
+    for (int r = 0; r < T::kBLoads; ++r) (buf ? Bs1 : Bs0)[tid + r * T::kThreads] = rb[r];
   };
 
   constexpr int kS = CM == 3 ? 1 : 0;          // third accumulator set (3M)
@@ -325,10 +244,9 @@ void zgemm_kernel(FlatLaunch L) {
                                                    : make_double2(0.0, 0.0);
         }
   }
-  // whole FP64 tiles: every lane of a wave instruction reads one complex
-  // from HBM into the next 16-byte slot after the wave's base in LDS
-  auto dma_tiles = [&](int k0, St* as, St* bs) __attribute__((always_inline)) {
-    if constexpr (kDL) {
+  // whole tiles: every lane of a wave instruction reads one complex from
+  // HBM into the next 16-byte slot after the wave's base in LDS
+  auto dma_tiles = [&](int k0, double2* as, double2* bs) __attribute__((always_inline)) {
 #pragma unroll
     for (int r = 0; r < T::kALoads; ++r) {
       const int q = tid + r * T::kThreads;
@@ -347,25 +265,22 @@ void zgemm_kernel(FlatLaunch L) {
                                       : B + ((long long)(n0 + n) * ldb + k0 + k);
       lds_dma16(src, bs + r * T::kThreads + wave * 64);
     }
-    }
   };
   const int lrow = lane & 15, lk = lane >> 4;
-  auto compute = [&](const St* as, const St* bs) __attribute__((always_inline)) {
+  auto compute = [&](const double2* as, const double2* bs) __attribute__((always_inline)) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kidx = kk * 4 + lk;
       Lt a[T::kTM], b[T::kTN];
 #pragma unroll
       for (int i = 0; i < T::kTM; ++i) {
-        if constexpr (kDL) a[i] = P::cvt(as[ia(kidx, wm * T::kWM + i * 16 + lrow)]);
-        else a[i] = as[ia(kidx, wm * T::kWM + i * 16 + lrow)];
-        if (kDL && OPA == 1) a[i].y = -a[i].y;
+        a[i] = P::cvt(as[ia(kidx, wm * T::kWM + i * 16 + lrow)]);
+        if (OPA == 1) a[i].y = -a[i].y;
       }
 #pragma unroll
       for (int j = 0; j < T::kTN; ++j) {
-        if constexpr (kDL) b[j] = P::cvt(bs[ib(kidx, wn * T::kWN + j * 16 + lrow)]);
-        else b[j] = bs[ib(kidx, wn * T::kWN + j * 16 + lrow)];
-        if (kDL && OPB == 1) b[j].y = -b[j].y;
+        b[j] = P::cvt(bs[ib(kidx, wn * T::kWN + j * 16 + lrow)]);
+        if (OPB == 1) b[j].y = -b[j].y;
       }
       if (CM == 3) {
         R as[T::kTM], bs[T::kTN];
@@ -399,7 +314,7 @@ void zgemm_kernel(FlatLaunch L) {
   const int nk = (K + BK - 1) / BK;
   // separate loops: in the direct one nothing waits for the next tile's
   // loads before the products of this one
-  if (kDL && full) {
+  if (full) {
     // two k tiles per trip, so that every access names its buffer statically
     dma_tiles(0, As0, Bs0);
     lds_dma_wait();
