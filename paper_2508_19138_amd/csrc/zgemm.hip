@@ -82,9 +82,6 @@ __device__ __forceinline__ int xcd_remap(int w, int G) {
   return w;
 }
 
-// TAG only separates kernel symbols (1 = rank-kPanel and rank-kSuper
-// updates of the inverse, 2 = its rank-kMega updates) so that profilers
-// report the uses apart.
 // Direct layout of an operand tile (the slot of each element in LDS).
 // A k-major tile (BK rows k of BW consecutive elements) is stored as read.
 // A row-major tile (BW rows w of BK consecutive k) permutes the k slots of
@@ -109,6 +106,7 @@ __device__ __forceinline__ void slot_elem(int s, int& w, int& k) {
     w = s % BW;
   }
 }
+
 // One complex from HBM into LDS without registers (global_load_lds_dwordx4):
 // the lane's 16 bytes land at lds_wave + 16 * (lane index), lds_wave being
 // the same for the whole wave.  Completion is counted by vmcnt.
@@ -131,6 +129,9 @@ __device__ __forceinline__ void lds_dma_wait() { asm volatile("s_waitcnt vmcnt(0
 // size (the stability analysis of the three-multiplication method).  Every
 // tile configuration uses the same form and the same k order, so the tile
 // still changes no bit of a result.
+// TAG only separates kernel symbols (1 = rank-kPanel and rank-kSuper
+// updates of the inverse, 2 = its rank-kMega updates) so that profilers
+// report the uses apart.
 template <class P, class T, int OPA, int OPB, int TAG, int CM>
 __global__ __launch_bounds__(T::kThreads)
 void zgemm_kernel(FlatLaunch L) {
